@@ -1,0 +1,217 @@
+"""Seeded synthetic option-pricing workloads (inputs only).
+
+This module produces the *inputs* of the all-at-once Crank-Nicolson solve:
+the spatial operator A (three diagonals, the paper's A ~ L of eq. (1.1)),
+the initial condition u^0 and the boundary forcing f^{k+1/2}.  It contains
+none of the method's arithmetic (no all-at-once assembly, no right-hand side
+b, no preconditioner, no Krylov step): both the CPU oracle and the GPU path
+take what it returns as their input.
+
+Problem family: 1D Black-Scholes in log-price x = ln S and time-to-maturity t,
+    u_t = a(x) u_xx + b(x) u_x - r u,   a = sigma(x)^2/2,  b = r - sigma(x)^2/2,
+an instance of the drift-diffusion-reaction operators of eq. (1.2) (first
+case), discretised by second-order central differences on the interior nodes
+x_i = x_min + i h, i = 1..N_x, h = (x_max - x_min)/(N_x + 1).  The European
+put payoff max(K - e^x, 0) is the initial condition; Dirichlet data are the
+discounted put asymptotics g_L(t) = K e^{-rt} - e^{x_min} (an exact solution
+of the PDE) and g_R(t) = 0.  The source term of eq. (2.1) is the boundary
+contribution evaluated at the midpoint t_{k+1/2} (Sec. 2.1): only its first
+entry is non-zero, f_1 = A_{1,0} g_L(t_{k+1/2}).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+X_MIN = -3.0
+X_MAX = 3.0
+
+
+@dataclass
+class Instance:
+    """One pricing instance: operator, data and solver settings."""
+    nx: int
+    nt: int
+    T: float
+    r: float
+    K: float
+    alpha: float
+    sigma: np.ndarray            # sigma(x_i) at the interior nodes, length nx
+    a_lo: np.ndarray             # A_{i,i-1} (entry 0 unused), length nx
+    a_di: np.ndarray             # A_{i,i}
+    a_up: np.ndarray             # A_{i,i+1} (entry nx-1 unused)
+    u0: np.ndarray               # initial condition, length nx
+    f: np.ndarray                # f^{k+1/2}, shape (nt, nx)
+    x: np.ndarray                # interior nodes
+    h: float
+    m: int = 20                  # GMRES restart length
+    rtol: float = 1e-8
+    pc_prec: str = "fp64"        # "fp64" or "fp32"
+    name: str = ""
+    params: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.nt
+
+
+def grid(nx: int, x_min: float = X_MIN, x_max: float = X_MAX):
+    h = (x_max - x_min) / (nx + 1)
+    x = x_min + h * np.arange(1, nx + 1, dtype=np.float64)
+    return x, h
+
+
+def bs_operator(sigma: np.ndarray, r: float, h: float):
+    """Central-difference Black-Scholes operator rows (lower, diagonal, upper)."""
+    a = 0.5 * sigma ** 2
+    b = r - 0.5 * sigma ** 2
+    peclet = np.abs(b) * h / a
+    if np.any(peclet >= 2.0):
+        raise ValueError(f"cell Peclet number {peclet.max():.3f} >= 2")
+    lo = a / h ** 2 - b / (2 * h)
+    di = -2.0 * a / h ** 2 - r
+    up = a / h ** 2 + b / (2 * h)
+    lo = lo.copy()
+    up = up.copy()
+    lo[0] = 0.0       # couples to the left boundary node (moved into f)
+    up[-1] = 0.0      # couples to the right boundary node (g_R = 0)
+    return lo, di, up
+
+
+def left_boundary(t, K: float, r: float, x_min: float = X_MIN):
+    return K * np.exp(-r * np.asarray(t, dtype=np.float64)) - np.exp(x_min)
+
+
+def make_instance(nx: int, nt: int, T: float, r: float, K: float,
+                  sigma_fn: Callable[[np.ndarray], np.ndarray], alpha: float,
+                  m: int = 20, rtol: float = 1e-8, pc_prec: str = "fp64",
+                  name: str = "", params: Optional[dict] = None) -> Instance:
+    x, h = grid(nx)
+    sigma = np.asarray(sigma_fn(x), dtype=np.float64)
+    if sigma.min() < 0.02:
+        raise ValueError("sigma below 0.02")
+    a = 0.5 * sigma ** 2
+    b = r - 0.5 * sigma ** 2
+    lo, di, up = bs_operator(sigma, r, h)
+    a10 = a[0] / h ** 2 - b[0] / (2 * h)        # A_{1,0}: coupling to x_0
+    u0 = np.maximum(K - np.exp(x), 0.0)
+    tau = T / nt
+    th = (np.arange(nt, dtype=np.float64) + 0.5) * tau
+    f = np.zeros((nt, nx), dtype=np.float64)
+    f[:, 0] = a10 * left_boundary(th, K, r)
+    return Instance(nx=nx, nt=nt, T=T, r=r, K=K, alpha=alpha, sigma=sigma,
+                    a_lo=lo, a_di=di, a_up=up, u0=u0, f=f, x=x, h=h, m=m,
+                    rtol=rtol, pc_prec=pc_prec, name=name, params=params or {})
+
+
+# ---------------------------------------------------------------------------
+# volatility families
+# ---------------------------------------------------------------------------
+
+def local_vol_amplitudes(rng: np.random.Generator):
+    """sigma(x) = 0.2 + a1 tanh x + a2 sin 3x with a1, a2 drawn within +-20%."""
+    a1 = 0.1 * rng.uniform(0.8, 1.2)
+    a2 = 0.05 * rng.uniform(0.8, 1.2)
+    return a1, a2
+
+
+def local_vol(a1: float, a2: float):
+    return lambda x: 0.2 + a1 * np.tanh(x) + a2 * np.sin(3.0 * x)
+
+
+# ---------------------------------------------------------------------------
+# the five workloads
+# ---------------------------------------------------------------------------
+
+def config1(nx: int = 127, nt: int = 64) -> Instance:
+    """Constant volatility put: sigma 0.3, r 0.05, K 1, T 1, alpha 0.01."""
+    return make_instance(nx, nt, T=1.0, r=0.05, K=1.0,
+                         sigma_fn=lambda x: np.full_like(x, 0.3), alpha=0.01,
+                         m=20, rtol=1e-12, pc_prec="fp64",
+                         name=f"bs-const-{nx}x{nt}")
+
+
+def config2(alpha: float = 0.01, pc_prec: str = "fp64", nx: int = 4095,
+            nt: int = 1024, seed: int = 2) -> Instance:
+    """Local volatility put, r 0.03, K 1, T 2, flexible GMRES(30), rtol 1e-8."""
+    rng = np.random.default_rng(seed)
+    a1, a2 = local_vol_amplitudes(rng)
+    return make_instance(nx, nt, T=2.0, r=0.03, K=1.0,
+                         sigma_fn=local_vol(a1, a2), alpha=alpha, m=30,
+                         rtol=1e-8, pc_prec=pc_prec,
+                         name=f"bs-localvol-{nx}x{nt}",
+                         params={"a1": a1, "a2": a2, "seed": seed})
+
+
+BATCH_NX = (255, 511, 1023, 2047)
+BATCH_NT = (64, 128, 256, 512)
+
+
+def config3(count: int = 512, seed: int = 3, nx_choices=BATCH_NX,
+            nt_choices=BATCH_NT) -> List[Instance]:
+    """Uneven batch of constant-volatility puts (FP32 preconditioner)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        sigma = rng.uniform(0.1, 0.5)
+        r = rng.uniform(0.0, 0.08)
+        K = rng.uniform(0.8, 1.2)
+        T = rng.uniform(0.25, 2.0)
+        nx = int(rng.choice(nx_choices))
+        nt = int(rng.choice(nt_choices))
+        out.append(make_instance(nx, nt, T=T, r=r, K=K,
+                                 sigma_fn=(lambda s: (lambda x: np.full_like(x, s)))(sigma),
+                                 alpha=0.01, m=20, rtol=1e-8, pc_prec="fp32",
+                                 name=f"batch-{q}",
+                                 params={"sigma": sigma}))
+    return out
+
+
+WS_NX = 2047
+WS_NT = 512
+WS_FEATURE_POINTS = 64
+
+
+def config4_params(count: int, seed: int):
+    """Per-instance (a1, a2, r, T, K) for the warm-start family."""
+    rng = np.random.default_rng(seed)
+    p = np.empty((count, 5), dtype=np.float64)
+    for q in range(count):
+        a1, a2 = local_vol_amplitudes(rng)
+        p[q] = (a1, a2, rng.uniform(0.0, 0.08), rng.uniform(0.25, 2.0),
+                rng.uniform(0.8, 1.2))
+    return p
+
+
+def config4_instance(p, nx: int = WS_NX, nt: int = WS_NT) -> Instance:
+    a1, a2, r, T, K = (float(v) for v in p)
+    return make_instance(nx, nt, T=T, r=r, K=K, sigma_fn=local_vol(a1, a2),
+                         alpha=0.01, m=20, rtol=1e-8, pc_prec="fp32",
+                         name="ws", params={"a1": a1, "a2": a2})
+
+
+def config4_features(params: np.ndarray) -> np.ndarray:
+    """sigma at 64 equispaced points of [-3, 3] followed by (r, T, K)."""
+    xs = np.linspace(X_MIN, X_MAX, WS_FEATURE_POINTS)
+    out = np.empty((params.shape[0], WS_FEATURE_POINTS + 3), dtype=np.float64)
+    for q, (a1, a2, r, T, K) in enumerate(params):
+        out[q, :WS_FEATURE_POINTS] = local_vol(a1, a2)(xs)
+        out[q, WS_FEATURE_POINTS:] = (r, T, K)
+    return out
+
+
+def config5(nx: int = 65535, nt: int = 4096, seed: int = 5) -> Instance:
+    """Production-size local volatility put, FP32 preconditioner, GMRES(20)."""
+    rng = np.random.default_rng(seed)
+    a1, a2 = local_vol_amplitudes(rng)
+    return make_instance(nx, nt, T=2.0, r=0.03, K=1.0,
+                         sigma_fn=local_vol(a1, a2), alpha=0.01, m=20,
+                         rtol=1e-8, pc_prec="fp32",
+                         name=f"bs-localvol-{nx}x{nt}",
+                         params={"a1": a1, "a2": a2, "seed": seed})
+
+
+def random_vector(n: int, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).standard_normal(n)
