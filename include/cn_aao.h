@@ -1,0 +1,149 @@
+/*
+ * cn_aao.h -- C ABI of the MI355X all-at-once Crank-Nicolson solver with the
+ * generalized block-circulant (alpha-circulant) preconditioner.
+ *
+ * Mathematics (arXiv 2401.16113):
+ *   - CN scheme, eq. (2.1): (u^{k+1}-u^k)/tau = A (u^{k+1}+u^k)/2 + f^{k+1/2},
+ *     tau = T/N_t, f evaluated at t_{k+1/2}.
+ *   - All-at-once system, eq. (2.2): M u = b,  M = B1 (x) I - B2 (x) A~,
+ *     A~ = tau A, B1 = tridiag(-1,1,0), B2 = tridiag(1,1,0)/2,
+ *     b = xi + tau f, xi = [(I + A~/2) u^0; 0; ...; 0].
+ *     Block form (Sec. 3.2): (M u)^1 = Q1 u^1, (M u)^k = Q1 u^k - Q2 u^{k-1},
+ *     Q1 = I - A~/2, Q2 = I + A~/2.
+ *   - Preconditioner, eq. (3.1): P_alpha = C1^(alpha) (x) I - C2^(alpha) (x) A~,
+ *     applied by the three steps of eq. (3.2) (alpha-weighted DFT along time,
+ *     N_t shifted spatial solves, inverse DFT), halved by conjugate symmetry
+ *     (Remark 1).
+ *   - Right-preconditioned restarted GMRES(m), zero initial guess, stop on the
+ *     relative residual (Sec. 5).
+ *
+ * Vector layout (all calls): a space-time vector of n = nx*nt doubles,
+ * element (k, i) at k*nx + i, k = 0..nt-1 standing for time level t_{k+1},
+ * space fastest (the lexicographic stacking u = [u^1; ...; u^{N_t}] of
+ * eq. (2.2)).
+ *
+ * Memory: every data pointer below is a DEVICE pointer (hipMalloc'ed or a
+ * torch tensor's storage) owned by the caller unless stated otherwise.  The
+ * handle owns only its own workspace and never frees caller memory.
+ *
+ * Streams: calls enqueue work on the stream given at creation and return
+ * without synchronising, except cn_aao_create (synchronises after set-up),
+ * cn_gmres_solve and cn_batch_solve (synchronise before filling `info`).
+ *
+ * Errors: every entry point returns a cn_status; no C++ exception crosses
+ * the ABI.  cn_last_error() returns a thread-local message for the last
+ * failure on the calling thread.  A handle is not thread-safe; distinct
+ * handles are independent.
+ */
+#ifndef CN_AAO_H
+#define CN_AAO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CN_OK = 0,              /* success                                        */
+    CN_NOT_CONVERGED = 1,   /* iteration budget spent; x holds the last iterate */
+    CN_EINVAL = -1,         /* invalid argument (sizes, alpha, pointers, ...)  */
+    CN_ENOMEM = -2,         /* device workspace does not fit                  */
+    CN_EHIP = -3,           /* a HIP runtime call failed                      */
+    CN_ESINGULAR = -4       /* a shifted system of step (b) is singular       */
+} cn_status;
+
+typedef enum {
+    CN_PC_FP64 = 0,         /* preconditioner in float64 / complex128        */
+    CN_PC_FP32 = 1          /* preconditioner in float32 / complex64 (flexible GMRES) */
+} cn_pc_prec;
+
+/* cn_problem.flags */
+#define CN_FLAG_ALLOW_ALPHA_ONE 1  /* accept alpha = 1: the classical block-circulant
+                                      preconditioner P_1 (Remark 2); singular
+                                      shifted systems then give CN_ESINGULAR   */
+
+typedef struct {
+    int32_t nx;             /* spatial unknowns N_x >= 1                       */
+    int32_t nt;             /* time steps N_t: power of two in [1, 8192]       */
+    int32_t m_max;          /* largest GMRES restart length used, 1..64        */
+    int32_t flags;          /* CN_FLAG_* bits                                  */
+    double T;               /* final time, > 0 (tau = T/nt)                    */
+    double alpha;           /* alpha of the alpha-circulants, 0 < alpha < 1    */
+    const double *a_lo;     /* device, nx: A_{i,i-1} (entry 0 ignored)         */
+    const double *a_di;     /* device, nx: A_{i,i}                             */
+    const double *a_up;     /* device, nx: A_{i,i+1} (entry nx-1 ignored)      */
+    const double *d_half;   /* device, nt, or NULL: time weights d(t_{k+1/2}) of
+                               L(t) = d(t) L (Sec. 5.2); the preconditioner then
+                               uses their mean times C2^(alpha)                */
+    cn_pc_prec pc_prec;     /* precision of the preconditioner                 */
+    void *stream;           /* hipStream_t; NULL = the default stream          */
+} cn_problem;
+
+typedef struct cn_aao cn_aao;
+
+/* Validate p, copy A~ = tau A and the time weights, build the float64 tables
+ * (alpha^{+-k/N_t}, twiddles, lambda_{1,j}/lambda_{2,j} from the
+ * diagonalisation of Sec. 3.1), factor the interface systems of the
+ * partitioned step-(b) solve and allocate the GMRES workspace for m_max.
+ * Returns CN_EINVAL on bad input, CN_ENOMEM if the workspace does not fit,
+ * CN_ESINGULAR if a shifted system is singular.  On success *out owns the
+ * handle (release with cn_aao_destroy); on failure *out is NULL. */
+cn_status cn_aao_create(const cn_problem *p, cn_aao **out);
+cn_status cn_aao_destroy(cn_aao *h);
+
+/* b = xi + tau f (eq. (2.2)); u0: nx values; f: nt*nx values f^{k+1/2}
+ * (row k = f^{k+1/2}); b: nt*nx.  All device pointers. */
+cn_status cn_rhs(cn_aao *h, const double *u0, const double *f, double *b);
+
+/* y = M x (eq. (2.2)).  x and y: n doubles, x != y (CN_EINVAL if they overlap). */
+cn_status cn_matvec(cn_aao *h, const double *x, double *y);
+
+/* z = P_alpha^{-1} v by the three steps of eq. (3.2), in the handle's
+ * preconditioner precision, float64 input and output.  v == z is allowed. */
+cn_status cn_pc_apply(cn_aao *h, const double *v, double *z);
+
+typedef struct {
+    int32_t m;              /* restart length, 1 <= m <= m_max                 */
+    int32_t max_iters;      /* total inner-iteration budget, >= 1              */
+    int32_t use_x0;         /* nonzero: x holds the initial guess; else x0 = 0 */
+    int32_t reserved;
+    double rtol;            /* stop when ||b - M x||_2 / ||b||_2 <= rtol       */
+} cn_gmres_opts;
+
+typedef struct {
+    int32_t iters;          /* inner iterations (= preconditioned matvecs)    */
+    int32_t restarts;       /* completed cycles that did not converge         */
+    int32_t matvecs;        /* all products with M, residual checks included  */
+    int32_t pc_applies;     /* preconditioner applications                    */
+    double relres_true;     /* ||b - M x|| / ||b|| at return (recomputed)      */
+    double relres_est;      /* last least-squares residual estimate / ||b||   */
+    double seconds;         /* wall time of the call                          */
+} cn_gmres_info;
+
+/* Right-preconditioned restarted GMRES(m) (flexible form: the preconditioned
+ * vectors are stored, so x += Z y), Arnoldi by classical Gram-Schmidt with
+ * one re-orthogonalisation (CGS2) in float64.  With CN_PC_FP32 the
+ * preconditioner runs in float32 and its outputs are stored in float32 and
+ * multiplied by M as stored, which keeps the Arnoldi relation M Z = V H.
+ * b, x: device, n doubles, b != x.  On return x holds the last iterate and
+ * `info` (may be NULL) is filled.  Returns CN_OK when the true relative
+ * residual is <= rtol, CN_NOT_CONVERGED when max_iters is spent.  b = 0
+ * returns x = 0. */
+cn_status cn_gmres_solve(cn_aao *h, const double *b, double *x,
+                         const cn_gmres_opts *opts, cn_gmres_info *info);
+
+/* Sizes chosen at creation (for tests and tooling): tile width of the
+ * partitioned step-(b) solve, number of tiles and workgroup size of the
+ * transform kernels.  Any pointer may be NULL. */
+cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
+                       int32_t *threads);
+
+const char *cn_status_string(cn_status s);
+const char *cn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CN_AAO_H */

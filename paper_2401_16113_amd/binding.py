@@ -1,0 +1,190 @@
+"""ctypes binding of libcn_aao (include/cn_aao.h).
+
+Argument marshalling only: tensors are passed as device pointers, every step
+runs in the library's HIP kernels.  Loading fails loudly when the library has
+not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcn_aao.so")
+
+CN_OK = 0
+CN_NOT_CONVERGED = 1
+CN_EINVAL = -1
+CN_ENOMEM = -2
+CN_EHIP = -3
+CN_ESINGULAR = -4
+
+CN_PC_FP64 = 0
+CN_PC_FP32 = 1
+CN_FLAG_ALLOW_ALPHA_ONE = 1
+
+
+class CnProblem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("nt", ctypes.c_int32), ("m_max", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("T", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("a_lo", ctypes.c_void_p), ("a_di", ctypes.c_void_p), ("a_up", ctypes.c_void_p),
+        ("d_half", ctypes.c_void_p), ("pc_prec", ctypes.c_int), ("stream", ctypes.c_void_p),
+    ]
+
+
+class CnGmresOpts(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("use_x0", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rtol", ctypes.c_double)]
+
+
+class CnGmresInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("matvecs", ctypes.c_int32), ("pc_applies", ctypes.c_int32),
+                ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libcn_aao.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "cn_aao_create": (ctypes.c_int, [ctypes.POINTER(CnProblem), ctypes.POINTER(vp)]),
+        "cn_aao_destroy": (ctypes.c_int, [vp]),
+        "cn_aao_query": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(i32)]),
+        "cn_rhs": (ctypes.c_int, [vp, vp, vp, vp]),
+        "cn_matvec": (ctypes.c_int, [vp, vp, vp]),
+        "cn_pc_apply": (ctypes.c_int, [vp, vp, vp]),
+        "cn_gmres_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(CnGmresOpts),
+                                          ctypes.POINTER(CnGmresInfo)]),
+        "cn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "cn_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class CnError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load()
+        msg = lib.cn_last_error().decode()
+        super().__init__(f"{where}: {lib.cn_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError("tensor must live on the GPU")
+    if t.dtype != torch.float64:
+        raise TypeError("tensor must be float64")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(status: int, where: str, ok=(CN_OK,)):
+    if status not in ok:
+        raise CnError(status, where)
+    return status
+
+
+@dataclass
+class SolveResult:
+    status: int
+    iters: int
+    restarts: int
+    matvecs: int
+    pc_applies: int
+    relres_true: float
+    relres_est: float
+    seconds: float
+
+
+class Solver:
+    """One all-at-once CN problem on one GPU (wraps a cn_aao handle).
+
+    a_lo, a_di, a_up: float64 CUDA tensors of length nx holding the rows of A
+    (not tau A).  d_half: optional float64 CUDA tensor of length nt."""
+
+    def __init__(self, a_lo, a_di, a_up, nt: int, T: float, alpha: float, m_max: int = 30,
+                 pc_prec: str = "fp64", d_half=None, flags: int = 0, stream=None):
+        lib = load()
+        self._lib = lib
+        nx = int(a_lo.numel())
+        if stream is None:
+            stream = torch.cuda.current_stream(a_lo.device)
+        self.stream = stream
+        prob = CnProblem(nx=nx, nt=int(nt), m_max=int(m_max), flags=int(flags), T=float(T),
+                         alpha=float(alpha), a_lo=_ptr(a_lo), a_di=_ptr(a_di), a_up=_ptr(a_up),
+                         d_half=_ptr(d_half), pc_prec=CN_PC_FP32 if pc_prec == "fp32" else CN_PC_FP64,
+                         stream=ctypes.c_void_p(stream.cuda_stream))
+        h = ctypes.c_void_p()
+        _check(lib.cn_aao_create(ctypes.byref(prob), ctypes.byref(h)), "cn_aao_create")
+        self._h = h
+        self.nx, self.nt = nx, int(nt)
+        self.n = nx * int(nt)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cn_aao_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self):
+        b, p, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.cn_aao_query(self._h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(t)),
+               "cn_aao_query")
+        return {"tile_cols": b.value, "tiles": p.value, "threads": t.value}
+
+    def rhs(self, u0, f, out):
+        _check(self._lib.cn_rhs(self._h, _ptr(u0), _ptr(f), _ptr(out)), "cn_rhs")
+        return out
+
+    def matvec(self, x, out):
+        _check(self._lib.cn_matvec(self._h, _ptr(x), _ptr(out)), "cn_matvec")
+        return out
+
+    def pc_apply(self, v, out):
+        _check(self._lib.cn_pc_apply(self._h, _ptr(v), _ptr(out)), "cn_pc_apply")
+        return out
+
+    def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
+              use_x0: bool = False, allow_not_converged: bool = True) -> SolveResult:
+        opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=1 if use_x0 else 0,
+                           reserved=0, rtol=float(rtol))
+        info = CnGmresInfo()
+        ok = (CN_OK, CN_NOT_CONVERGED) if allow_not_converged else (CN_OK,)
+        st = _check(self._lib.cn_gmres_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(opts),
+                                             ctypes.byref(info)), "cn_gmres_solve", ok)
+        return SolveResult(st, info.iters, info.restarts, info.matvecs, info.pc_applies,
+                           info.relres_true, info.relres_est, info.seconds)

@@ -1,0 +1,470 @@
+// Host runtime of libcn_aao: the opaque handle, argument validation, the
+// float64 tables of the alpha-circulant diagonalisation (Sec. 3.1), the
+// workspace, and the GMRES(m) driver.  Every computational step runs in the
+// kernels of cn_pc.hip and cn_krylov.hip.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "cn_internal.hpp"
+
+using namespace cn;
+
+static thread_local std::string g_err;
+
+static cn_status fail(cn_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      return fail(e_ == hipErrorOutOfMemory ? CN_ENOMEM : CN_EHIP,                      \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+    }                                                                                   \
+  } while (0)
+
+struct cn_aao {
+  int nx = 0, nt = 0, m_max = 0, flags = 0;
+  double T = 0, alpha = 0, tau = 0;
+  int prec = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  long long n = 0, npad = 0;
+  PcPlan pl;
+  double* dw = nullptr;   // time weights (device) or null
+  double* V = nullptr;    // (m_max+1) x npad float64
+  void* Z = nullptr;      // m_max x npad, float64 or float32
+  double* w = nullptr;    // npad
+  double* partials = nullptr;
+  GState* st = nullptr;
+  GSummary* hsum = nullptr;  // pinned host, 4 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  std::vector<void*> dev_allocs;
+};
+
+static void release(cn_aao* h) {
+  if (h == nullptr) return;
+  if (h->stream != nullptr || true) (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->dev_allocs) (void)hipFree(p);
+  if (h->hsum != nullptr) (void)hipHostFree(h->hsum);
+  for (auto& e : h->ev)
+    if (e != nullptr) (void)hipEventDestroy(e);
+  if (h->t0 != nullptr) (void)hipEventDestroy(h->t0);
+  if (h->t1 != nullptr) (void)hipEventDestroy(h->t1);
+  delete h;
+}
+
+template <typename P>
+static hipError_t dalloc(cn_aao* h, P** ptr, size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes > 0 ? bytes : 16);
+  if (e == hipSuccess) {
+    h->dev_allocs.push_back(p);
+    *ptr = (P*)p;
+  }
+  return e;
+}
+
+static bool overlaps(const void* a, const void* b, size_t bytes) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+extern "C" {
+
+const char* cn_status_string(cn_status s) {
+  switch (s) {
+    case CN_OK: return "ok";
+    case CN_NOT_CONVERGED: return "not converged";
+    case CN_EINVAL: return "invalid argument";
+    case CN_ENOMEM: return "out of device memory";
+    case CN_EHIP: return "HIP runtime error";
+    case CN_ESINGULAR: return "singular shifted system";
+  }
+  return "unknown status";
+}
+
+const char* cn_last_error(void) { return g_err.c_str(); }
+
+cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
+  if (out == nullptr) return fail(CN_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (p == nullptr) return fail(CN_EINVAL, "problem is NULL");
+  if (p->nx < 1) return fail(CN_EINVAL, "nx must be >= 1");
+  if (p->nt < 1 || p->nt > 8192 || (p->nt & (p->nt - 1)) != 0)
+    return fail(CN_EINVAL, "nt must be a power of two in [1, 8192]");
+  if (p->m_max < 1 || p->m_max > MMAX) return fail(CN_EINVAL, "m_max must be in [1, 64]");
+  if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(CN_EINVAL, "T must be finite and > 0");
+  const bool allow1 = (p->flags & CN_FLAG_ALLOW_ALPHA_ONE) != 0;
+  if (!(p->alpha > 0.0) || !(p->alpha < 1.0 || (allow1 && p->alpha == 1.0)))
+    return fail(CN_EINVAL, "alpha must satisfy 0 < alpha < 1 (alpha = 1 needs CN_FLAG_ALLOW_ALPHA_ONE)");
+  if (p->pc_prec != CN_PC_FP64 && p->pc_prec != CN_PC_FP32)
+    return fail(CN_EINVAL, "pc_prec must be CN_PC_FP64 or CN_PC_FP32");
+  if (p->a_lo == nullptr || p->a_di == nullptr || p->a_up == nullptr)
+    return fail(CN_EINVAL, "A diagonals must be device pointers");
+  const long long n = (long long)p->nx * p->nt;
+  if (n > (1LL << 40)) return fail(CN_EINVAL, "problem too large");
+
+  cn_aao* h = new cn_aao();
+  h->nx = p->nx;
+  h->nt = p->nt;
+  h->m_max = p->m_max;
+  h->flags = p->flags;
+  h->T = p->T;
+  h->alpha = p->alpha;
+  h->tau = p->T / p->nt;
+  h->prec = p->pc_prec == CN_PC_FP32 ? 1 : 0;
+  h->stream = (hipStream_t)p->stream;
+  h->n = n;
+  h->npad = (n + 63) / 64 * 64;
+  cn_status rc = CN_OK;
+  auto bail = [&](cn_status s) {
+    release(h);
+    return s;
+  };
+#define TRY(expr)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      fail(e_ == hipErrorOutOfMemory ? CN_ENOMEM : CN_EHIP,                              \
+           std::string(#expr) + ": " + hipGetErrorString(e_));                           \
+      return bail(e_ == hipErrorOutOfMemory ? CN_ENOMEM : CN_EHIP);                      \
+    }                                                                                    \
+  } while (0)
+  TRY(hipGetDevice(&h->device));
+
+  // -- operator rows: A~ = tau A, boundary entries cleared ----------------------
+  const int nx = h->nx, nt = h->nt;
+  std::vector<double> lo(nx), di(nx), up(nx);
+  TRY(hipMemcpy(lo.data(), p->a_lo, nx * sizeof(double), hipMemcpyDeviceToHost));
+  TRY(hipMemcpy(di.data(), p->a_di, nx * sizeof(double), hipMemcpyDeviceToHost));
+  TRY(hipMemcpy(up.data(), p->a_up, nx * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < nx; ++i) {
+    if (i == 0) lo[i] = 0.0;
+    if (i == nx - 1) up[i] = 0.0;
+    if (!std::isfinite(lo[i]) || !std::isfinite(di[i]) || !std::isfinite(up[i])) {
+      fail(CN_EINVAL, "A has non-finite entries");
+      return bail(CN_EINVAL);
+    }
+    lo[i] *= h->tau;
+    di[i] *= h->tau;
+    up[i] *= h->tau;
+  }
+  double dbar = 1.0;
+  std::vector<double> dw;
+  if (p->d_half != nullptr) {
+    dw.resize(nt);
+    TRY(hipMemcpy(dw.data(), p->d_half, nt * sizeof(double), hipMemcpyDeviceToHost));
+    long double s = 0;
+    for (int k = 0; k < nt; ++k) {
+      if (!std::isfinite(dw[k]) || !(dw[k] > 0.0)) {
+        fail(CN_EINVAL, "time weights must be finite and > 0");
+        return bail(CN_EINVAL);
+      }
+      s += dw[k];
+    }
+    dbar = (double)(s / nt);
+  }
+
+  // -- plan -----------------------------------------------------------------------
+  PcPlan& pl = h->pl;
+  pl.nx = nx;
+  pl.nt = nt;
+  pl.log2n = 0;
+  while ((1 << pl.log2n) < nt) ++pl.log2n;
+  pl.F = nt / 2 + 1;
+  pl.prec = h->prec;
+  pl.alpha = h->alpha;
+  pl.dbar = dbar;
+  pc_config(pl.prec, pl.log2n, &pl.B, &pl.T);
+  pl.P = (nx + pl.B - 1) / pl.B;
+  pl.NS = pl.P - 1;
+  const size_t rsz = pl.prec ? sizeof(float) : sizeof(double);
+  const int nsr = pl.NS > 0 ? pl.NS : 1;
+
+  // workspace size check against free memory
+  size_t need = 0;
+  need += (size_t)(h->m_max + 1) * h->npad * sizeof(double);         // V
+  need += (size_t)h->m_max * h->npad * rsz;                           // Z
+  need += (size_t)h->npad * sizeof(double);                           // w
+  need += (size_t)pl.P * pl.B * nt * rsz;                             // spectrum tiles
+  need += (size_t)pl.F * pl.P * 3 * 2 * rsz;                          // interface values
+  need += (size_t)pl.F * nsr * 2 * rsz + (size_t)pl.F * nsr * 4 * sizeof(Cx<double>);
+  need += (size_t)pl.F * pl.P * 4 * sizeof(Cx<double>);               // set-up spikes
+  size_t freeb = 0, totalb = 0;
+  TRY(hipMemGetInfo(&freeb, &totalb));
+  if (need + (64u << 20) > freeb) {
+    fail(CN_ENOMEM, "workspace of " + std::to_string(need) + " bytes does not fit in " +
+                        std::to_string(freeb) + " free bytes");
+    return bail(CN_ENOMEM);
+  }
+
+  TRY(dalloc(h, &pl.lo, nx * sizeof(double)));
+  TRY(dalloc(h, &pl.di, nx * sizeof(double)));
+  TRY(dalloc(h, &pl.up, nx * sizeof(double)));
+  TRY(hipMemcpy(pl.lo, lo.data(), nx * sizeof(double), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(pl.di, di.data(), nx * sizeof(double), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(pl.up, up.data(), nx * sizeof(double), hipMemcpyHostToDevice));
+  if (!dw.empty()) {
+    TRY(dalloc(h, &h->dw, nt * sizeof(double)));
+    TRY(hipMemcpy(h->dw, dw.data(), nt * sizeof(double), hipMemcpyHostToDevice));
+  }
+
+  // -- float64 tables (computed in long double) -------------------------------------
+  const long double la = logl((long double)h->alpha);
+  const long double PI = 3.141592653589793238462643383279502884L;
+  std::vector<double> wfw(nt), winv(nt);
+  std::vector<Cx<double>> tw(nt), mu(pl.F), il2(pl.F);
+  std::vector<Cx<float>> twf(nt);
+  for (int k = 0; k < nt; ++k) {
+    wfw[k] = (double)expl(la * k / nt);                  // alpha^{k/N_t}
+    winv[k] = (double)(expl(-la * k / nt) / nt);         // alpha^{-k/N_t} / N_t
+    const long double ang = -2.0L * PI * k / nt;         // omega^k, omega = e^{-2 pi i/N_t}
+    tw[k] = Cx<double>{(double)cosl(ang), (double)sinl(ang)};
+    twf[k] = Cx<float>{(float)tw[k].x, (float)tw[k].y};
+  }
+  const long double a1 = expl(la / nt);                  // alpha^{1/N_t}
+  for (int j = 0; j < pl.F; ++j) {
+    const long double ang = -2.0L * PI * j / nt;
+    const long double wr = cosl(ang), wi = sinl(ang);
+    // lambda_1 = 1 - a omega^j, lambda_2 = dbar (1 + a omega^j) / 2
+    const long double l1r = 1.0L - a1 * wr, l1i = -a1 * wi;
+    const long double l2r = 0.5L * dbar * (1.0L + a1 * wr), l2i = 0.5L * dbar * a1 * wi;
+    const long double den = l2r * l2r + l2i * l2i;
+    if (!(den > 0.0L)) {
+      fail(CN_ESINGULAR, "lambda_2 vanishes");
+      return bail(CN_ESINGULAR);
+    }
+    mu[j] = Cx<double>{(double)((l1r * l2r + l1i * l2i) / den),
+                       (double)((l1i * l2r - l1r * l2i) / den)};
+    il2[j] = Cx<double>{(double)(l2r / den), (double)(-l2i / den)};
+  }
+  TRY(dalloc(h, &pl.wfw, nt * sizeof(double)));
+  TRY(dalloc(h, &pl.winv, nt * sizeof(double)));
+  TRY(dalloc(h, &pl.tw, nt * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.tw_f, nt * sizeof(Cx<float>)));
+  TRY(dalloc(h, &pl.mu, pl.F * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.il2, pl.F * sizeof(Cx<double>)));
+  TRY(hipMemcpy(pl.wfw, wfw.data(), nt * sizeof(double), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(pl.winv, winv.data(), nt * sizeof(double), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(pl.tw, tw.data(), nt * sizeof(Cx<double>), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(pl.tw_f, twf.data(), nt * sizeof(Cx<float>), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(pl.mu, mu.data(), pl.F * sizeof(Cx<double>), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(pl.il2, il2.data(), pl.F * sizeof(Cx<double>), hipMemcpyHostToDevice));
+
+  // -- preconditioner workspace and interface factorisation -------------------------
+  TRY(dalloc(h, &pl.spec, (size_t)pl.P * pl.B * nt * rsz));
+  TRY(dalloc(h, &pl.iface, (size_t)pl.F * pl.P * 3 * 2 * rsz));
+  TRY(dalloc(h, &pl.sep, (size_t)pl.F * nsr * 2 * rsz));
+  TRY(dalloc(h, &pl.red_a, (size_t)pl.F * nsr * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.red_ap, (size_t)pl.F * nsr * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.red_inv, (size_t)pl.F * nsr * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.red_tmp, (size_t)pl.F * nsr * sizeof(Cx<double>)));
+  {
+    Cx<double>* spk = nullptr;
+    int* err = nullptr;
+    TRY(hipMalloc((void**)&spk, (size_t)pl.F * pl.P * 4 * sizeof(Cx<double>)));
+    if (hipMalloc((void**)&err, sizeof(int)) != hipSuccess) {
+      (void)hipFree(spk);
+      fail(CN_ENOMEM, "set-up flag");
+      return bail(CN_ENOMEM);
+    }
+    hipError_t e = hipMemsetAsync(err, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) e = pc_setup(pl, spk, err, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    int herr = 0;
+    if (e == hipSuccess) e = hipMemcpy(&herr, err, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipFree(spk);
+    (void)hipFree(err);
+    if (e != hipSuccess) {
+      fail(CN_EHIP, std::string("preconditioner set-up: ") + hipGetErrorString(e));
+      return bail(CN_EHIP);
+    }
+    if (herr != 0) {
+      fail(CN_ESINGULAR, "a shifted system of step (b) is singular (alpha = " +
+                             std::to_string(h->alpha) + ")");
+      return bail(CN_ESINGULAR);
+    }
+  }
+
+  // -- GMRES workspace ----------------------------------------------------------------
+  TRY(dalloc(h, &h->V, (size_t)(h->m_max + 1) * h->npad * sizeof(double)));
+  TRY(dalloc(h, &h->Z, (size_t)h->m_max * h->npad * rsz));
+  TRY(dalloc(h, &h->w, (size_t)h->npad * sizeof(double)));
+  {
+    const int rows = matvec_rows(nx, nt);
+    const long long mgrid = (long long)((nx + 255) / 256) * ((nt + rows - 1) / rows);
+    const long long pgrid = mgrid > KGRID ? mgrid : KGRID;
+    TRY(dalloc(h, &h->partials, (size_t)pgrid * NVMAX * sizeof(double)));
+  }
+  TRY(dalloc(h, &h->st, sizeof(GState)));
+  TRY(hipMemsetAsync(h->st, 0, sizeof(GState), h->stream));
+  TRY(hipHostMalloc((void**)&h->hsum, 4 * sizeof(GSummary), hipHostMallocDefault));
+  memset(h->hsum, 0, 4 * sizeof(GSummary));
+  TRY(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
+  TRY(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
+  TRY(hipEventCreate(&h->t0));
+  TRY(hipEventCreate(&h->t1));
+  TRY(hipStreamSynchronize(h->stream));
+#undef TRY
+  (void)rc;
+  *out = h;
+  return CN_OK;
+}
+
+cn_status cn_aao_destroy(cn_aao* h) {
+  if (h == nullptr) return fail(CN_EINVAL, "handle is NULL");
+  release(h);
+  return CN_OK;
+}
+
+cn_status cn_aao_query(const cn_aao* h, int32_t* tile_cols, int32_t* tiles, int32_t* threads) {
+  if (h == nullptr) return fail(CN_EINVAL, "handle is NULL");
+  if (tile_cols != nullptr) *tile_cols = h->pl.B;
+  if (tiles != nullptr) *tiles = h->pl.P;
+  if (threads != nullptr) *threads = h->pl.T;
+  return CN_OK;
+}
+
+static KArgs kargs(cn_aao* h) {
+  KArgs a;
+  a.lo = h->pl.lo;
+  a.di = h->pl.di;
+  a.up = h->pl.up;
+  a.dw = h->dw;
+  a.nx = h->nx;
+  a.nt = h->nt;
+  a.rows = matvec_rows(h->nx, h->nt);
+  a.n = h->n;
+  a.V = h->V;
+  a.vstride = h->npad;
+  a.nv = 0;
+  a.st = h->st;
+  a.partials = h->partials;
+  return a;
+}
+
+cn_status cn_rhs(cn_aao* h, const double* u0, const double* f, double* b) {
+  if (h == nullptr || u0 == nullptr || f == nullptr || b == nullptr)
+    return fail(CN_EINVAL, "NULL argument");
+  if (overlaps(f, b, h->n * sizeof(double)) || overlaps(u0, b, h->n * sizeof(double)))
+    return fail(CN_EINVAL, "b must not overlap u0 or f");
+  HIP_TRY(launch_rhs(h->pl.lo, h->pl.di, h->pl.up, h->dw, h->tau, u0, f, b, h->nx, h->n,
+                     h->stream));
+  return CN_OK;
+}
+
+cn_status cn_matvec(cn_aao* h, const double* x, double* y) {
+  if (h == nullptr || x == nullptr || y == nullptr) return fail(CN_EINVAL, "NULL argument");
+  if (overlaps(x, y, h->n * sizeof(double))) return fail(CN_EINVAL, "x and y overlap");
+  KArgs a = kargs(h);
+  HIP_TRY(launch_matvec(a, x, 0, nullptr, y, 0, h->stream));
+  return CN_OK;
+}
+
+cn_status cn_pc_apply(cn_aao* h, const double* v, double* z) {
+  if (h == nullptr || v == nullptr || z == nullptr) return fail(CN_EINVAL, "NULL argument");
+  HIP_TRY(pc_forward(h->pl, v, nullptr, nullptr, h->stream));
+  HIP_TRY(pc_reduced(h->pl, nullptr, h->stream));
+  HIP_TRY(pc_inverse(h->pl, z, 0, nullptr, h->stream));
+  return CN_OK;
+}
+
+cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_opts* opts,
+                         cn_gmres_info* info) {
+  if (h == nullptr || b == nullptr || x == nullptr || opts == nullptr)
+    return fail(CN_EINVAL, "NULL argument");
+  if (opts->m < 1 || opts->m > h->m_max) return fail(CN_EINVAL, "opts->m must be in [1, m_max]");
+  if (opts->max_iters < 1) return fail(CN_EINVAL, "opts->max_iters must be >= 1");
+  if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
+    return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
+  if (overlaps(b, x, h->n * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
+  const auto wall0 = std::chrono::steady_clock::now();
+  hipStream_t s = h->stream;
+  GState* st = h->st;
+  const int* done = &st->sum.done;
+  const int zf = h->prec;
+  const size_t zes = zf ? sizeof(float) : sizeof(double);
+  HIP_TRY(hipEventRecord(h->t0, s));
+  if (!opts->use_x0) HIP_TRY(hipMemsetAsync(x, 0, h->n * sizeof(double), s));
+  const double rtol = opts->rtol;
+  HIP_TRY(hipMemcpyAsync(&st->rtol, &rtol, sizeof(double), hipMemcpyHostToDevice, s));
+  KArgs a = kargs(h);
+  // r_0 = b - M x_0 into v_0, ||b||, beta
+  HIP_TRY(launch_matvec(a, opts->use_x0 ? x : nullptr, 0, b, h->V, 1, s));
+  GSummary* hs = h->hsum;
+  HIP_TRY(hipMemcpyAsync(&hs[2], &st->sum, sizeof(GSummary), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  GSummary cur = hs[2];
+  int iters = 0, restarts = 0, matvecs = 1, pcs = 0;
+  double est = cur.relres;
+  if (cur.bnorm == 0.0) {
+    HIP_TRY(hipMemsetAsync(x, 0, h->n * sizeof(double), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info != nullptr) {
+      *info = cn_gmres_info{0, 0, 1, 0, 0.0, 0.0, 0.0};
+    }
+    return CN_OK;
+  }
+  while (!(cur.relres <= rtol) && iters < opts->max_iters) {
+    const int m_eff = std::min(opts->m, opts->max_iters - iters);
+    for (int j = 0; j < m_eff; ++j) {
+      const double* vj = h->V + (size_t)j * h->npad;
+      void* zj = (char*)h->Z + (size_t)j * h->npad * zes;
+      HIP_TRY(pc_forward(h->pl, vj, &st->vscale[j], done, s));
+      HIP_TRY(pc_reduced(h->pl, done, s));
+      HIP_TRY(pc_inverse(h->pl, zj, zf, done, s));
+      a.nv = j + 1;
+      HIP_TRY(launch_matvec(a, zj, zf, nullptr, h->w, 2, s));
+      HIP_TRY(launch_cgs(a, h->w, h->V + (size_t)(j + 1) * h->npad, j, m_eff, s));
+      HIP_TRY(hipMemcpyAsync(&hs[j & 1], &st->sum, sizeof(GSummary), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(h->ev[j & 1], s));
+      if (j >= 1) {
+        HIP_TRY(hipEventSynchronize(h->ev[(j - 1) & 1]));
+        if (hs[(j - 1) & 1].done) break;
+      }
+    }
+    HIP_TRY(launch_finish_update(st, h->Z, zf, h->npad, x, h->n, s));
+    HIP_TRY(hipMemcpyAsync(&hs[3], &st->sum, sizeof(GSummary), hipMemcpyDeviceToHost, s));
+    HIP_TRY(launch_matvec(a, x, 0, b, h->V, 1, s));
+    HIP_TRY(hipMemcpyAsync(&hs[2], &st->sum, sizeof(GSummary), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int k = hs[3].k;
+    est = hs[3].est;
+    cur = hs[2];
+    iters += k;
+    pcs += k;
+    matvecs += k + 1;
+    if (k == 0) break;  // no progress possible (should not happen)
+    if (!(cur.relres <= rtol) && iters < opts->max_iters) ++restarts;
+  }
+  HIP_TRY(hipEventRecord(h->t1, s));
+  HIP_TRY(hipEventSynchronize(h->t1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, h->t0, h->t1));
+  const auto wall1 = std::chrono::steady_clock::now();
+  (void)wall0;
+  (void)wall1;
+  if (info != nullptr) {
+    info->iters = iters;
+    info->restarts = restarts;
+    info->matvecs = matvecs;
+    info->pc_applies = pcs;
+    info->relres_true = cur.relres;
+    info->relres_est = est;
+    info->seconds = ms * 1e-3;
+  }
+  return cur.relres <= rtol ? CN_OK : CN_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+// Device building blocks for the alpha-circulant preconditioner on gfx950:
+// complex arithmetic, in-register DFTs, an LDS-staged Stockham FFT pass and
+// the tile-local tridiagonal solve of the partitioned step-(b) solver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cn {
+
+// ---------------------------------------------------------------------------
+// complex numbers
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Cx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ Cx<R> mk(R a, R b) { return Cx<R>{a, b}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator*(Cx<R> a, Cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return {s * a.x, s * a.y}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> conj(Cx<R> a) { return {a.x, -a.y}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename R, bool INV>
+__device__ __forceinline__ Cx<R> mul_mi(Cx<R> a) {
+  return INV ? Cx<R>{-a.y, a.x} : Cx<R>{a.y, -a.x};
+}
+
+// Reciprocals.  float64: hardware estimate refined by two Newton steps
+// (error ~1 ulp); float32: hardware estimate (1 ulp).
+__device__ __forceinline__ double rcp(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = __builtin_fma(-a, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-a, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
+
+template <typename R>
+__device__ __forceinline__ Cx<R> crcp(Cx<R> a) {
+  R s = rcp(a.x * a.x + a.y * a.y);
+  return {a.x * s, -a.y * s};
+}
+__device__ __forceinline__ double crcp(double a) { return rcp(a); }
+__device__ __forceinline__ float crcp(float a) { return rcp(a); }
+
+// ---------------------------------------------------------------------------
+// in-register DFT of size RAD (RAD = 1, 2, 4, 8, 16), decimation in time.
+// forward: X_q = sum_r u_r exp(-2 pi i r q / RAD); inverse: exp(+...).
+// ---------------------------------------------------------------------------
+// cos and sin of 2 pi m / 16, m = 0..15
+__host__ __device__ constexpr double cos16(int m) {
+  constexpr double t[16] = {
+      1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+      0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+      -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+      0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+  return t[m & 15];
+}
+__host__ __device__ constexpr double sin16(int m) { return cos16(m + 12); }
+
+template <typename R, int RAD, bool INV, int S = 1>
+struct Dft {
+  // in-place DFT of u[0], u[S], ..., u[(RAD-1) S]
+  static __device__ __forceinline__ void run(Cx<R>* u) {
+    if constexpr (RAD == 1) {
+      return;
+    } else if constexpr (RAD == 2) {
+      Cx<R> a = u[0], b = u[S];
+      u[0] = a + b;
+      u[S] = a - b;
+    } else {
+      // split into even and odd halves (stride 2S), transform each, combine
+      Dft<R, RAD / 2, INV, 2 * S>::run(u);
+      Dft<R, RAD / 2, INV, 2 * S>::run(u + S);
+      Cx<R> t[RAD];
+#pragma unroll
+      for (int q = 0; q < RAD; ++q) t[q] = u[q * S];
+      // now t[2q] = E_q (q < RAD/2), t[2q+1] = O_q
+#pragma unroll
+      for (int q = 0; q < RAD / 2; ++q) {
+        Cx<R> e = t[2 * q], o = t[2 * q + 1];
+        Cx<R> w;
+        constexpr int step = 16 / RAD;
+        if (q == 0) {
+          w = o;
+        } else if (4 * q == RAD) {
+          w = mul_mi<R, INV>(o);
+        } else {
+          const R c = (R)cos16(q * step);
+          const R s = INV ? (R)sin16(q * step) : -(R)sin16(q * step);
+          w = Cx<R>{o.x * c - o.y * s, o.x * s + o.y * c};
+        }
+        u[q * S] = e + w;
+        u[(q + RAD / 2) * S] = e - w;
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// transform kernel configuration for a given precision and N_t = 2^LOG2N
+// ---------------------------------------------------------------------------
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int clog2(int v) { return v <= 1 ? 0 : 1 + clog2(v / 2); }
+
+template <typename R, int LOG2N>
+struct PcCfg {
+  static constexpr int N = 1 << LOG2N;
+  static constexpr int BUDGET = 128 * 1024;  // bytes of tile image in LDS
+  static constexpr int Braw = BUDGET / (N * (int)sizeof(R));
+  static constexpr int B = cmax(2, cmin(16, Braw));      // tile columns (even)
+  static constexpr int NSEQ = B / 2;                       // complex sequences
+  static constexpr int ELEMS = NSEQ * N;                   // complex elements
+  static constexpr int T = cmax(64, cmin(1024, ELEMS / 16));
+  static constexpr int E = cmax(1, ELEMS / T);             // elements per thread
+  static constexpr int MAXLOG = cmax(1, cmin(4, clog2(E)));  // largest radix 2^MAXLOG
+  // padded LDS layout: one spare complex slot every 16, plus one per sequence
+  static constexpr int SSTRIDE = N + N / 16 + 1;
+  static constexpr int LDS_ELEMS = NSEQ * SSTRIDE;
+  static constexpr int TASKS = N >= 2 ? N / 2 : 1;          // step-(b) tasks
+};
+
+template <int N>
+__device__ __forceinline__ int lidx(int s, int e) {
+  return s * (N + N / 16 + 1) + e + (e >> 4);
+}
+
+// One Stockham radix-2^LR pass over NSEQ sequences of length N held in LDS.
+// p is the product of the radices of earlier passes.  All inputs of the pass
+// are read to registers before a barrier, so the pass runs in place.
+template <typename R, int N, int NSEQ, int T, bool INV, int LR, int P>
+__device__ __forceinline__ void fft_pass(Cx<R>* lds, const Cx<R>* __restrict__ tw) {
+  constexpr int RAD = 1 << LR;
+  constexpr int NQ = N / RAD;             // butterflies per sequence
+  constexpr int NB = NSEQ * NQ;           // butterflies in the pass
+  constexpr int PER = (NB + T - 1) / T;   // per thread
+  const int tid = threadIdx.x;
+  Cx<R> u[PER][RAD];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * T;
+    if (NB % T == 0 || b < NB) {
+      const int s = b / NQ, i = b % NQ;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) u[q][r] = lds[lidx<N>(s, i + r * NQ)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * T;
+    if (NB % T == 0 || b < NB) {
+      const int s = b / NQ, i = b % NQ;
+      const int k = i & (P - 1);
+      if constexpr (P > 1) {
+        // twiddle exp(-+2 pi i r k / (P RAD)) = tw[r k N/(P RAD)]
+        constexpr int SCL = N / (P * RAD);
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          Cx<R> w = tw[r * k * SCL];
+          if (INV) w.y = -w.y;
+          u[q][r] = u[q][r] * w;
+        }
+      }
+      Dft<R, RAD, INV>::run(u[q]);
+      const int j = (i - k) * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) lds[lidx<N>(s, j + r * P)] = u[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int LOG2N, int NSEQ, int T, bool INV, int MAXLOG, int DONE>
+__device__ __forceinline__ void fft_run(Cx<R>* lds, const Cx<R>* __restrict__ tw) {
+  if constexpr (DONE < LOG2N) {
+    constexpr int LR = (DONE == 0 && (LOG2N % MAXLOG) != 0) ? (LOG2N % MAXLOG) : MAXLOG;
+    fft_pass<R, (1 << LOG2N), NSEQ, T, INV, LR, (1 << DONE)>(lds, tw);
+    fft_run<R, LOG2N, NSEQ, T, INV, MAXLOG, DONE + LR>(lds, tw);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile-local solve of (mu I - A~) restricted to the nb interior columns of a
+// tile (rows b = 0..nb-1, global column i0 + b).  Couplings to the columns
+// left of b = 0 and right of b = nb-1 are excluded (they are the interface
+// unknowns of the partitioned solve).  Plain Thomas elimination, no pivoting
+// (the matrix is strictly diagonally dominant for 0 < alpha < 1).
+// C is Cx<R> for a complex shift, R for a real one.  lo/di/up hold tau*A.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ Cx<R> shift_sub(Cx<R> mu, R d) { return {mu.x - d, mu.y}; }
+template <typename R>
+__device__ __forceinline__ R shift_sub(R mu, R d) { return mu - d; }
+template <typename R>
+__device__ __forceinline__ Cx<R> zero_of(Cx<R>) { return {R(0), R(0)}; }
+template <typename R>
+__device__ __forceinline__ R zero_of(R) { return R(0); }
+template <typename R>
+__device__ __forceinline__ Cx<R> axpy_r(Cx<R> a, R s, Cx<R> b) {  // a - s*b
+  return {a.x - s * b.x, a.y - s * b.y};
+}
+__device__ __forceinline__ double axpy_r(double a, double s, double b) { return a - s * b; }
+__device__ __forceinline__ float axpy_r(float a, float s, float b) { return a - s * b; }
+template <typename R>
+__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) { return a * b; }
+__device__ __forceinline__ double cmul(double a, double b) { return a * b; }
+__device__ __forceinline__ float cmul(float a, float b) { return a * b; }
+template <typename R>
+__device__ __forceinline__ Cx<R> rmul(R s, Cx<R> a) { return {s * a.x, s * a.y}; }
+__device__ __forceinline__ double rmul(double s, double a) { return s * a; }
+__device__ __forceinline__ float rmul(float s, float a) { return s * a; }
+
+// co: LDS, per column b of the tile: co[3b] = lo, co[3b+1] = di, co[3b+2] = up
+template <typename R, typename C, int B>
+__device__ __forceinline__ void tile_solve(C (&d)[B], C mu, const R* co, int nb) {
+  C c[B];
+  C yp = zero_of(mu);
+  C cp = zero_of(mu);
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    if (b < nb) {
+      const R lb = (b == 0) ? R(0) : -co[3 * b];
+      // pivot = (mu - di) - lb * c_{b-1}
+      const C piv = axpy_r(shift_sub(mu, co[3 * b + 1]), lb, cp);
+      const C q = crcp(piv);
+      cp = (b < nb - 1) ? rmul(-co[3 * b + 2], q) : zero_of(mu);
+      c[b] = cp;
+      yp = cmul(axpy_r(d[b], lb, yp), q);
+      d[b] = yp;
+    }
+  }
+#pragma unroll
+  for (int b = B - 2; b >= 0; --b) {
+    if (b < nb - 1) d[b] = d[b] - cmul(c[b], d[b + 1]);
+  }
+}
+
+// Remap a flat workgroup index so that consecutive tiles run on the same XCD
+// (workgroups are dealt round-robin over the 8 XCDs, each with its own L2).
+__device__ __forceinline__ int xcd_tile(int wg, int nwg_padded) {
+  const int per = nwg_padded >> 3;
+  return (wg & 7) * per + (wg >> 3);
+}
+
+}  // namespace cn
