@@ -139,6 +139,22 @@ cn_status cn_gmres_solve(cn_aao *h, const double *b, double *x,
 cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
                        int32_t *threads);
 
+/* Kernel timing of one inner iteration, for benchmarking.  Must follow a
+ * cn_gmres_solve on the same handle that ran at least j+1 inner iterations
+ * (its basis is reused; the solution is not touched).  Launches each of the
+ * six kernels of iteration j `reps` times back to back on the handle's
+ * stream, timed with HIP events, and returns per kernel the average launch
+ * duration in milliseconds and the algorithmic bytes one launch must move
+ * (reads + writes of its inputs and outputs, each touched once).  Kernel
+ * order: 0 pc_forward (steps (a) + local (b)), 1 pc_reduced (interface
+ * systems of (b)), 2 pc_inverse (correction + step (c)), 3 matvec fused with
+ * the first Gram-Schmidt dots, 4 second Gram-Schmidt dots, 5 basis update +
+ * norm + Givens; the three Krylov entries include their one-workgroup
+ * finishing reduction kernel.  ms and bytes: host arrays of 6 doubles.
+ * Synchronises. */
+#define CN_PROFILE_KERNELS 6
+cn_status cn_profile_step(cn_aao *h, int32_t j, int32_t reps, double *ms, double *bytes);
+
 const char *cn_status_string(cn_status s);
 const char *cn_last_error(void);
 

@@ -74,6 +74,8 @@ def load():
         "cn_pc_apply": (ctypes.c_int, [vp, vp, vp]),
         "cn_gmres_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(CnGmresOpts),
                                           ctypes.POINTER(CnGmresInfo)]),
+        "cn_profile_step": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(dbl),
+                                           ctypes.POINTER(dbl)]),
         "cn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "cn_last_error": (ctypes.c_char_p, []),
     }
@@ -177,6 +179,17 @@ class Solver:
     def pc_apply(self, v, out):
         _check(self._lib.cn_pc_apply(self._h, _ptr(v), _ptr(out)), "cn_pc_apply")
         return out
+
+    KERNELS = ("pc_forward", "pc_reduced", "pc_inverse", "matvec_dots", "cgs_pass1",
+               "cgs_pass2")
+
+    def profile_step(self, j: int, reps: int = 20):
+        """Average launch time (ms) and algorithmic bytes of the six kernels of
+        inner iteration j (after a solve with more than j iterations)."""
+        ms = (ctypes.c_double * 6)()
+        by = (ctypes.c_double * 6)()
+        _check(self._lib.cn_profile_step(self._h, int(j), int(reps), ms, by), "cn_profile_step")
+        return {k: {"ms": ms[i], "bytes": by[i]} for i, k in enumerate(self.KERNELS)}
 
     def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
               use_x0: bool = False, allow_not_converged: bool = True) -> SolveResult:

@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -45,9 +46,10 @@ struct cn_aao {
   double* w = nullptr;    // npad
   double* partials = nullptr;
   GState* st = nullptr;
-  GSummary* hsum = nullptr;  // pinned host, 4 slots
+  GSummary* hsum = nullptr;  // pinned coherent host memory, 4 slots
+  GSummary* hsum_dev = nullptr;  // the same slots as seen by kernels
+  int seqc = 0;                  // last sequence number handed to a kernel
   hipEvent_t ev[2] = {nullptr, nullptr};
-  hipEvent_t t0 = nullptr, t1 = nullptr;
   std::vector<void*> dev_allocs;
 };
 
@@ -58,8 +60,6 @@ static void release(cn_aao* h) {
   if (h->hsum != nullptr) (void)hipHostFree(h->hsum);
   for (auto& e : h->ev)
     if (e != nullptr) (void)hipEventDestroy(e);
-  if (h->t0 != nullptr) (void)hipEventDestroy(h->t0);
-  if (h->t1 != nullptr) (void)hipEventDestroy(h->t1);
   delete h;
 }
 
@@ -79,6 +79,40 @@ static bool overlaps(const void* a, const void* b, size_t bytes) {
   const char* y = (const char*)b;
   return x < y + bytes && y < x + bytes;
 }
+
+// Spin until a kernel has published sequence number `seq` into `slot`
+// (coherent pinned host memory), then copy the summary out.
+static cn_status wait_slot(cn_aao* h, GSummary* slot, int seq, GSummary* out) {
+  volatile int* p = &slot->seq;
+  long spins = 0;
+  while (*p != seq) {
+    if ((++spins & 4095) == 0) {
+      const hipError_t e = hipStreamQuery(h->stream);
+      if (e != hipSuccess && e != hipErrorNotReady)
+        return fail(CN_EHIP, std::string("solver stream: ") + hipGetErrorString(e));
+      if (e == hipSuccess && *p != seq)
+        return fail(CN_EHIP, "solver kernels finished without publishing their summary");
+    }
+    __builtin_ia32_pause();
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  volatile GSummary* v = slot;
+  out->bnorm = v->bnorm;
+  out->beta = v->beta;
+  out->est = v->est;
+  out->relres = v->relres;
+  out->k = v->k;
+  out->done = v->done;
+  out->breakdown = v->breakdown;
+  out->seq = seq;
+  return CN_OK;
+}
+
+#define CN_TRY(expr)               \
+  do {                             \
+    const cn_status st_ = (expr);  \
+    if (st_ != CN_OK) return st_;  \
+  } while (0)
 
 extern "C" {
 
@@ -235,16 +269,31 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
   }
   const long double a1 = expl(la / nt);                  // alpha^{1/N_t}
   for (int j = 0; j < pl.F; ++j) {
-    const long double ang = -2.0L * PI * j / nt;
-    const long double wr = cosl(ang), wi = sinl(ang);
+    // omega^j; the modes j = 0 and j = N_t/2 are real (omega^j = +-1 exactly)
+    long double wr, wi;
+    if (j == 0) {
+      wr = 1.0L;
+      wi = 0.0L;
+    } else if (2 * j == nt) {
+      wr = -1.0L;
+      wi = 0.0L;
+    } else {
+      const long double ang = -2.0L * PI * j / nt;
+      wr = cosl(ang);
+      wi = sinl(ang);
+    }
     // lambda_1 = 1 - a omega^j, lambda_2 = dbar (1 + a omega^j) / 2
     const long double l1r = 1.0L - a1 * wr, l1i = -a1 * wi;
-    const long double l2r = 0.5L * dbar * (1.0L + a1 * wr), l2i = 0.5L * dbar * a1 * wi;
-    const long double den = l2r * l2r + l2i * l2i;
-    if (!(den > 0.0L)) {
-      fail(CN_ESINGULAR, "lambda_2 vanishes");
-      return bail(CN_ESINGULAR);
+    long double l2r = 0.5L * dbar * (1.0L + a1 * wr), l2i = 0.5L * dbar * a1 * wi;
+    // lambda_2 vanishes only for alpha = 1 at j = N_t/2, where the shifted
+    // system reduces to lambda_1 I; a relative floor of 1e-15 keeps the
+    // (mu I - A~)/lambda_2 form finite (a perturbation far below rounding)
+    const long double l1m = sqrtl(l1r * l1r + l1i * l1i);
+    if (sqrtl(l2r * l2r + l2i * l2i) < 1e-15L * l1m) {
+      l2r = 1e-15L * l1m;
+      l2i = 0.0L;
     }
+    const long double den = l2r * l2r + l2i * l2i;
     mu[j] = Cx<double>{(double)((l1r * l2r + l1i * l2i) / den),
                        (double)((l1i * l2r - l1r * l2i) / den)};
     il2[j] = Cx<double>{(double)(l2r / den), (double)(-l2i / den)};
@@ -309,12 +358,12 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
   }
   TRY(dalloc(h, &h->st, sizeof(GState)));
   TRY(hipMemsetAsync(h->st, 0, sizeof(GState), h->stream));
-  TRY(hipHostMalloc((void**)&h->hsum, 4 * sizeof(GSummary), hipHostMallocDefault));
+  TRY(hipHostMalloc((void**)&h->hsum, 4 * sizeof(GSummary),
+                    hipHostMallocCoherent | hipHostMallocMapped));
   memset(h->hsum, 0, 4 * sizeof(GSummary));
+  TRY(hipHostGetDevicePointer((void**)&h->hsum_dev, h->hsum, 0));
   TRY(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
   TRY(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
-  TRY(hipEventCreate(&h->t0));
-  TRY(hipEventCreate(&h->t1));
   TRY(hipStreamSynchronize(h->stream));
 #undef TRY
   (void)rc;
@@ -395,29 +444,24 @@ cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_o
   const int* done = &st->sum.done;
   const int zf = h->prec;
   const size_t zes = zf ? sizeof(float) : sizeof(double);
-  HIP_TRY(hipEventRecord(h->t0, s));
-  if (!opts->use_x0) HIP_TRY(hipMemsetAsync(x, 0, h->n * sizeof(double), s));
   const double rtol = opts->rtol;
-  HIP_TRY(hipMemcpyAsync(&st->rtol, &rtol, sizeof(double), hipMemcpyHostToDevice, s));
   KArgs a = kargs(h);
-  // r_0 = b - M x_0 into v_0, ||b||, beta
-  HIP_TRY(launch_matvec(a, opts->use_x0 ? x : nullptr, 0, b, h->V, 1, s));
   GSummary* hs = h->hsum;
-  HIP_TRY(hipMemcpyAsync(&hs[2], &st->sum, sizeof(GSummary), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  GSummary cur = hs[2];
+  GSummary* hd = h->hsum_dev;
+  // r_0 = b - M x_0 into v_0 (x_0 = 0 is never read); its summary -> slot 2.
+  // No host wait here: if r_0 already meets rtol the device flag makes the
+  // first cycle's kernels return at once.
+  int seq_res = ++h->seqc;
+  HIP_TRY(launch_matvec(a, opts->use_x0 ? x : nullptr, 0, b, h->V, 1, s, rtol, hd + 2, seq_res));
+  GSummary cur{}, fin{}, it{};
   int iters = 0, restarts = 0, matvecs = 1, pcs = 0;
-  double est = cur.relres;
-  if (cur.bnorm == 0.0) {
-    HIP_TRY(hipMemsetAsync(x, 0, h->n * sizeof(double), s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (info != nullptr) {
-      *info = cn_gmres_info{0, 0, 1, 0, 0.0, 0.0, 0.0};
-    }
-    return CN_OK;
-  }
-  while (!(cur.relres <= rtol) && iters < opts->max_iters) {
+  double est = 0.0;
+  bool x_zero = !opts->use_x0;
+  int seqs[MMAX];
+  double ests[MMAX];
+  while (true) {
     const int m_eff = std::min(opts->m, opts->max_iters - iters);
+    int known = 0;  // iterations of this cycle whose summary the host has read
     for (int j = 0; j < m_eff; ++j) {
       const double* vj = h->V + (size_t)j * h->npad;
       void* zj = (char*)h->Z + (size_t)j * h->npad * zes;
@@ -425,46 +469,134 @@ cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_o
       HIP_TRY(pc_reduced(h->pl, done, s));
       HIP_TRY(pc_inverse(h->pl, zj, zf, done, s));
       a.nv = j + 1;
-      HIP_TRY(launch_matvec(a, zj, zf, nullptr, h->w, 2, s));
-      HIP_TRY(launch_cgs(a, h->w, h->V + (size_t)(j + 1) * h->npad, j, m_eff, s));
-      HIP_TRY(hipMemcpyAsync(&hs[j & 1], &st->sum, sizeof(GSummary), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipEventRecord(h->ev[j & 1], s));
+      HIP_TRY(launch_matvec(a, zj, zf, nullptr, h->w, 2, s, rtol));
+      // iteration j publishes into slot j & 1; check iteration j-1 while j runs
+      seqs[j] = ++h->seqc;
+      HIP_TRY(launch_cgs(a, h->w, h->V + (size_t)(j + 1) * h->npad, j, m_eff, s, 3, rtol,
+                         hd + (j & 1), seqs[j]));
       if (j >= 1) {
-        HIP_TRY(hipEventSynchronize(h->ev[(j - 1) & 1]));
-        if (hs[(j - 1) & 1].done) break;
+        if (known < j) {
+          CN_TRY(wait_slot(h, hs + ((j - 1) & 1), seqs[j - 1], &it));
+          ests[j - 1] = it.est;
+          known = j;
+          if (it.done) break;
+        }
+        // The residual estimate falls at least geometrically (usually
+        // faster).  When the rate of the last two steps brings iteration j
+        // within 50x of rtol, wait for it instead of queueing iteration j+1:
+        // an iteration queued after convergence still costs nine no-op kernel
+        // dispatches (~45 us), a wrong guess only a short idle gap (~15 us).
+        double prev;
+        if (j >= 2) {
+          prev = ests[j - 2];
+        } else {
+          volatile GSummary* r0 = hs + 2;
+          prev = (r0->seq == seq_res && r0->relres > 0.0) ? r0->relres : 1.0;
+        }
+        const double rate = prev > 0.0 ? ests[j - 1] / prev : 1.0;
+        if (j + 1 < m_eff && ests[j - 1] * rate < 50.0 * rtol) {
+          CN_TRY(wait_slot(h, hs + (j & 1), seqs[j], &it));
+          ests[j] = it.est;
+          known = j + 1;
+          if (it.done) break;
+        }
       }
     }
-    HIP_TRY(launch_finish_update(st, h->Z, zf, h->npad, x, h->n, s));
-    HIP_TRY(hipMemcpyAsync(&hs[3], &st->sum, sizeof(GSummary), hipMemcpyDeviceToHost, s));
-    HIP_TRY(launch_matvec(a, x, 0, b, h->V, 1, s));
-    HIP_TRY(hipMemcpyAsync(&hs[2], &st->sum, sizeof(GSummary), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const int k = hs[3].k;
-    est = hs[3].est;
-    cur = hs[2];
+    // y from the triangular factor (cycle summary -> slot 3), x += Z y, then
+    // the true residual (-> slot 2)
+    const int seq_fin = ++h->seqc;
+    HIP_TRY(launch_finish_update(st, h->Z, zf, h->npad, x, h->n, x_zero ? 1 : 0, hd + 3,
+                                 seq_fin, s));
+    x_zero = false;
+    seq_res = ++h->seqc;
+    HIP_TRY(launch_matvec(a, x, 0, b, h->V, 1, s, rtol, hd + 2, seq_res));
+    CN_TRY(wait_slot(h, hs + 3, seq_fin, &fin));
+    CN_TRY(wait_slot(h, hs + 2, seq_res, &cur));
+    const int k = fin.k;
+    if (k > 0) est = fin.est;
     iters += k;
     pcs += k;
     matvecs += k + 1;
-    if (k == 0) break;  // no progress possible (should not happen)
-    if (!(cur.relres <= rtol) && iters < opts->max_iters) ++restarts;
+    if (k == 0 || cur.relres <= rtol || iters >= opts->max_iters) break;
+    ++restarts;
   }
-  HIP_TRY(hipEventRecord(h->t1, s));
-  HIP_TRY(hipEventSynchronize(h->t1));
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, h->t0, h->t1));
+  if (cur.bnorm == 0.0) {
+    // b = 0: the solution is x = 0 whatever the initial guess
+    HIP_TRY(hipMemsetAsync(x, 0, h->n * sizeof(double), s));
+    cur.relres = 0.0;
+    est = 0.0;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
   const auto wall1 = std::chrono::steady_clock::now();
-  (void)wall0;
-  (void)wall1;
   if (info != nullptr) {
     info->iters = iters;
     info->restarts = restarts;
     info->matvecs = matvecs;
     info->pc_applies = pcs;
     info->relres_true = cur.relres;
-    info->relres_est = est;
-    info->seconds = ms * 1e-3;
+    info->relres_est = iters > 0 ? est : cur.relres;
+    info->seconds = std::chrono::duration<double>(wall1 - wall0).count();
   }
   return cur.relres <= rtol ? CN_OK : CN_NOT_CONVERGED;
+}
+
+cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double* bytes) {
+  if (h == nullptr || ms == nullptr || bytes == nullptr) return fail(CN_EINVAL, "NULL argument");
+  if (j < 0 || j >= h->m_max || reps < 1) return fail(CN_EINVAL, "j or reps out of range");
+  hipStream_t s = h->stream;
+  GState* st = h->st;
+  const int zf = h->prec;
+  const size_t zes = zf ? sizeof(float) : sizeof(double);
+  const size_t rsz = h->prec ? sizeof(float) : sizeof(double);
+  const double* vj = h->V + (size_t)j * h->npad;
+  void* zj = (char*)h->Z + (size_t)j * h->npad * zes;
+  KArgs a = kargs(h);
+  a.nv = j + 1;
+  // keep every kernel of the step active
+  const int zero = 0;
+  HIP_TRY(hipMemcpyAsync(&st->sum.done, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  const int* done = &st->sum.done;
+  hipEvent_t ev[2];
+  HIP_TRY(hipEventCreate(&ev[0]));
+  HIP_TRY(hipEventCreate(&ev[1]));
+  const PcPlan& pl = h->pl;
+  const double n = (double)h->n;
+  const double nimg = (double)pl.P * pl.B * pl.nt;
+  const double nsep = (double)pl.F * pl.NS;
+  bytes[0] = n * 8 + nimg * rsz + (double)pl.F * pl.P * 6 * rsz;
+  bytes[1] = nsep * (6 * rsz + 3 * 16 + 2 * 16 + 2 * rsz);
+  bytes[2] = nimg * rsz + (double)pl.F * pl.P * 4 * rsz + n * zes;
+  bytes[3] = n * zes + n * 8 + (double)(j + 1) * n * 8;
+  bytes[4] = (double)(j + 2) * n * 8;
+  bytes[5] = (double)(j + 3) * n * 8;
+  cn_status rc = CN_OK;
+  for (int kk = 0; kk < CN_PROFILE_KERNELS && rc == CN_OK; ++kk) {
+    hipError_t e = hipEventRecord(ev[0], s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      switch (kk) {
+        case 0: e = pc_forward(pl, vj, &st->vscale[j], done, s); break;
+        case 1: e = pc_reduced(pl, done, s); break;
+        case 2: e = pc_inverse(pl, zj, zf, done, s); break;
+        case 3: e = launch_matvec(a, zj, zf, nullptr, h->w, 2, s); break;
+        case 4: e = launch_cgs(a, h->w, nullptr, j, -1, s, 1, -1.0, nullptr, 0); break;
+        // rtol < 0 and an unreachable restart length keep the stop flag clear
+        case 5: e = launch_cgs(a, h->w, h->V + (size_t)(j + 1) * h->npad, j, 1 << 30, s, 2,
+                               -1.0, nullptr, 0); break;
+      }
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+    if (e != hipSuccess) {
+      rc = fail(CN_EHIP, std::string("profile: ") + hipGetErrorString(e));
+      break;
+    }
+    ms[kk] = (double)t / reps;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  return rc;
 }
 
 }  // extern "C"

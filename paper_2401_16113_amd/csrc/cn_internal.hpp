@@ -44,13 +44,12 @@ struct GSummary {
   int k;          // inner iterations completed in the current cycle
   int done;       // nonzero: the cycle has stopped, remaining kernels return
   int breakdown;  // lucky breakdown (h_{j+1,j} == 0)
-  int pad;
+  int seq;        // sequence number of the write (host polling), written last
 };
 
 // Device state of one GMRES solve (float64), read and written by kernels.
 struct GState {
   GSummary sum;
-  double rtol;
   double H[(MMAX + 1) * MMAX];  // triangular factor, column j at H[j*(MMAX+1)]
   double g[MMAX + 1];
   double cs[MMAX], sn[MMAX];
@@ -58,7 +57,6 @@ struct GState {
   double h1[NVMAX], c1[NVMAX];  // first Gram-Schmidt pass: coefficients
   double h2[NVMAX], c2[NVMAX];  // second pass
   double y[MMAX];
-  unsigned int tickets[8];
 };
 
 // Launchers (cn_pc.hip)
@@ -87,12 +85,18 @@ struct KArgs {
 };
 constexpr int KGRID = 2048;  // target number of workgroups of a streaming pass
 int matvec_rows(int nx, int nt);
+// mode 0: y = M x; 1: y = b - M x + norms (finish: cycle start, summary to
+// `host`); 2: y = M x + first Gram-Schmidt dots
 hipError_t launch_matvec(const KArgs& a, const void* x, int x_is_float, const double* b,
-                         double* y, int mode, hipStream_t s);
+                         double* y, int mode, hipStream_t s, double rtol = 0.0,
+                         GSummary* host = nullptr, int seq = 0);
+// passes: 1 = second Gram-Schmidt dots, 2 = update + norm + Givens, 3 = both
 hipError_t launch_cgs(const KArgs& a, const double* w, double* vout, int j, int stop_iter,
-                      hipStream_t s);
+                      hipStream_t s, int passes = 3, double rtol = 0.0,
+                      GSummary* host = nullptr, int seq = 0);
 hipError_t launch_finish_update(GState* st, const void* Z, int z_is_float, long long zstride,
-                                double* x, long long n, hipStream_t s);
+                                double* x, long long n, int x_zero, GSummary* host, int seq,
+                                hipStream_t s);
 hipError_t launch_rhs(const double* lo, const double* di, const double* up, const double* dw,
                       double tau, const double* u0, const double* f, double* b, int nx,
                       long long n, hipStream_t s);

@@ -7,8 +7,11 @@
 //   * the Givens / least-squares update, done by the last workgroup of the
 //     final pass (no host round-trip inside a cycle);
 //   * x += Z y and the right-hand side b = xi + tau f (eq. (2.2)).
-// Reductions are deterministic: per-workgroup partial sums in a fixed order,
-// summed in a fixed order by whichever workgroup finishes last.
+// Reductions are deterministic: every workgroup of a streaming pass writes
+// its partial sums; a one-workgroup finishing kernel adds them in a fixed
+// order and updates the solver state.  Stream order makes the partials
+// visible, so no workgroup issues a device-scope fence (on a multi-XCD part
+// such a fence writes back and invalidates the XCD's L2).
 #include <math.h>
 
 #include "cn_internal.hpp"
@@ -23,7 +26,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block-reduce NV accumulators into partials[blk*NVMAX + q] (fixed order).
+// Block-reduce NV accumulators into partials[q*nblk + blk] (fixed order).
 template <int NV>
 __device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, double* red,
                                                double* partials, int blk) {
@@ -40,45 +43,50 @@ __device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, 
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < KT / 64; ++w) s += red[w * NV + tid];
-    partials[(size_t)blk * NVMAX + tid] = s;
+    partials[(size_t)tid * gridDim.x + blk] = s;
   }
 }
 
-// Returns true in exactly one workgroup: the last one to finish.  Its
-// threads see every other workgroup's partials afterwards.
-__device__ __forceinline__ bool last_block(unsigned int* ticket, unsigned int nblk) {
-  __shared__ unsigned int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int t = atomicAdd(ticket, 1u);
-    s_last = (t == nblk - 1) ? 1u : 0u;
-  }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    if (threadIdx.x == 0) *ticket = 0u;  // re-arm for the next launch
-  }
-  return s_last != 0u;
-}
-
-// Sum partials over blocks for q < nv into out[q] (fixed order).
-__device__ __forceinline__ void reduce_partials(const double* partials, int nblk, int nv,
-                                                double* out, double* red) {
-  const int tid = threadIdx.x;
-  for (int q = 0; q < nv; ++q) {
+// Sum partials[q*nblk + b] over b for q < nv into out[q]: wave w handles
+// q = w, w + 16, ...; lane l adds b = l, l + 64, ... then the wave adds its
+// lanes.  The order is fixed, so the result is bitwise reproducible.
+constexpr int FT = 1024;  // threads of a finishing kernel
+constexpr int FCHUNK = 32;  // partials per lane loaded back to back
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int nblk,
+                                                int nv, double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = wv; q < nv; q += FT / 64) {
+    const double* p = partials + (size_t)q * nblk;
     double s = 0.0;
-    for (int b = tid; b < nblk; b += KT) s += partials[(size_t)b * NVMAX + q];
-    s = wave_sum(s);
-    if ((tid & 63) == 0) red[tid >> 6] = s;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < KT / 64; ++w) t += red[w];
-      out[q] = t;
+    for (int base = 0; base < nblk; base += 64 * FCHUNK) {
+      double v[FCHUNK];
+#pragma unroll
+      for (int i = 0; i < FCHUNK; ++i) {
+        const int b = base + lane + 64 * i;
+        v[i] = b < nblk ? p[b] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < FCHUNK; ++i) s += v[i];
     }
-    __syncthreads();
+    s = wave_sum(s);
+    if (lane == 0) out[q] = s;
   }
+  __syncthreads();
+}
+
+// Publish the summary to the host slot: fields first, then (after a
+// system-scope fence) the sequence number the host polls for.
+__device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int seq) {
+  if (host == nullptr) return;
+  host->bnorm = sm.bnorm;
+  host->beta = sm.beta;
+  host->est = sm.est;
+  host->relres = sm.relres;
+  host->k = sm.k;
+  host->done = sm.done;
+  host->breakdown = sm.breakdown;
+  __threadfence_system();
+  *(volatile int*)&host->seq = seq;
 }
 
 // ---------------------------------------------------------------------------
@@ -142,33 +150,8 @@ __global__ __launch_bounds__(KT) void k_matvec(KArgs a, const TX* __restrict__ x
     }
   }
   if (MODE == 0) return;
-  const int nblk = gridDim.x;
   const int nacc = MODE == 1 ? 2 : a.nv;
   block_partials<(NV > 2 ? NV : 2)>(acc, nacc, red, a.partials, blk);
-  if (!last_block(&st->tickets[MODE], nblk)) return;
-  __shared__ double out[NVMAX];
-  reduce_partials(a.partials, nblk, nacc, out, red);
-  if (threadIdx.x == 0) {
-    if (MODE == 1) {
-      // start of a cycle: beta = ||r||, v_0 = r / beta (stored unnormalised)
-      GSummary& sm = st->sum;
-      sm.bnorm = sqrt(out[1]);
-      const double beta = sqrt(out[0]);
-      sm.beta = beta;
-      st->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
-      st->g[0] = beta;
-      for (int q = 1; q <= MMAX; ++q) st->g[q] = 0.0;
-      sm.relres = sm.bnorm > 0.0 ? beta / sm.bnorm : 0.0;
-      sm.breakdown = 0;
-      sm.done = (sm.relres <= st->rtol || beta == 0.0) ? 1 : 0;
-    } else {
-      for (int q = 0; q < a.nv; ++q) {
-        const double h = out[q] * st->vscale[q];
-        st->h1[q] = h;
-        st->c1[q] = h * st->vscale[q];
-      }
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -197,18 +180,7 @@ __global__ __launch_bounds__(KT) void k_cgs_pass1(KArgs a, const double* __restr
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] += vq[q] * wv;
   }
-  const int nblk = gridDim.x;
   block_partials<NV>(acc, a.nv, red, a.partials, blockIdx.x);
-  if (!last_block(&st->tickets[3], nblk)) return;
-  __shared__ double out[NVMAX];
-  reduce_partials(a.partials, nblk, a.nv, out, red);
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < a.nv; ++q) {
-      const double h = out[q] * st->vscale[q];
-      st->h2[q] = h;
-      st->c2[q] = h * st->vscale[q];
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -217,8 +189,7 @@ __global__ __launch_bounds__(KT) void k_cgs_pass1(KArgs a, const double* __restr
 // ---------------------------------------------------------------------------
 template <int NV>
 __global__ __launch_bounds__(KT) void k_cgs_pass2(KArgs a, const double* __restrict__ w,
-                                                  double* __restrict__ vout, int j,
-                                                  int stop_iter) {
+                                                  double* __restrict__ vout) {
   __shared__ double red[(KT / 64) * 2];
   GState* st = a.st;
   if (st->sum.done) return;
@@ -235,12 +206,53 @@ __global__ __launch_bounds__(KT) void k_cgs_pass2(KArgs a, const double* __restr
     vout[e] = wv;
     acc[0] += wv * wv;
   }
-  const int nblk = gridDim.x;
   block_partials<2>(acc, 1, red, a.partials, blockIdx.x);
-  if (!last_block(&st->tickets[4], nblk)) return;
+}
+
+// ---------------------------------------------------------------------------
+// finishing kernels (one workgroup): fixed-order sums of the partials
+// ---------------------------------------------------------------------------
+// FIN 1: residual r = b - M x -> ||b||, beta, v_0 scale, g, relres, stop flag
+// FIN 2: first Gram-Schmidt dots -> h1, c1
+// FIN 3: second Gram-Schmidt dots -> h2, c2
+// FIN 4: ||v_{j+1}|| -> Hessenberg column, Givens rotation, residual estimate
+template <int FIN>
+__global__ __launch_bounds__(FT) void k_finish(GState* __restrict__ st,
+                                               const double* __restrict__ partials, int nblk,
+                                               int nv, int j, int stop_iter, double rtol,
+                                               GSummary* __restrict__ host, int seq) {
   __shared__ double out[NVMAX];
-  reduce_partials(a.partials, nblk, 1, out, red);
-  if (threadIdx.x == 0) {
+  if (FIN != 1 && st->sum.done) {
+    // the cycle already stopped: still tell a polling host so
+    if (FIN == 4 && threadIdx.x == 0) publish(host, st->sum, seq);
+    return;
+  }
+  const int nq = FIN == 1 ? 2 : (FIN == 4 ? 1 : nv);
+  reduce_partials(partials, nblk, nq, out);
+  if (threadIdx.x != 0) return;
+  GSummary& sm = st->sum;
+  if (FIN == 1) {
+    // start of a cycle: beta = ||r||, v_0 = r / beta (stored unnormalised)
+    sm.bnorm = sqrt(out[1]);
+    const double beta = sqrt(out[0]);
+    sm.beta = beta;
+    st->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+    st->g[0] = beta;
+    for (int q = 1; q <= MMAX; ++q) st->g[q] = 0.0;
+    sm.relres = sm.bnorm > 0.0 ? beta / sm.bnorm : 0.0;
+    sm.breakdown = 0;
+    sm.k = 0;
+    sm.done = (sm.relres <= rtol || beta == 0.0) ? 1 : 0;
+    publish(host, sm, seq);
+  } else if (FIN == 2 || FIN == 3) {
+    double* hh = FIN == 2 ? st->h1 : st->h2;
+    double* cc = FIN == 2 ? st->c1 : st->c2;
+    for (int q = 0; q < nv; ++q) {
+      const double h = out[q] * st->vscale[q];
+      hh[q] = h;
+      cc[q] = h * st->vscale[q];
+    }
+  } else {
     const double hn = sqrt(out[0]);
     double col[MMAX + 1];
     for (int q = 0; q <= j; ++q) col[q] = st->h1[q] + st->h2[q];
@@ -264,20 +276,22 @@ __global__ __launch_bounds__(KT) void k_cgs_pass2(KArgs a, const double* __restr
     const double gj = st->g[j];
     st->g[j] = cs * gj;
     st->g[j + 1] = -sn * gj;
-    GSummary& sm = st->sum;
     const double est = fabs(st->g[j + 1]);
     sm.est = sm.bnorm > 0.0 ? est / sm.bnorm : 0.0;
     st->vscale[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
     sm.k = j + 1;
     const bool brk = !(hn > 1e-300 * (sm.beta > 0.0 ? sm.beta : 1.0));
     sm.breakdown = brk ? 1 : 0;
-    if (est <= st->rtol * sm.bnorm || brk || j + 1 >= stop_iter) sm.done = 1;
+    if (est <= rtol * sm.bnorm || brk || j + 1 >= stop_iter) sm.done = 1;
+    publish(host, sm, seq);
   }
 }
 
-// End of a cycle: solve the k x k triangular system R y = g.
-__global__ void k_cycle_finish(GState* st) {
+// End of a cycle: solve the k x k triangular system R y = g; copy the
+// cycle's summary (k, estimate) to the host slot.
+__global__ void k_cycle_finish(GState* st, GSummary* host, int seq) {
   if (threadIdx.x != 0) return;
+  publish(host, st->sum, seq);
   const int k = st->sum.k;
   for (int q = k - 1; q >= 0; --q) {
     double s = st->g[q];
@@ -291,12 +305,13 @@ __global__ void k_cycle_finish(GState* st) {
 template <typename TZ>
 __global__ __launch_bounds__(KT) void k_update(const GState* __restrict__ st,
                                                const TZ* __restrict__ Z, long long zstride,
-                                               double* __restrict__ x, long long n) {
+                                               double* __restrict__ x, long long n,
+                                               int x_zero) {
   const int k = st->sum.k;
   const double* y = st->y;
   const long long stride = (long long)gridDim.x * KT;
   for (long long e = (long long)blockIdx.x * KT + threadIdx.x; e < n; e += stride) {
-    double s = x[e];
+    double s = x_zero ? 0.0 : x[e];
     int q = 0;
     for (; q + 4 <= k; q += 4) {
       s += y[q] * (double)Z[(size_t)q * zstride + e] +
@@ -361,17 +376,23 @@ int stream_grid(long long n) {
 }
 
 hipError_t launch_matvec(const KArgs& a, const void* x, int x_is_float, const double* b,
-                         double* y, int mode, hipStream_t s) {
-  const int grid = matvec_grid(a.nx, a.nt);
+                         double* y, int mode, hipStream_t s, double rtol, GSummary* host,
+                         int seq) {
+  const int grid = ((a.nx + KT - 1) / KT) * ((a.nt + a.rows - 1) / a.rows);
   if (mode == 0) {
     if (x_is_float)
       hipLaunchKernelGGL((k_matvec<float, 0, 2>), dim3(grid), dim3(KT), 0, s, a, (const float*)x, b, y);
     else
       hipLaunchKernelGGL((k_matvec<double, 0, 2>), dim3(grid), dim3(KT), 0, s, a, (const double*)x, b, y);
-  } else if (mode == 1) {
+    return hipGetLastError();
+  }
+  if (mode == 1) {
     hipLaunchKernelGGL((k_matvec<double, 1, 2>), dim3(grid), dim3(KT), 0, s, a, (const double*)x, b, y);
-  } else {
-    const int bk = nv_bucket(a.nv);
+    hipLaunchKernelGGL((k_finish<1>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, 2, 0, 0,
+                       rtol, host, seq);
+    return hipGetLastError();
+  }
+  const int bk = nv_bucket(a.nv);
 #define MV(NVB)                                                                                    \
   case NVB:                                                                                        \
     if (x_is_float)                                                                                \
@@ -379,26 +400,35 @@ hipError_t launch_matvec(const KArgs& a, const void* x, int x_is_float, const do
     else                                                                                           \
       hipLaunchKernelGGL((k_matvec<double, 2, NVB>), dim3(grid), dim3(KT), 0, s, a, (const double*)x, b, y); \
     break;
-    switch (bk) {
-      MV(1) MV(2) MV(4) MV(8) MV(16) MV(32) MV(64)
-      default:
-        return hipErrorInvalidValue;
-    }
-#undef MV
+  switch (bk) {
+    MV(1) MV(2) MV(4) MV(8) MV(16) MV(32) MV(64)
+    default:
+      return hipErrorInvalidValue;
   }
+#undef MV
+  hipLaunchKernelGGL((k_finish<2>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, a.nv, 0, 0,
+                     rtol, nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_cgs(const KArgs& a, const double* w, double* vout, int j, int stop_iter,
-                      hipStream_t s) {
+                      hipStream_t s, int passes, double rtol, GSummary* host, int seq) {
   const int grid = stream_grid(a.n);
   const int bk = nv_bucket(a.nv);
+  if ((passes & 2) && vout == nullptr) return hipErrorInvalidValue;
   switch (bk) {
-#define CG(NVB)                                                                           \
-  case NVB:                                                                               \
-    hipLaunchKernelGGL((k_cgs_pass1<NVB>), dim3(grid), dim3(KT), 0, s, a, w);             \
-    hipLaunchKernelGGL((k_cgs_pass2<NVB>), dim3(grid), dim3(KT), 0, s, a, w, vout, j,    \
-                       stop_iter);                                                        \
+#define CG(NVB)                                                                            \
+  case NVB:                                                                                \
+    if (passes & 1) {                                                                      \
+      hipLaunchKernelGGL((k_cgs_pass1<NVB>), dim3(grid), dim3(KT), 0, s, a, w);            \
+      hipLaunchKernelGGL((k_finish<3>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid,   \
+                         a.nv, j, stop_iter, rtol, nullptr, 0);                            \
+    }                                                                                      \
+    if (passes & 2) {                                                                      \
+      hipLaunchKernelGGL((k_cgs_pass2<NVB>), dim3(grid), dim3(KT), 0, s, a, w, vout);      \
+      hipLaunchKernelGGL((k_finish<4>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid,   \
+                         a.nv, j, stop_iter, rtol, host, seq);                             \
+    }                                                                                      \
     break;
     CG(1) CG(2) CG(4) CG(8) CG(16) CG(32) CG(64)
 #undef CG
@@ -409,13 +439,14 @@ hipError_t launch_cgs(const KArgs& a, const double* w, double* vout, int j, int 
 }
 
 hipError_t launch_finish_update(GState* st, const void* Z, int z_is_float, long long zstride,
-                                double* x, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_finish, dim3(1), dim3(64), 0, s, st);
+                                double* x, long long n, int x_zero, GSummary* host, int seq,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_finish, dim3(1), dim3(64), 0, s, st, host, seq);
   const int grid = stream_grid(n);
   if (z_is_float)
-    hipLaunchKernelGGL((k_update<float>), dim3(grid), dim3(KT), 0, s, st, (const float*)Z, zstride, x, n);
+    hipLaunchKernelGGL((k_update<float>), dim3(grid), dim3(KT), 0, s, st, (const float*)Z, zstride, x, n, x_zero);
   else
-    hipLaunchKernelGGL((k_update<double>), dim3(grid), dim3(KT), 0, s, st, (const double*)Z, zstride, x, n);
+    hipLaunchKernelGGL((k_update<double>), dim3(grid), dim3(KT), 0, s, st, (const double*)Z, zstride, x, n, x_zero);
   return hipGetLastError();
 }
 

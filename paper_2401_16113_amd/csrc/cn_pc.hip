@@ -50,13 +50,26 @@ __global__ __launch_bounds__((PcCfg<R, LOG2N>::T)) void k_pc_forward(
     if (b < ncols) val = (R)(c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]));
     co[tid] = val;
   }
-  // step (a): alpha-weighted tile, columns (2s, 2s+1) packed as one complex sequence
+  // step (a): alpha-weighted tile, columns (2s, 2s+1) packed as one complex
+  // sequence.  All of a thread's loads are issued before any is consumed.
   R* ldsr = reinterpret_cast<R*>(lds);
-  for (int e = tid; e < N * B; e += T) {
-    const int k = e / B, b = e % B;
-    double x = 0.0;
-    if (b < ncols) x = v[(size_t)k * nx + i0 + b] * (wfw[k] * sc);
-    ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] = (R)x;
+  {
+    constexpr int LPT = (N * B + T - 1) / T;
+    double xv[LPT];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + q * T;
+      const int k = e / B, b = e % B;
+      xv[q] = ((N * B) % T == 0 || e < N * B) && b < ncols ? v[(size_t)k * nx + i0 + b] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + q * T;
+      if ((N * B) % T == 0 || e < N * B) {
+        const int k = e / B, b = e % B;
+        ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] = (R)(xv[q] * (wfw[k] * sc));
+      }
+    }
   }
   __syncthreads();
   fft_run<R, LOG2N, NSEQ, T, false, Cfg::MAXLOG, 0>(lds, tw);
@@ -127,9 +140,13 @@ __global__ __launch_bounds__((PcCfg<R, LOG2N>::T)) void k_pc_forward(
   }
   __syncthreads();
   Cx<R>* img = spec + (size_t)p * NSEQ * N;
-  for (int e = tid; e < NSEQ * N; e += T) {
-    const int s = e / N, k = e % N;
-    img[e] = lds[lidx<N>(s, k)];
+  {
+    constexpr int SPT = (NSEQ * N + T - 1) / T;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = tid + q * T;
+      if ((NSEQ * N) % T == 0 || e < NSEQ * N) img[e] = lds[lidx<N>(e / N, e % N)];
+    }
   }
 }
 
@@ -161,9 +178,19 @@ __global__ __launch_bounds__((PcCfg<R, LOG2N>::T)) void k_pc_inverse(
     co[tid] = val;
   }
   const Cx<R>* img = spec + (size_t)p * NSEQ * N;
-  for (int e = tid; e < NSEQ * N; e += T) {
-    const int s = e / N, k = e % N;
-    lds[lidx<N>(s, k)] = img[e];
+  {
+    constexpr int SPT = (NSEQ * N + T - 1) / T;
+    Cx<R> iv[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = tid + q * T;
+      if ((NSEQ * N) % T == 0 || e < NSEQ * N) iv[q] = img[e];
+    }
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = tid + q * T;
+      if ((NSEQ * N) % T == 0 || e < NSEQ * N) lds[lidx<N>(e / N, e % N)] = iv[q];
+    }
   }
   __syncthreads();
   const bool has_sep = p < P - 1;
@@ -226,11 +253,16 @@ __global__ __launch_bounds__((PcCfg<R, LOG2N>::T)) void k_pc_inverse(
   __syncthreads();
   fft_run<R, LOG2N, NSEQ, T, true, Cfg::MAXLOG, 0>(lds, tw);
   const R* ldsr = reinterpret_cast<const R*>(lds);
-  for (int e = tid; e < N * B; e += T) {
-    const int k = e / B, b = e % B;
-    if (b < ncols) {
-      const double val = (double)ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] * winv[k];
-      z[(size_t)k * nx + i0 + b] = (TZ)val;
+  {
+    constexpr int LPT = (N * B + T - 1) / T;
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + q * T;
+      const int k = e / B, b = e % B;
+      if (((N * B) % T == 0 || e < N * B) && b < ncols) {
+        const double val = (double)ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] * winv[k];
+        z[(size_t)k * nx + i0 + b] = (TZ)val;
+      }
     }
   }
 }
