@@ -19,6 +19,7 @@ timing of each kernel of one inner iteration, algorithmic bytes per launch
 against the 8 TB/s HBM peak) and the CPU oracle timed on the host.
 """
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -31,6 +32,39 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 RTOL = 1e-8
 M = 30
+# sources whose change invalidates stored hardware-counter traffic figures
+KERNEL_SOURCES = ["paper_2401_16113_amd/csrc/cn_device.hpp",
+                  "paper_2401_16113_amd/csrc/cn_pc_kernels.hpp",
+                  "paper_2401_16113_amd/csrc/cn_pc.hip",
+                  "paper_2401_16113_amd/csrc/cn_krylov.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_localvol_4095x1024_fp32pc.txt")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a copy of known size), or None when the
+    summary is missing or the kernel sources changed since it was taken."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_hash") != kernel_source_hash():
+            return None
+        v = kv.get(f"traffic_bytes[{kernel}]")
+        return float(v) if v is not None else None
+    except OSError:
+        return None
 
 
 def log(msg):
@@ -58,6 +92,7 @@ def run_variant(B, W, inst, prec, steps, warmup, dev, torch):
     ms = el / steps * 1e3
     prof = s.profile_step(j=min(1, last.iters - 1), reps=20)
     out = {
+        "pc_variant": s.query(),
         "ms_per_solve": ms,
         "unknowns_per_s": inst.n / (ms * 1e-3),
         "iters": last.iters,
@@ -106,6 +141,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--alpha", type=float, default=0.01)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run 256 MiB device copies (hardware-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -130,7 +167,8 @@ def main():
     dom = max(prof, key=lambda k: prof[k]["ms"])
     ach = prof[dom]["bytes"] / (prof[dom]["ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic(dom),
             "avg_launch_us": round(prof[dom]["ms"] * 1e3, 2),
             "algorithmic_bytes": prof[dom]["bytes"]}
     out = {
@@ -152,6 +190,14 @@ def main():
         "variants": variants,
         "roofline": roof,
     }
+    if args.calibrate_copy:
+        log("[bench] calibration: 5 device copies of 256 MiB")
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 8
     if not args.no_cpu_baseline:
         log("[bench] cpu_baseline: oracle solve on the host")
         out["cpu_baseline"] = cpu_baseline(inst, {"plain_fp64": xs["fp64"], "fp32_pc": xs["fp32"]})

@@ -149,9 +149,9 @@ cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
  * order: 0 pc_forward (steps (a) + local (b)), 1 pc_reduced (interface
  * systems of (b)), 2 pc_inverse (correction + step (c)), 3 matvec fused with
  * the first Gram-Schmidt dots, 4 second Gram-Schmidt dots, 5 basis update +
- * norm + Givens; the three Krylov entries include their one-workgroup
- * finishing reduction kernel.  ms and bytes: host arrays of 6 doubles.
- * Synchronises. */
+ * norm (each Krylov entry is the streaming kernel alone, without the
+ * one-workgroup kernel that finishes its reduction).  ms and bytes: host
+ * arrays of 6 doubles.  Synchronises. */
 #define CN_PROFILE_KERNELS 6
 cn_status cn_profile_step(cn_aao *h, int32_t j, int32_t reps, double *ms, double *bytes);
 

@@ -6,8 +6,12 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -17,6 +21,11 @@
 using namespace cn;
 
 static thread_local std::string g_err;
+
+// Process-wide cache of the autotuned transform variant per
+// (precision, log2 N_t, N_x): later handles of the same shape skip tuning.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tune;
 
 static cn_status fail(cn_status s, const std::string& msg) {
   g_err = msg;
@@ -220,21 +229,54 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
   pl.prec = h->prec;
   pl.alpha = h->alpha;
   pl.dbar = dbar;
-  pc_config(pl.prec, pl.log2n, &pl.B, &pl.T);
-  pl.P = (nx + pl.B - 1) / pl.B;
-  pl.NS = pl.P - 1;
   const size_t rsz = pl.prec ? sizeof(float) : sizeof(double);
-  const int nsr = pl.NS > 0 ? pl.NS : 1;
+  // compiled (B, T) variants of the transform kernels for this N_t
+  std::vector<int> cands;
+  for (int ci = 0; ci < kNumCand; ++ci) {
+    int B = 0, T = 0;
+    if (pc_candidate(pl.prec, pl.log2n, ci, &B, &T)) cands.push_back(ci);
+  }
+  {
+    // CN_PC_TILE="B,T" forces a variant; CN_AUTOTUNE=0 keeps the default
+    const char* force = getenv("CN_PC_TILE");
+    const char* at = getenv("CN_AUTOTUNE");
+    int fb = 0, ft = 0;
+    if (force != nullptr && sscanf(force, "%d,%d", &fb, &ft) == 2) {
+      std::vector<int> keep;
+      for (int ci : cands) {
+        int B = 0, T = 0;
+        pc_candidate(pl.prec, pl.log2n, ci, &B, &T);
+        if (B == fb && T == ft) keep.push_back(ci);
+      }
+      if (keep.empty()) {
+        fail(CN_EINVAL, std::string("CN_PC_TILE=") + force + " is not a compiled variant");
+        return bail(CN_EINVAL);
+      }
+      cands = keep;
+    } else if (at != nullptr && at[0] == '0') {
+      cands.assign(1, 0);
+    }
+  }
+  // buffers sized for the most demanding candidate
+  size_t spec_elems = 0, nsep_max = 1, ptile_max = 1;
+  for (int ci : cands) {
+    int B = 0, T = 0;
+    pc_candidate(pl.prec, pl.log2n, ci, &B, &T);
+    const size_t P = (size_t)(nx + B - 1) / B;
+    spec_elems = std::max(spec_elems, P * B * (size_t)nt);
+    ptile_max = std::max(ptile_max, P);
+    nsep_max = std::max(nsep_max, P > 1 ? P - 1 : (size_t)1);
+  }
 
   // workspace size check against free memory
   size_t need = 0;
   need += (size_t)(h->m_max + 1) * h->npad * sizeof(double);         // V
   need += (size_t)h->m_max * h->npad * rsz;                           // Z
   need += (size_t)h->npad * sizeof(double);                           // w
-  need += (size_t)pl.P * pl.B * nt * rsz;                             // spectrum tiles
-  need += (size_t)pl.F * pl.P * 3 * 2 * rsz;                          // interface values
-  need += (size_t)pl.F * nsr * 2 * rsz + (size_t)pl.F * nsr * 4 * sizeof(Cx<double>);
-  need += (size_t)pl.F * pl.P * 4 * sizeof(Cx<double>);               // set-up spikes
+  need += spec_elems * rsz;                                           // spectrum tiles
+  need += (size_t)pl.F * ptile_max * 3 * 2 * rsz;                     // interface values
+  need += (size_t)pl.F * nsep_max * 2 * rsz + (size_t)pl.F * nsep_max * 4 * sizeof(Cx<double>);
+  need += (size_t)pl.F * ptile_max * 4 * sizeof(Cx<double>);          // set-up spikes
   size_t freeb = 0, totalb = 0;
   TRY(hipMemGetInfo(&freeb, &totalb));
   if (need + (64u << 20) > freeb) {
@@ -311,45 +353,109 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
   TRY(hipMemcpy(pl.mu, mu.data(), pl.F * sizeof(Cx<double>), hipMemcpyHostToDevice));
   TRY(hipMemcpy(pl.il2, il2.data(), pl.F * sizeof(Cx<double>), hipMemcpyHostToDevice));
 
-  // -- preconditioner workspace and interface factorisation -------------------------
-  TRY(dalloc(h, &pl.spec, (size_t)pl.P * pl.B * nt * rsz));
-  TRY(dalloc(h, &pl.iface, (size_t)pl.F * pl.P * 3 * 2 * rsz));
-  TRY(dalloc(h, &pl.sep, (size_t)pl.F * nsr * 2 * rsz));
-  TRY(dalloc(h, &pl.red_a, (size_t)pl.F * nsr * sizeof(Cx<double>)));
-  TRY(dalloc(h, &pl.red_ap, (size_t)pl.F * nsr * sizeof(Cx<double>)));
-  TRY(dalloc(h, &pl.red_inv, (size_t)pl.F * nsr * sizeof(Cx<double>)));
-  TRY(dalloc(h, &pl.red_tmp, (size_t)pl.F * nsr * sizeof(Cx<double>)));
+  // -- GMRES basis (also the autotuner's scratch) ---------------------------------------
+  TRY(dalloc(h, &h->V, (size_t)(h->m_max + 1) * h->npad * sizeof(double)));
+  TRY(dalloc(h, &h->Z, (size_t)h->m_max * h->npad * rsz));
+  TRY(dalloc(h, &h->w, (size_t)h->npad * sizeof(double)));
+
+  // -- preconditioner workspace, interface factorisation, variant choice -------------
+  TRY(dalloc(h, &pl.spec, spec_elems * rsz));
+  TRY(dalloc(h, &pl.iface, (size_t)pl.F * ptile_max * 3 * 2 * rsz));
+  TRY(dalloc(h, &pl.sep, (size_t)pl.F * nsep_max * 2 * rsz));
+  TRY(dalloc(h, &pl.red_a, (size_t)pl.F * nsep_max * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.red_ap, (size_t)pl.F * nsep_max * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.red_inv, (size_t)pl.F * nsep_max * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.red_tmp, (size_t)pl.F * nsep_max * sizeof(Cx<double>)));
   {
     Cx<double>* spk = nullptr;
     int* err = nullptr;
-    TRY(hipMalloc((void**)&spk, (size_t)pl.F * pl.P * 4 * sizeof(Cx<double>)));
+    TRY(hipMalloc((void**)&spk, (size_t)pl.F * ptile_max * 4 * sizeof(Cx<double>)));
     if (hipMalloc((void**)&err, sizeof(int)) != hipSuccess) {
       (void)hipFree(spk);
       fail(CN_ENOMEM, "set-up flag");
       return bail(CN_ENOMEM);
     }
-    hipError_t e = hipMemsetAsync(err, 0, sizeof(int), h->stream);
-    if (e == hipSuccess) e = pc_setup(pl, spk, err, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    int herr = 0;
-    if (e == hipSuccess) e = hipMemcpy(&herr, err, sizeof(int), hipMemcpyDeviceToHost);
-    (void)hipFree(spk);
-    (void)hipFree(err);
+    auto free_tmp = [&]() {
+      (void)hipStreamSynchronize(h->stream);
+      (void)hipFree(spk);
+      (void)hipFree(err);
+    };
+    // set up the interface factors of candidate ci (singular -> *singular = 1)
+    auto setup = [&](int ci, int* singular) -> hipError_t {
+      int B = 0, T = 0;
+      pc_candidate(pl.prec, pl.log2n, ci, &B, &T);
+      pl.cand = ci;
+      pl.B = B;
+      pl.T = T;
+      pl.P = (nx + B - 1) / B;
+      pl.NS = pl.P - 1;
+      hipError_t e = hipMemsetAsync(err, 0, sizeof(int), h->stream);
+      if (e == hipSuccess) e = pc_setup(pl, spk, err, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      int herr = 0;
+      if (e == hipSuccess) e = hipMemcpy(&herr, err, sizeof(int), hipMemcpyDeviceToHost);
+      *singular = herr != 0;
+      return e;
+    };
+    int best = -1;
+    const auto key = std::make_tuple(pl.prec, pl.log2n, nx);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
+        best = it->second;
+    }
+    if (best < 0 && cands.size() == 1) best = cands[0];
+    hipError_t e = hipSuccess;
+    if (best < 0) {
+      // time three applies of every candidate on this problem's shape
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      e = hipEventCreate(&e0);
+      if (e == hipSuccess) e = hipEventCreate(&e1);
+      if (e == hipSuccess) e = hipMemsetAsync(h->V, 0, (size_t)h->n * sizeof(double), h->stream);
+      float best_ms = 1e30f;
+      for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
+        const int ci = cands[c];
+        int sing = 0;
+        e = setup(ci, &sing);
+        if (e != hipSuccess || sing) continue;
+        for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+          if (r == 1) e = hipEventRecord(e0, h->stream);
+          if (e == hipSuccess) e = pc_forward(pl, h->V, nullptr, nullptr, h->stream);
+          if (e == hipSuccess) e = pc_reduced(pl, nullptr, h->stream);
+          if (e == hipSuccess) e = pc_inverse(pl, h->Z, pl.prec, nullptr, h->stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best_ms) {
+          best_ms = ms;
+          best = ci;
+        }
+      }
+      if (e0 != nullptr) (void)hipEventDestroy(e0);
+      if (e1 != nullptr) (void)hipEventDestroy(e1);
+      if (e == hipSuccess && best >= 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = best;
+      }
+    }
+    int sing = 1;
+    if (e == hipSuccess && best >= 0) e = setup(best, &sing);
+    free_tmp();
     if (e != hipSuccess) {
       fail(CN_EHIP, std::string("preconditioner set-up: ") + hipGetErrorString(e));
       return bail(CN_EHIP);
     }
-    if (herr != 0) {
+    if (sing) {
       fail(CN_ESINGULAR, "a shifted system of step (b) is singular (alpha = " +
                              std::to_string(h->alpha) + ")");
       return bail(CN_ESINGULAR);
     }
   }
 
-  // -- GMRES workspace ----------------------------------------------------------------
-  TRY(dalloc(h, &h->V, (size_t)(h->m_max + 1) * h->npad * sizeof(double)));
-  TRY(dalloc(h, &h->Z, (size_t)h->m_max * h->npad * rsz));
-  TRY(dalloc(h, &h->w, (size_t)h->npad * sizeof(double)));
+  // -- remaining GMRES workspace -------------------------------------------------------
   {
     const int rows = matvec_rows(nx, nt);
     const long long mgrid = (long long)((nx + 255) / 256) * ((nt + rows - 1) / rows);
@@ -577,11 +683,12 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
         case 0: e = pc_forward(pl, vj, &st->vscale[j], done, s); break;
         case 1: e = pc_reduced(pl, done, s); break;
         case 2: e = pc_inverse(pl, zj, zf, done, s); break;
-        case 3: e = launch_matvec(a, zj, zf, nullptr, h->w, 2, s); break;
-        case 4: e = launch_cgs(a, h->w, nullptr, j, -1, s, 1, -1.0, nullptr, 0); break;
-        // rtol < 0 and an unreachable restart length keep the stop flag clear
+        // the three streaming Krylov kernels alone (their one-workgroup
+        // finishing reductions are left out, so each entry is one kernel)
+        case 3: e = launch_matvec(a, zj, zf, nullptr, h->w, 2, s, 0.0, nullptr, 0, false); break;
+        case 4: e = launch_cgs(a, h->w, nullptr, j, -1, s, 1, 0.0, nullptr, 0, false); break;
         case 5: e = launch_cgs(a, h->w, h->V + (size_t)(j + 1) * h->npad, j, 1 << 30, s, 2,
-                               -1.0, nullptr, 0); break;
+                               0.0, nullptr, 0, false); break;
       }
     }
     if (e == hipSuccess) e = hipEventRecord(ev[1], s);

@@ -115,21 +115,49 @@ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int clog2(int v) { return v <= 1 ? 0 : 1 + clog2(v / 2); }
 
+// Default tile width B (columns, even) and workgroup size T of the transform
+// kernels: the widest tile whose image fits 128 KB of LDS, ~16 complex
+// elements per thread.
 template <typename R, int LOG2N>
+struct PcDefault {
+  static constexpr int N = 1 << LOG2N;
+  static constexpr int B = cmax(2, cmin(16, (128 * 1024) / (N * (int)sizeof(R))));
+  static constexpr int T = cmax(64, cmin(1024, (B / 2) * N / 16));
+};
+
+template <typename R, int LOG2N, int B_, int T_>
 struct PcCfg {
   static constexpr int N = 1 << LOG2N;
-  static constexpr int BUDGET = 128 * 1024;  // bytes of tile image in LDS
-  static constexpr int Braw = BUDGET / (N * (int)sizeof(R));
-  static constexpr int B = cmax(2, cmin(16, Braw));      // tile columns (even)
+  static constexpr int B = B_;                             // tile columns (even)
   static constexpr int NSEQ = B / 2;                       // complex sequences
   static constexpr int ELEMS = NSEQ * N;                   // complex elements
-  static constexpr int T = cmax(64, cmin(1024, ELEMS / 16));
+  static constexpr int T = T_;
   static constexpr int E = cmax(1, ELEMS / T);             // elements per thread
   static constexpr int MAXLOG = cmax(1, cmin(4, clog2(E)));  // largest radix 2^MAXLOG
   // padded LDS layout: one spare complex slot every 16, plus one per sequence
   static constexpr int SSTRIDE = N + N / 16 + 1;
   static constexpr int LDS_ELEMS = NSEQ * SSTRIDE;
+  static constexpr int LDS_BYTES = LDS_ELEMS * 2 * (int)sizeof(R) + 3 * B * (int)sizeof(R);
   static constexpr int TASKS = N >= 2 ? N / 2 : 1;          // step-(b) tasks
+};
+
+// Candidate (B, T) variants the create-time autotuner times; index 0 is the
+// default.  A candidate is compiled for 64 <= N_t <= 4096 when its tile
+// image fits the LDS, every thread owns at least one element and the
+// tile-solve registers fit the VGPR budget of its workgroup size.
+constexpr int kNumCand = 9;
+constexpr int kCandB[kNumCand] = {0, 16, 16, 16, 8, 8, 8, 4, 4};
+constexpr int kCandT[kNumCand] = {0, 256, 512, 1024, 256, 512, 1024, 256, 512};
+
+template <typename R, int LOG2N, int CI>
+struct PcCand {
+  static constexpr int B = CI == 0 ? PcDefault<R, LOG2N>::B : kCandB[CI];
+  static constexpr int T = CI == 0 ? PcDefault<R, LOG2N>::T : kCandT[CI];
+  using Cfg = PcCfg<R, LOG2N, B, T>;
+  static constexpr bool dup = CI != 0 && B == PcDefault<R, LOG2N>::B && T == PcDefault<R, LOG2N>::T;
+  static constexpr bool ok =
+      CI == 0 || (!dup && LOG2N >= 6 && LOG2N <= 12 && Cfg::LDS_BYTES <= 150 * 1024 &&
+                  Cfg::ELEMS >= T && (T < 1024 || B * (int)sizeof(R) <= 64));
 };
 
 template <int N>

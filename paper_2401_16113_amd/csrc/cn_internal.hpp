@@ -18,6 +18,7 @@ struct PcPlan {
   int nx = 0, nt = 0, log2n = 0, F = 0;  // F = nt/2 + 1 frequency lines kept
   int prec = 0;                           // 0: float64, 1: float32
   int B = 0, P = 0, NS = 0, T = 0;        // tile cols, tiles, separators, threads
+  int cand = 0;                           // compiled (B, T) variant (0 = default)
   double alpha = 0, dbar = 1;
   // device tables
   double *lo = nullptr, *di = nullptr, *up = nullptr;   // tau*A rows
@@ -66,7 +67,8 @@ hipError_t pc_forward(const PcPlan& pl, const double* v, const double* scale_dev
 hipError_t pc_reduced(const PcPlan& pl, const int* done, hipStream_t s);
 hipError_t pc_inverse(const PcPlan& pl, void* z, int z_is_float, const int* done,
                       hipStream_t s);
-void pc_config(int prec, int log2n, int* B, int* T);
+// (B, T) of compiled candidate `ci`; false if that candidate is not compiled
+bool pc_candidate(int prec, int log2n, int ci, int* B, int* T);
 
 // Krylov launchers (cn_krylov.hip)
 struct KArgs {
@@ -89,11 +91,11 @@ int matvec_rows(int nx, int nt);
 // `host`); 2: y = M x + first Gram-Schmidt dots
 hipError_t launch_matvec(const KArgs& a, const void* x, int x_is_float, const double* b,
                          double* y, int mode, hipStream_t s, double rtol = 0.0,
-                         GSummary* host = nullptr, int seq = 0);
+                         GSummary* host = nullptr, int seq = 0, bool finish = true);
 // passes: 1 = second Gram-Schmidt dots, 2 = update + norm + Givens, 3 = both
 hipError_t launch_cgs(const KArgs& a, const double* w, double* vout, int j, int stop_iter,
                       hipStream_t s, int passes = 3, double rtol = 0.0,
-                      GSummary* host = nullptr, int seq = 0);
+                      GSummary* host = nullptr, int seq = 0, bool finish = true);
 hipError_t launch_finish_update(GState* st, const void* Z, int z_is_float, long long zstride,
                                 double* x, long long n, int x_zero, GSummary* host, int seq,
                                 hipStream_t s);

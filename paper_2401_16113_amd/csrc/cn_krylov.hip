@@ -377,7 +377,7 @@ int stream_grid(long long n) {
 
 hipError_t launch_matvec(const KArgs& a, const void* x, int x_is_float, const double* b,
                          double* y, int mode, hipStream_t s, double rtol, GSummary* host,
-                         int seq) {
+                         int seq, bool finish) {
   const int grid = ((a.nx + KT - 1) / KT) * ((a.nt + a.rows - 1) / a.rows);
   if (mode == 0) {
     if (x_is_float)
@@ -406,13 +406,15 @@ hipError_t launch_matvec(const KArgs& a, const void* x, int x_is_float, const do
       return hipErrorInvalidValue;
   }
 #undef MV
-  hipLaunchKernelGGL((k_finish<2>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, a.nv, 0, 0,
-                     rtol, nullptr, 0);
+  if (finish)
+    hipLaunchKernelGGL((k_finish<2>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, a.nv, 0,
+                       0, rtol, nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_cgs(const KArgs& a, const double* w, double* vout, int j, int stop_iter,
-                      hipStream_t s, int passes, double rtol, GSummary* host, int seq) {
+                      hipStream_t s, int passes, double rtol, GSummary* host, int seq,
+                      bool finish) {
   const int grid = stream_grid(a.n);
   const int bk = nv_bucket(a.nv);
   if ((passes & 2) && vout == nullptr) return hipErrorInvalidValue;
@@ -421,13 +423,15 @@ hipError_t launch_cgs(const KArgs& a, const double* w, double* vout, int j, int 
   case NVB:                                                                                \
     if (passes & 1) {                                                                      \
       hipLaunchKernelGGL((k_cgs_pass1<NVB>), dim3(grid), dim3(KT), 0, s, a, w);            \
-      hipLaunchKernelGGL((k_finish<3>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid,   \
-                         a.nv, j, stop_iter, rtol, nullptr, 0);                            \
+      if (finish)                                                                          \
+        hipLaunchKernelGGL((k_finish<3>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, \
+                           a.nv, j, stop_iter, rtol, nullptr, 0);                          \
     }                                                                                      \
     if (passes & 2) {                                                                      \
       hipLaunchKernelGGL((k_cgs_pass2<NVB>), dim3(grid), dim3(KT), 0, s, a, w, vout);      \
-      hipLaunchKernelGGL((k_finish<4>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid,   \
-                         a.nv, j, stop_iter, rtol, host, seq);                             \
+      if (finish)                                                                          \
+        hipLaunchKernelGGL((k_finish<4>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, \
+                           a.nv, j, stop_iter, rtol, host, seq);                           \
     }                                                                                      \
     break;
     CG(1) CG(2) CG(4) CG(8) CG(16) CG(32) CG(64)

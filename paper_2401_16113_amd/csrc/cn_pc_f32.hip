@@ -1,0 +1,18 @@
+// float instantiation of the preconditioner transform kernels.
+#include "cn_pc_kernels.hpp"
+
+namespace cn {
+
+#define CN_FWD_CASE_f32(L) \
+  case L:                 \
+    return fwd_cand<float, L>(pl.cand, pl, v, scale, done, s);
+#define CN_INV_CASE_f32(L) \
+  case L:                 \
+    return inv_cand<float, L>(pl.cand, pl, z, zf, done, s);
+#define CN_INFO_CASE_f32(L) \
+  case L:                  \
+    return cand_info<float, L>(ci, B, T);
+
+CN_DEFINE_PC_PRECISION(float, f32)
+
+}  // namespace cn

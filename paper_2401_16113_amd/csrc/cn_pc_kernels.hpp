@@ -1,0 +1,371 @@
+// Transform kernels of the alpha-circulant preconditioner (included by the
+// per-precision translation units cn_pc_f64.hip and cn_pc_f32.hip).
+//
+//  K1 (k_pc_forward): one workgroup per tile of B spatial columns.  Loads the
+//     B x N_t tile, applies the alpha weights Lambda_alpha (step (a)), runs a
+//     length-N_t complex Stockham FFT in LDS on pairs of real columns (two
+//     real transforms per complex one; only the N_t/2+1 non-redundant modes
+//     are used, Remark 1), then for every frequency j solves the shifted
+//     system (lambda_{1,j} I - lambda_{2,j} A~) restricted to the tile's
+//     interior columns (step (b), local part) and writes the tile image plus
+//     three interface values per (j, tile).
+//  K3 (k_pc_inverse): per tile, adds the separator contributions to the local
+//     solution, runs the inverse FFT, multiplies by Lambda_alpha^{-1}/N_t
+//     (step (c)) and writes z.
+#pragma once
+#include <type_traits>
+
+#include "cn_internal.hpp"
+
+namespace cn {
+
+// ---------------------------------------------------------------------------
+// K1
+// ---------------------------------------------------------------------------
+template <typename R, int LOG2N, int BB, int TT>
+__global__ __launch_bounds__(TT) void k_pc_forward(
+    const double* __restrict__ v, const double* __restrict__ scale,
+    const int* __restrict__ done, const double* __restrict__ lo,
+    const double* __restrict__ di, const double* __restrict__ up,
+    const double* __restrict__ wfw, const Cx<R>* __restrict__ tw,
+    const Cx<double>* __restrict__ mu, const Cx<double>* __restrict__ il2,
+    Cx<R>* __restrict__ spec, Cx<R>* __restrict__ iface, int nx, int P, int nwg_pad) {
+  using Cfg = PcCfg<R, LOG2N, BB, TT>;
+  constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
+  __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
+  __shared__ R co[3 * B];
+  if (done != nullptr && *done) return;
+  const int p = xcd_tile(blockIdx.x, nwg_pad);
+  if (p >= P) return;
+  const int tid = threadIdx.x;
+  const int i0 = p * B;
+  const int ncols = min(B, nx - i0);
+  const double sc = scale != nullptr ? *scale : 1.0;
+  if (tid < 3 * B) {
+    const int b = tid / 3, c = tid % 3;
+    R val = R(0);
+    if (b < ncols) val = (R)(c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]));
+    co[tid] = val;
+  }
+  // step (a): alpha-weighted tile, columns (2s, 2s+1) packed as one complex
+  // sequence.  All of a thread's loads are issued before any is consumed.
+  R* ldsr = reinterpret_cast<R*>(lds);
+  {
+    constexpr int LPT = (N * B + T - 1) / T;
+    double xv[LPT];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + q * T;
+      const int k = e / B, b = e % B;
+      xv[q] = ((N * B) % T == 0 || e < N * B) && b < ncols ? v[(size_t)k * nx + i0 + b] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + q * T;
+      if ((N * B) % T == 0 || e < N * B) {
+        const int k = e / B, b = e % B;
+        ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] = (R)(xv[q] * (wfw[k] * sc));
+      }
+    }
+  }
+  __syncthreads();
+  fft_run<R, LOG2N, NSEQ, T, false, Cfg::MAXLOG, 0>(lds, tw);
+
+  // step (b), tile-local part
+  const bool has_sep = p < P - 1;
+  const int nb = has_sep ? B - 1 : ncols;
+  Cx<R>* ifc = iface + (size_t)p * 3;
+  for (int t = tid; t < Cfg::TASKS; t += T) {
+    if (t == 0) {
+      // j = 0 and j = N/2: real modes, real shifts
+      const int nreal = N >= 2 ? 2 : 1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h >= nreal) break;
+        const int j = h == 0 ? 0 : N / 2;
+        const R m = (R)mu[j].x, s2 = (R)il2[j].x;
+        R d[B];
+#pragma unroll
+        for (int c = 0; c < NSEQ; ++c) {
+          const Cx<R> z = lds[lidx<N>(c, j)];
+          d[2 * c] = z.x * s2;
+          d[2 * c + 1] = z.y * s2;
+        }
+        const R sepv = d[B - 1];
+        tile_solve<R, R, B>(d, m, co, nb);
+        R ylast = d[0];
+#pragma unroll
+        for (int b = 1; b < B; ++b)
+          if (b == nb - 1) ylast = d[b];
+#pragma unroll
+        for (int c = 0; c < NSEQ; ++c) lds[lidx<N>(c, j)] = Cx<R>{d[2 * c], d[2 * c + 1]};
+        Cx<R>* f = ifc + (size_t)j * P * 3;
+        f[0] = Cx<R>{has_sep ? sepv : R(0), R(0)};
+        f[1] = Cx<R>{ylast, R(0)};
+        f[2] = Cx<R>{d[0], R(0)};
+      }
+    } else {
+      const int j = t;
+      const Cx<double> md = mu[j], sd = il2[j];
+      const Cx<R> m{(R)md.x, (R)md.y}, s2{(R)sd.x, (R)sd.y};
+      Cx<R> d[B];
+#pragma unroll
+      for (int c = 0; c < NSEQ; ++c) {
+        const Cx<R> z = lds[lidx<N>(c, j)];
+        const Cx<R> zc = conj(lds[lidx<N>(c, N - j)]);
+        const Cx<R> sum = z + zc, dif = z - zc;
+        // X_{2c} = (Z_j + conj Z_{N-j})/2, X_{2c+1} = (Z_j - conj Z_{N-j})/(2i)
+        d[2 * c] = (R(0.5) * sum) * s2;
+        d[2 * c + 1] = Cx<R>{R(0.5) * dif.y, R(-0.5) * dif.x} * s2;
+      }
+      const Cx<R> sepv = d[B - 1];
+      tile_solve<R, Cx<R>, B>(d, m, co, nb);
+      Cx<R> ylast = d[0];
+#pragma unroll
+      for (int b = 1; b < B; ++b)
+        if (b == nb - 1) ylast = d[b];
+#pragma unroll
+      for (int c = 0; c < NSEQ; ++c) {
+        lds[lidx<N>(c, j)] = d[2 * c];
+        lds[lidx<N>(c, N - j)] = d[2 * c + 1];
+      }
+      Cx<R>* f = ifc + (size_t)j * P * 3;
+      f[0] = has_sep ? sepv : Cx<R>{R(0), R(0)};
+      f[1] = ylast;
+      f[2] = d[0];
+    }
+  }
+  __syncthreads();
+  Cx<R>* img = spec + (size_t)p * NSEQ * N;
+  {
+    constexpr int SPT = (NSEQ * N + T - 1) / T;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = tid + q * T;
+      if ((NSEQ * N) % T == 0 || e < NSEQ * N) img[e] = lds[lidx<N>(e / N, e % N)];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K3
+// ---------------------------------------------------------------------------
+template <typename R, int LOG2N, int BB, int TT, typename TZ>
+__global__ __launch_bounds__(TT) void k_pc_inverse(
+    const Cx<R>* __restrict__ spec, const Cx<R>* __restrict__ sep,
+    const int* __restrict__ done, const double* __restrict__ lo,
+    const double* __restrict__ di, const double* __restrict__ up,
+    const double* __restrict__ winv, const Cx<R>* __restrict__ tw,
+    const Cx<double>* __restrict__ mu, TZ* __restrict__ z, int nx, int P, int NS,
+    int nwg_pad) {
+  using Cfg = PcCfg<R, LOG2N, BB, TT>;
+  constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
+  __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
+  __shared__ R co[3 * B];
+  if (done != nullptr && *done) return;
+  const int p = xcd_tile(blockIdx.x, nwg_pad);
+  if (p >= P) return;
+  const int tid = threadIdx.x;
+  const int i0 = p * B;
+  const int ncols = min(B, nx - i0);
+  if (tid < 3 * B) {
+    const int b = tid / 3, c = tid % 3;
+    R val = R(0);
+    if (b < ncols) val = (R)(c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]));
+    co[tid] = val;
+  }
+  const Cx<R>* img = spec + (size_t)p * NSEQ * N;
+  {
+    constexpr int SPT = (NSEQ * N + T - 1) / T;
+    Cx<R> iv[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = tid + q * T;
+      if ((NSEQ * N) % T == 0 || e < NSEQ * N) iv[q] = img[e];
+    }
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = tid + q * T;
+      if ((NSEQ * N) % T == 0 || e < NSEQ * N) lds[lidx<N>(e / N, e % N)] = iv[q];
+    }
+  }
+  __syncthreads();
+  const bool has_sep = p < P - 1;
+  const bool has_left = p > 0;
+  const int nb = has_sep ? B - 1 : ncols;
+  for (int t = tid; t < Cfg::TASKS; t += T) {
+    if (t == 0) {
+      const int nreal = N >= 2 ? 2 : 1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h >= nreal) break;
+        const int j = h == 0 ? 0 : N / 2;
+        const R m = (R)mu[j].x;
+        const R sl = has_left ? sep[(size_t)j * NS + p - 1].x : R(0);
+        const R sr = has_sep ? sep[(size_t)j * NS + p].x : R(0);
+        R d[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) d[b] = R(0);
+        d[0] = co[0] * sl;
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+          if (b == nb - 1) d[b] = d[b] + co[3 * b + 2] * sr;
+        tile_solve<R, R, B>(d, m, co, nb);
+#pragma unroll
+        for (int c = 0; c < NSEQ; ++c) {
+          const Cx<R> yv = lds[lidx<N>(c, j)];
+          R xa = yv.x + d[2 * c], xb = yv.y + d[2 * c + 1];
+          if (2 * c >= nb) xa = (2 * c == B - 1 && has_sep) ? sr : R(0);
+          if (2 * c + 1 >= nb) xb = (2 * c + 1 == B - 1 && has_sep) ? sr : R(0);
+          lds[lidx<N>(c, j)] = Cx<R>{xa, xb};
+        }
+      }
+    } else {
+      const int j = t;
+      const Cx<double> md = mu[j];
+      const Cx<R> m{(R)md.x, (R)md.y};
+      const Cx<R> zero{R(0), R(0)};
+      const Cx<R> sl = has_left ? sep[(size_t)j * NS + p - 1] : zero;
+      const Cx<R> sr = has_sep ? sep[(size_t)j * NS + p] : zero;
+      Cx<R> d[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) d[b] = zero;
+      d[0] = co[0] * sl;
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (b == nb - 1) d[b] = d[b] + co[3 * b + 2] * sr;
+      tile_solve<R, Cx<R>, B>(d, m, co, nb);
+#pragma unroll
+      for (int c = 0; c < NSEQ; ++c) {
+        Cx<R> xa = lds[lidx<N>(c, j)] + d[2 * c];
+        Cx<R> xb = lds[lidx<N>(c, N - j)] + d[2 * c + 1];
+        if (2 * c >= nb) xa = (2 * c == B - 1 && has_sep) ? sr : zero;
+        if (2 * c + 1 >= nb) xb = (2 * c + 1 == B - 1 && has_sep) ? sr : zero;
+        // Z'_j = X_{2c} + i X_{2c+1}; Z'_{N-j} = conj(X_{2c}) + i conj(X_{2c+1})
+        lds[lidx<N>(c, j)] = Cx<R>{xa.x - xb.y, xa.y + xb.x};
+        lds[lidx<N>(c, N - j)] = Cx<R>{xa.x + xb.y, xb.x - xa.y};
+      }
+    }
+  }
+  __syncthreads();
+  fft_run<R, LOG2N, NSEQ, T, true, Cfg::MAXLOG, 0>(lds, tw);
+  const R* ldsr = reinterpret_cast<const R*>(lds);
+  {
+    constexpr int LPT = (N * B + T - 1) / T;
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int e = tid + q * T;
+      const int k = e / B, b = e % B;
+      if (((N * B) % T == 0 || e < N * B) && b < ncols) {
+        const double val = (double)ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] * winv[k];
+        z[(size_t)k * nx + i0 + b] = (TZ)val;
+      }
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// launch one compiled (B, T) candidate; dispatch over candidates and log2(N_t)
+// ---------------------------------------------------------------------------
+static inline int pad8(int v) { return (v + 7) / 8 * 8; }
+
+template <typename R, int L, int CI>
+static hipError_t launch_fwd_c(const PcPlan& pl, const double* v, const double* scale,
+                               const int* done, hipStream_t s) {
+  using C = PcCand<R, L, CI>;
+  if constexpr (!C::ok) {
+    return hipErrorInvalidValue;
+  } else {
+    const int nwg = pad8(pl.P);
+    const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
+    hipLaunchKernelGGL((k_pc_forward<R, L, C::B, C::T>), dim3(nwg), dim3(C::T), 0, s, v, scale,
+                       done, pl.lo, pl.di, pl.up, pl.wfw, tw, pl.mu, pl.il2, (Cx<R>*)pl.spec,
+                       (Cx<R>*)pl.iface, pl.nx, pl.P, nwg);
+    return hipGetLastError();
+  }
+}
+
+template <typename R, int L, int CI>
+static hipError_t launch_inv_c(const PcPlan& pl, void* z, int zf, const int* done,
+                               hipStream_t s) {
+  using C = PcCand<R, L, CI>;
+  if constexpr (!C::ok) {
+    return hipErrorInvalidValue;
+  } else {
+    const int nwg = pad8(pl.P);
+    const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
+    if (zf)
+      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, float>), dim3(nwg), dim3(C::T), 0, s,
+                         (const Cx<R>*)pl.spec, (const Cx<R>*)pl.sep, done, pl.lo, pl.di, pl.up,
+                         pl.winv, tw, pl.mu, (float*)z, pl.nx, pl.P, pl.NS, nwg);
+    else
+      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, double>), dim3(nwg), dim3(C::T), 0, s,
+                         (const Cx<R>*)pl.spec, (const Cx<R>*)pl.sep, done, pl.lo, pl.di, pl.up,
+                         pl.winv, tw, pl.mu, (double*)z, pl.nx, pl.P, pl.NS, nwg);
+    return hipGetLastError();
+  }
+}
+
+template <typename R, int L, int CI = 0>
+static hipError_t fwd_cand(int ci, const PcPlan& pl, const double* v, const double* scale,
+                           const int* done, hipStream_t s) {
+  if constexpr (CI >= kNumCand) {
+    return hipErrorInvalidValue;
+  } else {
+    if (ci == CI) return launch_fwd_c<R, L, CI>(pl, v, scale, done, s);
+    return fwd_cand<R, L, CI + 1>(ci, pl, v, scale, done, s);
+  }
+}
+
+template <typename R, int L, int CI = 0>
+static hipError_t inv_cand(int ci, const PcPlan& pl, void* z, int zf, const int* done,
+                           hipStream_t s) {
+  if constexpr (CI >= kNumCand) {
+    return hipErrorInvalidValue;
+  } else {
+    if (ci == CI) return launch_inv_c<R, L, CI>(pl, z, zf, done, s);
+    return inv_cand<R, L, CI + 1>(ci, pl, z, zf, done, s);
+  }
+}
+
+template <typename R, int L, int CI = 0>
+static bool cand_info(int ci, int* B, int* T) {
+  if constexpr (CI >= kNumCand) {
+    return false;
+  } else {
+    if (ci == CI) {
+      *B = PcCand<R, L, CI>::B;
+      *T = PcCand<R, L, CI>::T;
+      return PcCand<R, L, CI>::ok;
+    }
+    return cand_info<R, L, CI + 1>(ci, B, T);
+  }
+}
+
+#define CN_LOG2N_CASES(X) \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)
+
+#define CN_DEFINE_PC_PRECISION(R, SUF)                                                        \
+  hipError_t pc_forward_##SUF(const PcPlan& pl, const double* v, const double* scale,         \
+                              const int* done, hipStream_t s) {                              \
+    switch (pl.log2n) {                                                                       \
+      CN_LOG2N_CASES(CN_FWD_CASE_##SUF)                                                       \
+    }                                                                                         \
+    return hipErrorInvalidValue;                                                              \
+  }                                                                                           \
+  hipError_t pc_inverse_##SUF(const PcPlan& pl, void* z, int zf, const int* done,             \
+                              hipStream_t s) {                                               \
+    switch (pl.log2n) {                                                                       \
+      CN_LOG2N_CASES(CN_INV_CASE_##SUF)                                                       \
+    }                                                                                         \
+    return hipErrorInvalidValue;                                                              \
+  }                                                                                           \
+  bool pc_candidate_##SUF(int log2n, int ci, int* B, int* T) {                                \
+    switch (log2n) {                                                                          \
+      CN_LOG2N_CASES(CN_INFO_CASE_##SUF)                                                      \
+    }                                                                                         \
+    return false;                                                                             \
+  }
+
+}  // namespace cn

@@ -310,3 +310,37 @@ def test_aliasing_rejected():
         s.solve(x, x)
     with pytest.raises(B.CnError):
         s.solve(x, torch.empty_like(x), m=inst.m + 1)
+
+
+# ---------------------------------------------------------------------------
+# every compiled (tile width, workgroup size) variant of the transform kernels
+# ---------------------------------------------------------------------------
+
+VARIANTS = [(16, 256), (16, 512), (16, 1024), (8, 256), (8, 512), (8, 1024), (4, 256),
+            (4, 512)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nx,nt", [(300, 64), (1000, 512), (257, 1024), (255, 4096)])
+def test_pc_apply_every_variant(nx, nt, prec, monkeypatch):
+    """The autotuner may pick any compiled variant: each one must match."""
+    inst = localvol(nx, nt) if nx >= 255 else W.config1(nx=nx, nt=nt)
+    v = W.random_vector(inst.n, 11)
+    ref = O.pc_apply(*oracle_args(inst), inst.alpha, v)
+    ran = 0
+    for bcols, thr in VARIANTS:
+        monkeypatch.setenv("CN_PC_TILE", f"{bcols},{thr}")
+        try:
+            s = solver(inst, pc_prec=prec)
+        except B.CnError as e:
+            assert e.status == B.CN_EINVAL and "not a compiled variant" in str(e)
+            continue
+        banner(f"pc_apply variant {prec} B={bcols} T={thr} nx={nx} nt={nt}")
+        assert s.query()["tile_cols"] == bcols and s.query()["threads"] == thr
+        z = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+        s.pc_apply(T(v), z)
+        err = rel_inf(z.cpu().numpy(), ref)
+        assert err <= pc_tol(inst.alpha, prec, nt), (bcols, thr, err)
+        s.close()
+        ran += 1
+    assert ran >= 1
