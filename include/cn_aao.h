@@ -139,6 +139,44 @@ cn_status cn_gmres_solve(cn_aao *h, const double *b, double *x,
 cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
                        int32_t *threads);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent problems of uneven sizes solved together.  Every
+ * step of the method (each transform, interface solve, matvec, Gram-Schmidt
+ * pass, finishing reduction, update) is one kernel launch over a work list
+ * covering all instances; instances that converged skip their work.  The
+ * transform kernels run one launch per distinct N_t, with the (tile width,
+ * workgroup size) variant chosen by the create-time autotuner on that
+ * group's widest instance.
+ * ------------------------------------------------------------------------- */
+typedef struct cn_batch cn_batch;
+
+/* Create a batch of `count` problems (each validated as by cn_aao_create).
+ * All problems need the same pc_prec and stream.  Packed vectors hold the
+ * instances back to back in order: instance i occupies [off[i], off[i+1])
+ * of b and x (n_i = nx_i * nt_i elements), and [space_off[i], space_off[i+1])
+ * of a packed u0 (nx_i elements).  Errors name the failing problem. */
+cn_status cn_batch_create(const cn_problem *probs, int32_t count, cn_batch **out);
+cn_status cn_batch_destroy(cn_batch *b);
+
+/* Offsets of the packed layout: off and space_off are host arrays of
+ * count+1 int64 (either may be NULL). */
+cn_status cn_batch_offsets(const cn_batch *b, int64_t *off, int64_t *space_off);
+
+/* Packed b = xi + tau f for every instance (u0 packed by space_off, f and b
+ * packed by off); device pointers. */
+cn_status cn_batch_rhs(cn_batch *b, const double *u0, const double *f, double *bp);
+
+/* Solve every instance with GMRES(m) as cn_gmres_solve does (flexible form,
+ * CGS2, float64 Krylov; preconditioner in the batch's precision).  opts->m
+ * must not exceed the smallest m_max of the batch; the iteration budget
+ * counts cycles' inner iterations of the batch as a whole.  infos: host array
+ * of `count` entries (may be NULL); total (may be NULL) gets the largest
+ * iteration count and relative residual and the summed matvecs.  Returns
+ * CN_OK when every instance reached rtol, else CN_NOT_CONVERGED.
+ * Synchronises. */
+cn_status cn_batch_solve(cn_batch *b, const double *bp, double *xp, const cn_gmres_opts *opts,
+                         cn_gmres_info *infos, cn_gmres_info *total);
+
 /* Kernel timing of one inner iteration, for benchmarking.  Must follow a
  * cn_gmres_solve on the same handle that ran at least j+1 inner iterations
  * (its basis is reused; the solution is not touched).  Launches each of the

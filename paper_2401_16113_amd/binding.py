@@ -76,6 +76,14 @@ def load():
                                           ctypes.POINTER(CnGmresInfo)]),
         "cn_profile_step": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(dbl),
                                            ctypes.POINTER(dbl)]),
+        "cn_batch_create": (ctypes.c_int, [ctypes.POINTER(CnProblem), i32, ctypes.POINTER(vp)]),
+        "cn_batch_destroy": (ctypes.c_int, [vp]),
+        "cn_batch_offsets": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int64)]),
+        "cn_batch_rhs": (ctypes.c_int, [vp, vp, vp, vp]),
+        "cn_batch_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(CnGmresOpts),
+                                          ctypes.POINTER(CnGmresInfo),
+                                          ctypes.POINTER(CnGmresInfo)]),
         "cn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "cn_last_error": (ctypes.c_char_p, []),
     }
@@ -201,3 +209,69 @@ class Solver:
                                              ctypes.byref(info)), "cn_gmres_solve", ok)
         return SolveResult(st, info.iters, info.restarts, info.matvecs, info.pc_applies,
                            info.relres_true, info.relres_est, info.seconds)
+
+
+class Batch:
+    """Many independent problems of uneven size solved together (wraps a
+    cn_batch handle).  `problems`: list of dicts with keys a_lo, a_di, a_up
+    (float64 CUDA tensors of length nx), nt, T, alpha and optionally m_max,
+    d_half.  Packed vectors hold the instances back to back (see offsets)."""
+
+    def __init__(self, problems, pc_prec: str = "fp32", stream=None):
+        lib = load()
+        self._lib = lib
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._keep = []
+        arr = (CnProblem * len(problems))()
+        for i, pr in enumerate(problems):
+            self._keep.append(pr)
+            arr[i] = CnProblem(nx=int(pr["a_lo"].numel()), nt=int(pr["nt"]),
+                               m_max=int(pr.get("m_max", 20)), flags=int(pr.get("flags", 0)),
+                               T=float(pr["T"]), alpha=float(pr["alpha"]),
+                               a_lo=_ptr(pr["a_lo"]), a_di=_ptr(pr["a_di"]),
+                               a_up=_ptr(pr["a_up"]), d_half=_ptr(pr.get("d_half")),
+                               pc_prec=CN_PC_FP32 if pc_prec == "fp32" else CN_PC_FP64,
+                               stream=ctypes.c_void_p(stream.cuda_stream))
+        h = ctypes.c_void_p()
+        _check(lib.cn_batch_create(arr, len(problems), ctypes.byref(h)), "cn_batch_create")
+        self._h = h
+        self.count = len(problems)
+        off = (ctypes.c_int64 * (self.count + 1))()
+        soff = (ctypes.c_int64 * (self.count + 1))()
+        _check(lib.cn_batch_offsets(h, off, soff), "cn_batch_offsets")
+        self.offsets = list(off)
+        self.space_offsets = list(soff)
+        self.n = self.offsets[-1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cn_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rhs(self, u0, f, out):
+        _check(self._lib.cn_batch_rhs(self._h, _ptr(u0), _ptr(f), _ptr(out)), "cn_batch_rhs")
+        return out
+
+    def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
+              use_x0: bool = False):
+        opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=1 if use_x0 else 0,
+                           reserved=0, rtol=float(rtol))
+        infos = (CnGmresInfo * self.count)()
+        total = CnGmresInfo()
+        st = _check(self._lib.cn_batch_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(opts), infos,
+                                             ctypes.byref(total)), "cn_batch_solve",
+                    (CN_OK, CN_NOT_CONVERGED))
+        per = [SolveResult(CN_OK if i.relres_true <= rtol else CN_NOT_CONVERGED, i.iters,
+                           i.restarts, i.matvecs, i.pc_applies, i.relres_true, i.relres_est,
+                           i.seconds) for i in infos]
+        tot = SolveResult(st, total.iters, total.restarts, total.matvecs, total.pc_applies,
+                          total.relres_true, total.relres_est, total.seconds)
+        return tot, per

@@ -1,19 +1,24 @@
-// Host runtime of libcn_aao: the opaque handle, argument validation, the
-// float64 tables of the alpha-circulant diagonalisation (Sec. 3.1), the
-// workspace, and the GMRES(m) driver.  Every computational step runs in the
-// kernels of cn_pc.hip and cn_krylov.hip.
+// Host runtime of libcn_aao: the opaque handles (one problem, or a batch of
+// uneven problems), argument validation, the float64 tables of the
+// alpha-circulant diagonalisation (Sec. 3.1), the workspace, the
+// create-time autotuner and the GMRES(m) driver.  Every computational step
+// runs in the kernels of cn_pc*.hip and cn_krylov.hip; a handle is a launch
+// context of one instance descriptor, a batch concatenates the descriptors
+// and work lists of its instances so that each step is one launch.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <map>
 #include <mutex>
-#include <tuple>
-#include <cmath>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "cn_internal.hpp"
@@ -41,6 +46,43 @@ static cn_status fail(cn_status s, const std::string& msg) {
     }                                                                                   \
   } while (0)
 
+// work lists of one launch context (device arrays)
+struct WorkLists {
+  int2* pc = nullptr;   // (instance, tile) for the transform kernels
+  int2* k2 = nullptr;   // (instance, frequency) for the interface solve
+  int2* mv = nullptr;   // (instance, matvec block)
+  int2* st = nullptr;   // (instance, streaming block)
+  Items I_pc, I_k2, I_mv, I_st;
+  void release() {
+    for (int2* p : {pc, k2, mv, st})
+      if (p != nullptr) (void)hipFree(p);
+    pc = k2 = mv = st = nullptr;
+    I_pc = I_k2 = I_mv = I_st = Items{};
+  }
+};
+
+static hipError_t upload_items(const std::vector<int2>& v, int2** dptr, Items* it) {
+  if (*dptr != nullptr) {
+    (void)hipFree(*dptr);
+    *dptr = nullptr;
+  }
+  *it = Items{};
+  if (v.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dptr, v.size() * sizeof(int2));
+  if (e == hipSuccess) e = hipMemcpy(*dptr, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    it->it = *dptr;
+    it->n = (int)v.size();
+  }
+  return e;
+}
+
+static int k2_threads_for(int ns) {
+  int thr = 64;
+  while (thr < 256 && thr < ns) thr *= 2;
+  return thr;
+}
+
 struct cn_aao {
   int nx = 0, nt = 0, m_max = 0, flags = 0;
   double T = 0, alpha = 0, tau = 0;
@@ -55,20 +97,24 @@ struct cn_aao {
   double* w = nullptr;    // npad
   double* partials = nullptr;
   GState* st = nullptr;
-  GSummary* hsum = nullptr;  // pinned coherent host memory, 4 slots
+  GSummary* hsum = nullptr;      // pinned coherent host memory, 4 slots
   GSummary* hsum_dev = nullptr;  // the same slots as seen by kernels
   int seqc = 0;                  // last sequence number handed to a kernel
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  // launch context: one descriptor and its work lists
+  InstDesc desc{};
+  InstDesc* d_desc = nullptr;
+  WorkLists wl;
+  Launch L{};
+  int k2_thr = 64;
   std::vector<void*> dev_allocs;
 };
 
 static void release(cn_aao* h) {
   if (h == nullptr) return;
-  if (h->stream != nullptr || true) (void)hipStreamSynchronize(h->stream);
+  (void)hipStreamSynchronize(h->stream);
+  h->wl.release();
   for (void* p : h->dev_allocs) (void)hipFree(p);
   if (h->hsum != nullptr) (void)hipHostFree(h->hsum);
-  for (auto& e : h->ev)
-    if (e != nullptr) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -89,14 +135,64 @@ static bool overlaps(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+// Fill the instance descriptor of h from its plan and workspace.
+static void fill_desc(cn_aao* h, InstDesc* d) {
+  d->pl = h->pl;
+  d->dw = h->dw;
+  d->nx = h->nx;
+  d->nt = h->nt;
+  d->rows = matvec_rows(h->nx, h->nt);
+  d->mv_cols = (h->nx + 255) / 256;
+  d->mv_grid = d->mv_cols * ((h->nt + d->rows - 1) / d->rows);
+  d->st_grid = stream_grid(h->n);
+  d->n = h->n;
+  d->vstride = h->npad;
+  d->off = 0;
+  d->V = h->V;
+  d->Z = h->Z;
+  d->w = h->w;
+  d->partials = h->partials;
+  d->st = h->st;
+  d->host = h->hsum_dev;
+  d->zf = h->prec;
+}
+
+// Work items of one instance (appended with instance index `inst`).
+static void append_items(const InstDesc& d, int inst, std::vector<int2>* pc, std::vector<int2>* k2,
+                         std::vector<int2>* mv, std::vector<int2>* stv) {
+  if (pc != nullptr)
+    for (int p = 0; p < d.pl.P; ++p) pc->push_back(make_int2(inst, p));
+  if (k2 != nullptr && d.pl.NS > 0)
+    for (int j = 0; j < d.pl.F; ++j) k2->push_back(make_int2(inst, j));
+  if (mv != nullptr)
+    for (int b = 0; b < d.mv_grid; ++b) mv->push_back(make_int2(inst, b));
+  if (stv != nullptr)
+    for (int b = 0; b < d.st_grid; ++b) stv->push_back(make_int2(inst, b));
+}
+
+// (Re)build the one-instance launch context of h.
+static hipError_t build_launch(cn_aao* h) {
+  fill_desc(h, &h->desc);
+  hipError_t e = hipMemcpy(h->d_desc, &h->desc, sizeof(InstDesc), hipMemcpyHostToDevice);
+  std::vector<int2> pc, k2, mv, stv;
+  append_items(h->desc, 0, &pc, &k2, &mv, &stv);
+  if (e == hipSuccess) e = upload_items(pc, &h->wl.pc, &h->wl.I_pc);
+  if (e == hipSuccess) e = upload_items(k2, &h->wl.k2, &h->wl.I_k2);
+  if (e == hipSuccess) e = upload_items(mv, &h->wl.mv, &h->wl.I_mv);
+  if (e == hipSuccess) e = upload_items(stv, &h->wl.st, &h->wl.I_st);
+  h->L = Launch{h->d_desc, 1, h->prec};
+  h->k2_thr = k2_threads_for(h->pl.NS);
+  return e;
+}
+
 // Spin until a kernel has published sequence number `seq` into `slot`
 // (coherent pinned host memory), then copy the summary out.
-static cn_status wait_slot(cn_aao* h, GSummary* slot, int seq, GSummary* out) {
+static cn_status wait_slot(hipStream_t stream, GSummary* slot, int seq, GSummary* out) {
   volatile int* p = &slot->seq;
   long spins = 0;
   while (*p != seq) {
     if ((++spins & 4095) == 0) {
-      const hipError_t e = hipStreamQuery(h->stream);
+      const hipError_t e = hipStreamQuery(stream);
       if (e != hipSuccess && e != hipErrorNotReady)
         return fail(CN_EHIP, std::string("solver stream: ") + hipGetErrorString(e));
       if (e == hipSuccess && *p != seq)
@@ -124,7 +220,6 @@ static cn_status wait_slot(cn_aao* h, GSummary* slot, int seq, GSummary* out) {
   } while (0)
 
 extern "C" {
-
 const char* cn_status_string(cn_status s) {
   switch (s) {
     case CN_OK: return "ok";
@@ -139,7 +234,10 @@ const char* cn_status_string(cn_status s) {
 
 const char* cn_last_error(void) { return g_err.c_str(); }
 
-cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
+}  // extern "C"
+
+// Create a handle; force_cand >= 0 skips autotuning and uses that variant.
+static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out) {
   if (out == nullptr) return fail(CN_EINVAL, "out is NULL");
   *out = nullptr;
   if (p == nullptr) return fail(CN_EINVAL, "problem is NULL");
@@ -170,7 +268,6 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
   h->stream = (hipStream_t)p->stream;
   h->n = n;
   h->npad = (n + 63) / 64 * 64;
-  cn_status rc = CN_OK;
   auto bail = [&](cn_status s) {
     release(h);
     return s;
@@ -255,6 +352,14 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
       cands = keep;
     } else if (at != nullptr && at[0] == '0') {
       cands.assign(1, 0);
+    }
+    if (force_cand >= 0) {
+      int B = 0, T = 0;
+      if (!pc_candidate(pl.prec, pl.log2n, force_cand, &B, &T)) {
+        fail(CN_EINVAL, "requested transform variant is not compiled");
+        return bail(CN_EINVAL);
+      }
+      cands.assign(1, force_cand);
     }
   }
   // buffers sized for the most demanding candidate
@@ -353,10 +458,23 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
   TRY(hipMemcpy(pl.mu, mu.data(), pl.F * sizeof(Cx<double>), hipMemcpyHostToDevice));
   TRY(hipMemcpy(pl.il2, il2.data(), pl.F * sizeof(Cx<double>), hipMemcpyHostToDevice));
 
-  // -- GMRES basis (also the autotuner's scratch) ---------------------------------------
+  // -- GMRES basis (also the autotuner's scratch) and solver state -------------------
   TRY(dalloc(h, &h->V, (size_t)(h->m_max + 1) * h->npad * sizeof(double)));
   TRY(dalloc(h, &h->Z, (size_t)h->m_max * h->npad * rsz));
   TRY(dalloc(h, &h->w, (size_t)h->npad * sizeof(double)));
+  {
+    const int rows = matvec_rows(nx, nt);
+    const long long mgrid = (long long)((nx + 255) / 256) * ((nt + rows - 1) / rows);
+    const long long pgrid = std::max<long long>(mgrid, stream_grid(h->n));
+    TRY(dalloc(h, &h->partials, (size_t)pgrid * NVMAX * sizeof(double)));
+  }
+  TRY(dalloc(h, &h->st, sizeof(GState)));
+  TRY(hipMemsetAsync(h->st, 0, sizeof(GState), h->stream));
+  TRY(hipHostMalloc((void**)&h->hsum, 4 * sizeof(GSummary),
+                    hipHostMallocCoherent | hipHostMallocMapped));
+  memset(h->hsum, 0, 4 * sizeof(GSummary));
+  TRY(hipHostGetDevicePointer((void**)&h->hsum_dev, h->hsum, 0));
+  TRY(dalloc(h, &h->d_desc, sizeof(InstDesc)));
 
   // -- preconditioner workspace, interface factorisation, variant choice -------------
   TRY(dalloc(h, &pl.spec, spec_elems * rsz));
@@ -380,7 +498,7 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
       (void)hipFree(spk);
       (void)hipFree(err);
     };
-    // set up the interface factors of candidate ci (singular -> *singular = 1)
+    // set up the interface factors and launch context of candidate ci
     auto setup = [&](int ci, int* singular) -> hipError_t {
       int B = 0, T = 0;
       pc_candidate(pl.prec, pl.log2n, ci, &B, &T);
@@ -394,12 +512,13 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
       int herr = 0;
       if (e == hipSuccess) e = hipMemcpy(&herr, err, sizeof(int), hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = build_launch(h);
       *singular = herr != 0;
       return e;
     };
     int best = -1;
     const auto key = std::make_tuple(pl.prec, pl.log2n, nx);
-    {
+    if (force_cand < 0) {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune.find(key);
       if (it != g_tune.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
@@ -408,35 +527,49 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
     if (best < 0 && cands.size() == 1) best = cands[0];
     hipError_t e = hipSuccess;
     if (best < 0) {
-      // time three applies of every candidate on this problem's shape
+      // time every candidate on this problem's shape as it runs inside a
+      // solve: caches cold (the basis buffer, up to 1 GB, is overwritten
+      // before each timed apply; its first vector, all zero, is the input),
+      // one warm-up apply, the best of three
       hipEvent_t e0 = nullptr, e1 = nullptr;
       e = hipEventCreate(&e0);
       if (e == hipSuccess) e = hipEventCreate(&e1);
-      if (e == hipSuccess) e = hipMemsetAsync(h->V, 0, (size_t)h->n * sizeof(double), h->stream);
+      const size_t flush = std::min<size_t>((size_t)(h->m_max + 1) * h->npad * sizeof(double),
+                                            (size_t)1 << 30);
+      if (e == hipSuccess) e = hipMemsetAsync(h->V, 0, flush, h->stream);
       float best_ms = 1e30f;
       for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
         const int ci = cands[c];
         int sing = 0;
         e = setup(ci, &sing);
         if (e != hipSuccess || sing) continue;
-        for (int r = 0; r < 4 && e == hipSuccess; ++r) {
-          if (r == 1) e = hipEventRecord(e0, h->stream);
-          if (e == hipSuccess) e = pc_forward(pl, h->V, nullptr, nullptr, h->stream);
-          if (e == hipSuccess) e = pc_reduced(pl, nullptr, h->stream);
-          if (e == hipSuccess) e = pc_inverse(pl, h->Z, pl.prec, nullptr, h->stream);
+        auto apply = [&]() -> hipError_t {
+          hipError_t r = pc_forward(pl.prec, pl.log2n, ci, h->L, h->wl.I_pc, 0, h->V, h->stream);
+          if (r == hipSuccess) r = pc_reduced(pl.prec, h->L, h->wl.I_k2, h->k2_thr, 0, 1, h->stream);
+          if (r == hipSuccess)
+            r = pc_inverse(pl.prec, pl.log2n, ci, h->L, h->wl.I_pc, 0, h->Z, pl.prec, h->stream);
+          return r;
+        };
+        e = apply();
+        float cand_ms = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+          e = hipMemsetAsync(h->V, 0, flush, h->stream);
+          if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+          if (e == hipSuccess) e = apply();
+          if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e == hipSuccess) cand_ms = std::min(cand_ms, ms);
         }
-        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && ms < best_ms) {
-          best_ms = ms;
+        if (e == hipSuccess && cand_ms < best_ms) {
+          best_ms = cand_ms;
           best = ci;
         }
       }
       if (e0 != nullptr) (void)hipEventDestroy(e0);
       if (e1 != nullptr) (void)hipEventDestroy(e1);
-      if (e == hipSuccess && best >= 0) {
+      if (e == hipSuccess && best >= 0 && force_cand < 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = best;
       }
@@ -454,28 +587,240 @@ cn_status cn_aao_create(const cn_problem* p, cn_aao** out) {
       return bail(CN_ESINGULAR);
     }
   }
-
-  // -- remaining GMRES workspace -------------------------------------------------------
-  {
-    const int rows = matvec_rows(nx, nt);
-    const long long mgrid = (long long)((nx + 255) / 256) * ((nt + rows - 1) / rows);
-    const long long pgrid = mgrid > KGRID ? mgrid : KGRID;
-    TRY(dalloc(h, &h->partials, (size_t)pgrid * NVMAX * sizeof(double)));
-  }
-  TRY(dalloc(h, &h->st, sizeof(GState)));
-  TRY(hipMemsetAsync(h->st, 0, sizeof(GState), h->stream));
-  TRY(hipHostMalloc((void**)&h->hsum, 4 * sizeof(GSummary),
-                    hipHostMallocCoherent | hipHostMallocMapped));
-  memset(h->hsum, 0, 4 * sizeof(GSummary));
-  TRY(hipHostGetDevicePointer((void**)&h->hsum_dev, h->hsum, 0));
-  TRY(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
-  TRY(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
   TRY(hipStreamSynchronize(h->stream));
 #undef TRY
-  (void)rc;
   *out = h;
   return CN_OK;
 }
+
+// ---------------------------------------------------------------------------
+// the solve driver, shared by a handle (one instance) and a batch
+// ---------------------------------------------------------------------------
+struct PcGroup {
+  int prec, log2n, cand;
+  Items items;
+};
+
+struct SolveCtx {
+  hipStream_t s = nullptr;
+  Launch L{};
+  std::vector<PcGroup> groups;  // transform launches (one per N_t group)
+  Items k2, mv, stv;
+  int k2_thr = 64;
+  int prec = 0;
+  bool batched = false;
+  // one instance: its host slots and sequence counter
+  GSummary* hs = nullptr;
+  int* seqc = nullptr;
+  // batch: batch-summary slots (host and device view), device counter, host count
+  GSummary* bh = nullptr;
+  GSummary* bh_dev = nullptr;
+  int* dcounter = nullptr;
+  int* bseq = nullptr;
+  std::vector<GSummary*> inst_host;  // per-instance host slots
+  std::vector<long long> off, len;   // packed offsets and lengths
+};
+
+static hipError_t enqueue_iteration(SolveCtx& c, int j, int stop_iter, double rtol, int slot,
+                                    int seq) {
+  hipError_t e = hipSuccess;
+  for (const PcGroup& g : c.groups)
+    if (e == hipSuccess) e = pc_forward(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, c.s);
+  if (e == hipSuccess) e = pc_reduced(c.prec, c.L, c.k2, c.k2_thr, j, 0, c.s);
+  for (const PcGroup& g : c.groups)
+    if (e == hipSuccess)
+      e = pc_inverse(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, c.L.zf, c.s);
+  if (e == hipSuccess) e = launch_arnoldi(c.L, c.mv, c.stv, j, stop_iter, rtol, slot, seq, c.s);
+  return e;
+}
+
+// Publish a batch summary (instances still iterating) and return its sequence number.
+static cn_status batch_publish(SolveCtx& c, int slot, int* seq) {
+  HIP_TRY(launch_batch_summary(c.L, c.dcounter, c.bh_dev + slot, c.s));
+  *seq = ++(*c.bseq);
+  return CN_OK;
+}
+
+static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmres_opts* opts,
+                           cn_gmres_info* infos, cn_gmres_info* total) {
+  const auto wall0 = std::chrono::steady_clock::now();
+  const int ninst = c.L.ninst;
+  const double rtol = opts->rtol;
+  std::vector<int> iters(ninst, 0), pcs(ninst, 0), mvs(ninst, 1), rest(ninst, 0);
+  std::vector<double> est(ninst, 0.0);
+  std::vector<GSummary> cur(ninst), fin(ninst);
+  // r_0 = b - M x_0 into v_0 (x_0 = 0 is never read); the stop flag covers
+  // instances that already meet rtol, so nothing waits here
+  int seq_res = c.batched ? 0 : ++(*c.seqc);
+  HIP_TRY(launch_residual(c.L, c.mv, b, x, opts->use_x0 ? 0 : 1, rtol, 2, seq_res, c.s));
+  bool x_zero = !opts->use_x0;
+  int done_iters = 0;
+  int seqs[MMAX];
+  double ests[MMAX];
+  GSummary it{};
+  while (true) {
+    const int m_eff = std::min(opts->m, opts->max_iters - done_iters);
+    int known = 0;  // iterations of this cycle whose summary the host has read
+    for (int j = 0; j < m_eff; ++j) {
+      seqs[j] = c.batched ? 0 : ++(*c.seqc);
+      HIP_TRY(enqueue_iteration(c, j, m_eff, rtol, j & 1, seqs[j]));
+      if (c.batched) CN_TRY(batch_publish(c, j & 1, &seqs[j]));
+      GSummary* slots = c.batched ? c.bh : c.hs;
+      if (j >= 1) {
+        if (known < j) {
+          CN_TRY(wait_slot(c.s, slots + ((j - 1) & 1), seqs[j - 1], &it));
+          ests[j - 1] = it.est;
+          known = j;
+          if (it.done) break;
+        }
+        // The residual estimate falls at least geometrically (usually
+        // faster).  When the rate of the last two steps brings iteration j
+        // within 50x of rtol, wait for it instead of queueing iteration j+1:
+        // an iteration queued after convergence still costs its kernel
+        // dispatches (~45 us), a wrong guess only a short idle gap (~15 us).
+        double prev = 1.0;
+        if (j >= 2) {
+          prev = ests[j - 2];
+        } else if (!c.batched) {
+          volatile GSummary* r0 = c.hs + 2;
+          prev = (r0->seq == seq_res && r0->relres > 0.0) ? r0->relres : 1.0;
+        }
+        const double rate = prev > 0.0 ? ests[j - 1] / prev : 1.0;
+        if (j + 1 < m_eff && ests[j - 1] * rate < 50.0 * rtol) {
+          CN_TRY(wait_slot(c.s, slots + (j & 1), seqs[j], &it));
+          ests[j] = it.est;
+          known = j + 1;
+          if (it.done) break;
+        }
+      }
+    }
+    // y from the triangular factors (cycle summaries -> slot 3), x += Z y,
+    // then the true residuals (-> slot 2)
+    const int seq_fin = c.batched ? 0 : ++(*c.seqc);
+    HIP_TRY(launch_cycle_end(c.L, c.stv, x, x_zero ? 1 : 0, 3, seq_fin, c.s));
+    x_zero = false;
+    seq_res = c.batched ? 0 : ++(*c.seqc);
+    HIP_TRY(launch_residual(c.L, c.mv, b, x, 0, rtol, 2, seq_res, c.s));
+    if (c.batched) {
+      int sq = 0;
+      CN_TRY(batch_publish(c, 2, &sq));
+      CN_TRY(wait_slot(c.s, c.bh + 2, sq, &it));
+      std::atomic_thread_fence(std::memory_order_acquire);
+      for (int i = 0; i < ninst; ++i) {
+        volatile GSummary* f3 = c.inst_host[i] + 3;
+        volatile GSummary* f2 = c.inst_host[i] + 2;
+        fin[i].k = f3->k;
+        fin[i].est = f3->est;
+        cur[i].relres = f2->relres;
+        cur[i].bnorm = f2->bnorm;
+      }
+    } else {
+      CN_TRY(wait_slot(c.s, c.hs + 3, seq_fin, &fin[0]));
+      CN_TRY(wait_slot(c.s, c.hs + 2, seq_res, &cur[0]));
+    }
+    int kmax = 0;
+    bool all_conv = true;
+    for (int i = 0; i < ninst; ++i) {
+      const int k = fin[i].k;
+      if (k > 0) est[i] = fin[i].est;
+      iters[i] += k;
+      pcs[i] += k;
+      mvs[i] += k + 1;
+      kmax = std::max(kmax, k);
+      if (!(cur[i].relres <= rtol)) all_conv = false;
+    }
+    done_iters += kmax;
+    if (kmax == 0 || all_conv || done_iters >= opts->max_iters) break;
+    for (int i = 0; i < ninst; ++i)
+      if (!(cur[i].relres <= rtol)) ++rest[i];
+  }
+  // b = 0: the solution is x = 0 whatever the initial guess
+  for (int i = 0; i < ninst; ++i) {
+    if (cur[i].bnorm == 0.0) {
+      HIP_TRY(hipMemsetAsync(x + c.off[i], 0, (size_t)c.len[i] * sizeof(double), c.s));
+      cur[i].relres = 0.0;
+      est[i] = 0.0;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(c.s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  bool ok = true;
+  cn_gmres_info tot{0, 0, 0, 0, 0.0, 0.0, secs};
+  for (int i = 0; i < ninst; ++i) {
+    cn_gmres_info in;
+    in.iters = iters[i];
+    in.restarts = rest[i];
+    in.matvecs = mvs[i];
+    in.pc_applies = pcs[i];
+    in.relres_true = cur[i].relres;
+    in.relres_est = iters[i] > 0 ? est[i] : cur[i].relres;
+    in.seconds = secs;
+    if (infos != nullptr) infos[i] = in;
+    if (!(cur[i].relres <= rtol)) ok = false;
+    tot.iters = std::max(tot.iters, in.iters);
+    tot.restarts = std::max(tot.restarts, in.restarts);
+    tot.matvecs += in.matvecs;
+    tot.pc_applies += in.pc_applies;
+    tot.relres_true = std::max(tot.relres_true, in.relres_true);
+    tot.relres_est = std::max(tot.relres_est, in.relres_est);
+  }
+  if (total != nullptr) *total = tot;
+  return ok ? CN_OK : CN_NOT_CONVERGED;
+}
+
+static SolveCtx handle_ctx(cn_aao* h) {
+  SolveCtx c;
+  c.s = h->stream;
+  c.L = h->L;
+  c.groups.push_back(PcGroup{h->prec, h->pl.log2n, h->pl.cand, h->wl.I_pc});
+  c.k2 = h->wl.I_k2;
+  c.mv = h->wl.I_mv;
+  c.stv = h->wl.I_st;
+  c.k2_thr = h->k2_thr;
+  c.prec = h->prec;
+  c.batched = false;
+  c.hs = h->hsum;
+  c.seqc = &h->seqc;
+  c.off.assign(1, 0);
+  c.len.assign(1, h->n);
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// batch of uneven instances
+// ---------------------------------------------------------------------------
+struct cn_batch {
+  std::vector<cn_aao*> inst;
+  std::vector<long long> off;      // count + 1 offsets into packed vectors
+  std::vector<long long> uoff;     // count + 1 offsets into packed u0 (space only)
+  hipStream_t stream = nullptr;
+  int prec = 0, m_min = 0;
+  InstDesc* d_desc = nullptr;
+  WorkLists wl;                    // k2, mv, st lists (pc lists per group below)
+  std::vector<int2*> pc_lists;
+  std::vector<PcGroup> groups;
+  int k2_thr = 64;
+  GSummary* bh = nullptr;          // 3 batch-summary slots (pinned coherent)
+  GSummary* bh_dev = nullptr;
+  int* dcounter = nullptr;
+  int bseq = 0;
+};
+
+static void batch_release(cn_batch* b) {
+  if (b == nullptr) return;
+  (void)hipStreamSynchronize(b->stream);
+  for (cn_aao* h : b->inst) release(h);
+  b->wl.release();
+  for (int2* p : b->pc_lists) (void)hipFree(p);
+  if (b->d_desc != nullptr) (void)hipFree(b->d_desc);
+  if (b->dcounter != nullptr) (void)hipFree(b->dcounter);
+  if (b->bh != nullptr) (void)hipHostFree(b->bh);
+  delete b;
+}
+
+extern "C" {
+
+cn_status cn_aao_create(const cn_problem* p, cn_aao** out) { return create_handle(p, -1, out); }
 
 cn_status cn_aao_destroy(cn_aao* h) {
   if (h == nullptr) return fail(CN_EINVAL, "handle is NULL");
@@ -491,24 +836,6 @@ cn_status cn_aao_query(const cn_aao* h, int32_t* tile_cols, int32_t* tiles, int3
   return CN_OK;
 }
 
-static KArgs kargs(cn_aao* h) {
-  KArgs a;
-  a.lo = h->pl.lo;
-  a.di = h->pl.di;
-  a.up = h->pl.up;
-  a.dw = h->dw;
-  a.nx = h->nx;
-  a.nt = h->nt;
-  a.rows = matvec_rows(h->nx, h->nt);
-  a.n = h->n;
-  a.V = h->V;
-  a.vstride = h->npad;
-  a.nv = 0;
-  a.st = h->st;
-  a.partials = h->partials;
-  return a;
-}
-
 cn_status cn_rhs(cn_aao* h, const double* u0, const double* f, double* b) {
   if (h == nullptr || u0 == nullptr || f == nullptr || b == nullptr)
     return fail(CN_EINVAL, "NULL argument");
@@ -522,16 +849,16 @@ cn_status cn_rhs(cn_aao* h, const double* u0, const double* f, double* b) {
 cn_status cn_matvec(cn_aao* h, const double* x, double* y) {
   if (h == nullptr || x == nullptr || y == nullptr) return fail(CN_EINVAL, "NULL argument");
   if (overlaps(x, y, h->n * sizeof(double))) return fail(CN_EINVAL, "x and y overlap");
-  KArgs a = kargs(h);
-  HIP_TRY(launch_matvec(a, x, 0, nullptr, y, 0, h->stream));
+  HIP_TRY(launch_matvec_plain(h->L, h->wl.I_mv, x, y, h->stream));
   return CN_OK;
 }
 
 cn_status cn_pc_apply(cn_aao* h, const double* v, double* z) {
   if (h == nullptr || v == nullptr || z == nullptr) return fail(CN_EINVAL, "NULL argument");
-  HIP_TRY(pc_forward(h->pl, v, nullptr, nullptr, h->stream));
-  HIP_TRY(pc_reduced(h->pl, nullptr, h->stream));
-  HIP_TRY(pc_inverse(h->pl, z, 0, nullptr, h->stream));
+  const PcPlan& pl = h->pl;
+  HIP_TRY(pc_forward(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, v, h->stream));
+  HIP_TRY(pc_reduced(pl.prec, h->L, h->wl.I_k2, h->k2_thr, 0, 1, h->stream));
+  HIP_TRY(pc_inverse(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, z, 0, h->stream));
   return CN_OK;
 }
 
@@ -544,106 +871,8 @@ cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_o
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
   if (overlaps(b, x, h->n * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
-  const auto wall0 = std::chrono::steady_clock::now();
-  hipStream_t s = h->stream;
-  GState* st = h->st;
-  const int* done = &st->sum.done;
-  const int zf = h->prec;
-  const size_t zes = zf ? sizeof(float) : sizeof(double);
-  const double rtol = opts->rtol;
-  KArgs a = kargs(h);
-  GSummary* hs = h->hsum;
-  GSummary* hd = h->hsum_dev;
-  // r_0 = b - M x_0 into v_0 (x_0 = 0 is never read); its summary -> slot 2.
-  // No host wait here: if r_0 already meets rtol the device flag makes the
-  // first cycle's kernels return at once.
-  int seq_res = ++h->seqc;
-  HIP_TRY(launch_matvec(a, opts->use_x0 ? x : nullptr, 0, b, h->V, 1, s, rtol, hd + 2, seq_res));
-  GSummary cur{}, fin{}, it{};
-  int iters = 0, restarts = 0, matvecs = 1, pcs = 0;
-  double est = 0.0;
-  bool x_zero = !opts->use_x0;
-  int seqs[MMAX];
-  double ests[MMAX];
-  while (true) {
-    const int m_eff = std::min(opts->m, opts->max_iters - iters);
-    int known = 0;  // iterations of this cycle whose summary the host has read
-    for (int j = 0; j < m_eff; ++j) {
-      const double* vj = h->V + (size_t)j * h->npad;
-      void* zj = (char*)h->Z + (size_t)j * h->npad * zes;
-      HIP_TRY(pc_forward(h->pl, vj, &st->vscale[j], done, s));
-      HIP_TRY(pc_reduced(h->pl, done, s));
-      HIP_TRY(pc_inverse(h->pl, zj, zf, done, s));
-      a.nv = j + 1;
-      HIP_TRY(launch_matvec(a, zj, zf, nullptr, h->w, 2, s, rtol));
-      // iteration j publishes into slot j & 1; check iteration j-1 while j runs
-      seqs[j] = ++h->seqc;
-      HIP_TRY(launch_cgs(a, h->w, h->V + (size_t)(j + 1) * h->npad, j, m_eff, s, 3, rtol,
-                         hd + (j & 1), seqs[j]));
-      if (j >= 1) {
-        if (known < j) {
-          CN_TRY(wait_slot(h, hs + ((j - 1) & 1), seqs[j - 1], &it));
-          ests[j - 1] = it.est;
-          known = j;
-          if (it.done) break;
-        }
-        // The residual estimate falls at least geometrically (usually
-        // faster).  When the rate of the last two steps brings iteration j
-        // within 50x of rtol, wait for it instead of queueing iteration j+1:
-        // an iteration queued after convergence still costs nine no-op kernel
-        // dispatches (~45 us), a wrong guess only a short idle gap (~15 us).
-        double prev;
-        if (j >= 2) {
-          prev = ests[j - 2];
-        } else {
-          volatile GSummary* r0 = hs + 2;
-          prev = (r0->seq == seq_res && r0->relres > 0.0) ? r0->relres : 1.0;
-        }
-        const double rate = prev > 0.0 ? ests[j - 1] / prev : 1.0;
-        if (j + 1 < m_eff && ests[j - 1] * rate < 50.0 * rtol) {
-          CN_TRY(wait_slot(h, hs + (j & 1), seqs[j], &it));
-          ests[j] = it.est;
-          known = j + 1;
-          if (it.done) break;
-        }
-      }
-    }
-    // y from the triangular factor (cycle summary -> slot 3), x += Z y, then
-    // the true residual (-> slot 2)
-    const int seq_fin = ++h->seqc;
-    HIP_TRY(launch_finish_update(st, h->Z, zf, h->npad, x, h->n, x_zero ? 1 : 0, hd + 3,
-                                 seq_fin, s));
-    x_zero = false;
-    seq_res = ++h->seqc;
-    HIP_TRY(launch_matvec(a, x, 0, b, h->V, 1, s, rtol, hd + 2, seq_res));
-    CN_TRY(wait_slot(h, hs + 3, seq_fin, &fin));
-    CN_TRY(wait_slot(h, hs + 2, seq_res, &cur));
-    const int k = fin.k;
-    if (k > 0) est = fin.est;
-    iters += k;
-    pcs += k;
-    matvecs += k + 1;
-    if (k == 0 || cur.relres <= rtol || iters >= opts->max_iters) break;
-    ++restarts;
-  }
-  if (cur.bnorm == 0.0) {
-    // b = 0: the solution is x = 0 whatever the initial guess
-    HIP_TRY(hipMemsetAsync(x, 0, h->n * sizeof(double), s));
-    cur.relres = 0.0;
-    est = 0.0;
-  }
-  HIP_TRY(hipStreamSynchronize(s));
-  const auto wall1 = std::chrono::steady_clock::now();
-  if (info != nullptr) {
-    info->iters = iters;
-    info->restarts = restarts;
-    info->matvecs = matvecs;
-    info->pc_applies = pcs;
-    info->relres_true = cur.relres;
-    info->relres_est = iters > 0 ? est : cur.relres;
-    info->seconds = std::chrono::duration<double>(wall1 - wall0).count();
-  }
-  return cur.relres <= rtol ? CN_OK : CN_NOT_CONVERGED;
+  SolveCtx c = handle_ctx(h);
+  return run_solve(c, b, x, opts, info, nullptr);
 }
 
 cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double* bytes) {
@@ -654,14 +883,9 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   const int zf = h->prec;
   const size_t zes = zf ? sizeof(float) : sizeof(double);
   const size_t rsz = h->prec ? sizeof(float) : sizeof(double);
-  const double* vj = h->V + (size_t)j * h->npad;
-  void* zj = (char*)h->Z + (size_t)j * h->npad * zes;
-  KArgs a = kargs(h);
-  a.nv = j + 1;
   // keep every kernel of the step active
   const int zero = 0;
   HIP_TRY(hipMemcpyAsync(&st->sum.done, &zero, sizeof(int), hipMemcpyHostToDevice, s));
-  const int* done = &st->sum.done;
   hipEvent_t ev[2];
   HIP_TRY(hipEventCreate(&ev[0]));
   HIP_TRY(hipEventCreate(&ev[1]));
@@ -680,15 +904,14 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
     hipError_t e = hipEventRecord(ev[0], s);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       switch (kk) {
-        case 0: e = pc_forward(pl, vj, &st->vscale[j], done, s); break;
-        case 1: e = pc_reduced(pl, done, s); break;
-        case 2: e = pc_inverse(pl, zj, zf, done, s); break;
+        case 0: e = pc_forward(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, j, nullptr, s); break;
+        case 1: e = pc_reduced(pl.prec, h->L, h->wl.I_k2, h->k2_thr, j, 0, s); break;
+        case 2: e = pc_inverse(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, j, nullptr, zf, s); break;
         // the three streaming Krylov kernels alone (their one-workgroup
         // finishing reductions are left out, so each entry is one kernel)
-        case 3: e = launch_matvec(a, zj, zf, nullptr, h->w, 2, s, 0.0, nullptr, 0, false); break;
-        case 4: e = launch_cgs(a, h->w, nullptr, j, -1, s, 1, 0.0, nullptr, 0, false); break;
-        case 5: e = launch_cgs(a, h->w, h->V + (size_t)(j + 1) * h->npad, j, 1 << 30, s, 2,
-                               0.0, nullptr, 0, false); break;
+        case 3: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 1, false); break;
+        case 4: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 2, false); break;
+        case 5: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 4, false); break;
       }
     }
     if (e == hipSuccess) e = hipEventRecord(ev[1], s);
@@ -703,7 +926,155 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
+  (void)zes;
   return rc;
+}
+
+// ---------------------------------------------------------------------------
+// batch entry points
+// ---------------------------------------------------------------------------
+cn_status cn_batch_create(const cn_problem* probs, int32_t count, cn_batch** out) {
+  if (out == nullptr) return fail(CN_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (probs == nullptr || count < 1) return fail(CN_EINVAL, "need at least one problem");
+  for (int i = 1; i < count; ++i) {
+    if (probs[i].pc_prec != probs[0].pc_prec)
+      return fail(CN_EINVAL, "all problems of a batch need the same pc_prec");
+    if (probs[i].stream != probs[0].stream)
+      return fail(CN_EINVAL, "all problems of a batch need the same stream");
+  }
+  cn_batch* b = new cn_batch();
+  b->stream = (hipStream_t)probs[0].stream;
+  b->prec = probs[0].pc_prec == CN_PC_FP32 ? 1 : 0;
+  b->inst.assign(count, nullptr);
+  // transform variant per N_t group: tuned on the group's widest instance
+  std::map<int, int> group_cand;  // log2 N_t -> candidate
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return probs[a].nx > probs[c].nx; });
+  for (int i : order) {
+    int l2 = 0;
+    while ((1 << l2) < probs[i].nt && l2 < 31) ++l2;
+    auto it = group_cand.find(l2);
+    cn_aao* h = nullptr;
+    const cn_status st = create_handle(&probs[i], it == group_cand.end() ? -1 : it->second, &h);
+    if (st != CN_OK) {
+      g_err = "problem " + std::to_string(i) + ": " + g_err;
+      batch_release(b);
+      return st;
+    }
+    b->inst[i] = h;
+    if (it == group_cand.end()) group_cand[l2] = h->pl.cand;
+  }
+  // packed offsets, descriptors and work lists
+  b->off.assign(count + 1, 0);
+  b->uoff.assign(count + 1, 0);
+  b->m_min = MMAX;
+  for (int i = 0; i < count; ++i) {
+    b->off[i + 1] = b->off[i] + b->inst[i]->n;
+    b->uoff[i + 1] = b->uoff[i] + b->inst[i]->nx;
+    b->m_min = std::min(b->m_min, b->inst[i]->m_max);
+  }
+  std::vector<InstDesc> desc(count);
+  std::vector<int2> k2, mv, stv;
+  std::map<int, std::vector<int2>> pcs;
+  int max_ns = 0;
+  for (int i = 0; i < count; ++i) {
+    desc[i] = b->inst[i]->desc;
+    desc[i].off = b->off[i];
+    append_items(desc[i], i, &pcs[b->inst[i]->pl.log2n], &k2, &mv, &stv);
+    max_ns = std::max(max_ns, desc[i].pl.NS);
+  }
+  hipError_t e = hipMalloc((void**)&b->d_desc, count * sizeof(InstDesc));
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_desc, desc.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = upload_items(k2, &b->wl.k2, &b->wl.I_k2);
+  if (e == hipSuccess) e = upload_items(mv, &b->wl.mv, &b->wl.I_mv);
+  if (e == hipSuccess) e = upload_items(stv, &b->wl.st, &b->wl.I_st);
+  for (auto& kv : pcs) {
+    if (e != hipSuccess) break;
+    int2* dptr = nullptr;
+    Items it;
+    e = upload_items(kv.second, &dptr, &it);
+    b->pc_lists.push_back(dptr);
+    b->groups.push_back(PcGroup{b->prec, kv.first, group_cand[kv.first], it});
+  }
+  b->k2_thr = k2_threads_for(max_ns);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->dcounter, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(b->dcounter, 0, sizeof(int));
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&b->bh, 3 * sizeof(GSummary),
+                      hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) {
+    memset(b->bh, 0, 3 * sizeof(GSummary));
+    e = hipHostGetDevicePointer((void**)&b->bh_dev, b->bh, 0);
+  }
+  if (e != hipSuccess) {
+    const cn_status st = fail(e == hipErrorOutOfMemory ? CN_ENOMEM : CN_EHIP,
+                              std::string("batch set-up: ") + hipGetErrorString(e));
+    batch_release(b);
+    return st;
+  }
+  *out = b;
+  return CN_OK;
+}
+
+cn_status cn_batch_destroy(cn_batch* b) {
+  if (b == nullptr) return fail(CN_EINVAL, "batch is NULL");
+  batch_release(b);
+  return CN_OK;
+}
+
+cn_status cn_batch_offsets(const cn_batch* b, int64_t* off, int64_t* space_off) {
+  if (b == nullptr) return fail(CN_EINVAL, "batch is NULL");
+  for (size_t i = 0; i < b->off.size(); ++i) {
+    if (off != nullptr) off[i] = b->off[i];
+    if (space_off != nullptr) space_off[i] = b->uoff[i];
+  }
+  return CN_OK;
+}
+
+cn_status cn_batch_rhs(cn_batch* b, const double* u0, const double* f, double* bp) {
+  if (b == nullptr || u0 == nullptr || f == nullptr || bp == nullptr)
+    return fail(CN_EINVAL, "NULL argument");
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    const cn_status st = cn_rhs(b->inst[i], u0 + b->uoff[i], f + b->off[i], bp + b->off[i]);
+    if (st != CN_OK) return st;
+  }
+  return CN_OK;
+}
+
+cn_status cn_batch_solve(cn_batch* b, const double* bp, double* xp, const cn_gmres_opts* opts,
+                         cn_gmres_info* infos, cn_gmres_info* total) {
+  if (b == nullptr || bp == nullptr || xp == nullptr || opts == nullptr)
+    return fail(CN_EINVAL, "NULL argument");
+  if (opts->m < 1 || opts->m > b->m_min)
+    return fail(CN_EINVAL, "opts->m must be in [1, smallest m_max of the batch]");
+  if (opts->max_iters < 1) return fail(CN_EINVAL, "opts->max_iters must be >= 1");
+  if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
+    return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
+  if (overlaps(bp, xp, b->off.back() * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
+  SolveCtx c;
+  c.s = b->stream;
+  c.L = Launch{b->d_desc, (int)b->inst.size(), b->prec};
+  c.groups = b->groups;
+  c.k2 = b->wl.I_k2;
+  c.mv = b->wl.I_mv;
+  c.stv = b->wl.I_st;
+  c.k2_thr = b->k2_thr;
+  c.prec = b->prec;
+  c.batched = true;
+  c.bh = b->bh;
+  c.bh_dev = b->bh_dev;
+  c.dcounter = b->dcounter;
+  c.bseq = &b->bseq;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    c.inst_host.push_back(b->inst[i]->hsum);
+    c.off.push_back(b->off[i]);
+    c.len.push_back(b->inst[i]->n);
+  }
+  return run_solve(c, bp, xp, opts, infos, total);
 }
 
 }  // extern "C"

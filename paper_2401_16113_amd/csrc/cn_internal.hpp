@@ -36,7 +36,8 @@ struct PcPlan {
   void* sep = nullptr;                                  // [F][NS]
 };
 
-// Scalars the host driver polls (copied to pinned host memory).
+// Scalars the host driver polls (written by kernels into pinned host memory).
+// A batch summary reuses the layout: k = instances still iterating.
 struct GSummary {
   double bnorm;   // ||b||
   double beta;    // ||b - M x|| at the start of the current cycle
@@ -60,45 +61,79 @@ struct GState {
   double y[MMAX];
 };
 
-// Launchers (cn_pc.hip)
+// Everything a kernel needs to know about one instance.  Kernels receive an
+// array of these plus a work list of (instance, block) items, so one launch
+// serves one instance (a handle) or many (a batch).
+struct InstDesc {
+  PcPlan pl;              // transform tables and preconditioner workspace
+  const double* dw;       // time weights d_k or null
+  int nx, nt;
+  int rows;               // time levels per matvec workgroup
+  int mv_cols;            // column blocks of the matvec
+  int mv_grid;            // matvec workgroups (partials per dot)
+  int st_grid;            // workgroups of the streaming passes
+  long long n;            // unknowns
+  long long vstride;      // elements between basis vectors
+  long long off;          // offset of the instance in packed b / x arrays
+  double* V;              // basis (m_max + 1 vectors)
+  void* Z;                // preconditioned vectors (float64 or float32)
+  double* w;              // matvec output
+  double* partials;       // per-workgroup partial sums [q][block]
+  GState* st;             // solver state
+  GSummary* host;         // the instance's summary slot in pinned host memory
+  int zf;                 // Z stored in float32
+  int pad;
+};
+
+// Launch context shared by the kernels of one handle or batch.
+struct Launch {
+  const InstDesc* D;      // device array of descriptors
+  int ninst;
+  int zf;                 // preconditioned vectors stored in float32 (all instances)
+};
+
+// Work list of one kernel kind: items[i] = (instance, local block).
+struct Items {
+  const int2* it = nullptr;
+  int n = 0;
+};
+
+// Launchers (cn_pc.hip, cn_pc_f64.hip, cn_pc_f32.hip).  `v`/`z` override the
+// basis vector V_j / Z_j of a single instance (standalone apply, no stop flag).
 hipError_t pc_setup(PcPlan& pl, Cx<double>* spk, int* err_dev, hipStream_t s);
-hipError_t pc_forward(const PcPlan& pl, const double* v, const double* scale_dev,
-                      const int* done, hipStream_t s);
-hipError_t pc_reduced(const PcPlan& pl, const int* done, hipStream_t s);
-hipError_t pc_inverse(const PcPlan& pl, void* z, int z_is_float, const int* done,
-                      hipStream_t s);
+hipError_t pc_forward(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
+                      const double* v, hipStream_t s);
+hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int threads, int j,
+                      int standalone, hipStream_t s);
+hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
+                      void* z, int zf, hipStream_t s);
 // (B, T) of compiled candidate `ci`; false if that candidate is not compiled
 bool pc_candidate(int prec, int log2n, int ci, int* B, int* T);
 
 // Krylov launchers (cn_krylov.hip)
-struct KArgs {
-  const double* lo;       // tau*A rows
-  const double* di;
-  const double* up;
-  const double* dw;       // time weights d_k or null
-  int nx, nt;
-  int rows;               // time levels per matvec workgroup
-  long long n;
-  const double* V;        // basis base pointer
-  long long vstride;      // elements between basis vectors
-  int nv;                 // vectors taking part
-  GState* st;
-  double* partials;       // [grid][NVMAX]
-};
 constexpr int KGRID = 2048;  // target number of workgroups of a streaming pass
 int matvec_rows(int nx, int nt);
-// mode 0: y = M x; 1: y = b - M x + norms (finish: cycle start, summary to
-// `host`); 2: y = M x + first Gram-Schmidt dots
-hipError_t launch_matvec(const KArgs& a, const void* x, int x_is_float, const double* b,
-                         double* y, int mode, hipStream_t s, double rtol = 0.0,
-                         GSummary* host = nullptr, int seq = 0, bool finish = true);
-// passes: 1 = second Gram-Schmidt dots, 2 = update + norm + Givens, 3 = both
-hipError_t launch_cgs(const KArgs& a, const double* w, double* vout, int j, int stop_iter,
-                      hipStream_t s, int passes = 3, double rtol = 0.0,
-                      GSummary* host = nullptr, int seq = 0, bool finish = true);
-hipError_t launch_finish_update(GState* st, const void* Z, int z_is_float, long long zstride,
-                                double* x, long long n, int x_zero, GSummary* host, int seq,
-                                hipStream_t s);
+int stream_grid(long long n);
+// y = M x for one instance (standalone matvec)
+hipError_t launch_matvec_plain(const Launch& L, const Items& mv, const double* x, double* y,
+                               hipStream_t s);
+// r = b - M x into V_0 of every instance (x = 0 is not read when x_zero), then
+// the per-instance cycle start (norms, stop flag, summary to the host slot)
+hipError_t launch_residual(const Launch& L, const Items& mv, const double* b_base,
+                           double* x_base, int x_zero, double rtol, int slot, int seq,
+                           hipStream_t s);
+// one inner iteration's Krylov part: w = M z_j with the first dots, the two
+// CGS2 passes and the Givens update (`finish` = false leaves out the
+// finishing kernels, for timing the streaming kernels alone)
+// passes: bit 0 matvec + first dots, bit 1 second dots, bit 2 update + norm
+hipError_t launch_arnoldi(const Launch& L, const Items& mv, const Items& stv, int j, int stop_iter,
+                          double rtol, int slot, int seq, hipStream_t s, int passes = 7,
+                          bool finish = true);
+// end of a cycle: triangular solve, x += Z y
+hipError_t launch_cycle_end(const Launch& L, const Items& stv, double* x_base, int x_zero,
+                            int slot, int seq, hipStream_t s);
+// publish the number of instances still iterating (batch polling)
+hipError_t launch_batch_summary(const Launch& L, int* counter, GSummary* host, hipStream_t s);
 hipError_t launch_rhs(const double* lo, const double* di, const double* up, const double* dw,
                       double tau, const double* u0, const double* f, double* b, int nx,
                       long long n, hipStream_t s);

@@ -4,14 +4,16 @@
 //   * the two remaining CGS2 passes (dots against the stored basis, update,
 //     norm) -- the basis is stored unnormalised with a float64 scale per
 //     vector, so normalisation never costs a pass;
-//   * the Givens / least-squares update, done by the last workgroup of the
-//     final pass (no host round-trip inside a cycle);
+//   * the Givens / least-squares update (one workgroup per instance);
 //   * x += Z y and the right-hand side b = xi + tau f (eq. (2.2)).
-// Reductions are deterministic: every workgroup of a streaming pass writes
-// its partial sums; a one-workgroup finishing kernel adds them in a fixed
-// order and updates the solver state.  Stream order makes the partials
-// visible, so no workgroup issues a device-scope fence (on a multi-XCD part
-// such a fence writes back and invalidates the XCD's L2).
+// Every kernel serves a list of instances: work items (instance, block) index
+// an array of instance descriptors, so a single solve and a batch of uneven
+// solves share one code path and one launch per step.
+// Reductions are deterministic: every workgroup writes its partial sums; a
+// finishing kernel (one workgroup per instance) adds them in a fixed order
+// and updates the solver state.  Stream order makes the partials visible,
+// so no workgroup issues a device-scope fence (on a multi-XCD part such a
+// fence writes back and invalidates the XCD's L2).
 #include <math.h>
 
 #include "cn_internal.hpp"
@@ -29,7 +31,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Block-reduce NV accumulators into partials[q*nblk + blk] (fixed order).
 template <int NV>
 __device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, double* red,
-                                               double* partials, int blk) {
+                                               double* partials, int blk, int nblk) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -43,14 +45,14 @@ __device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, 
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < KT / 64; ++w) s += red[w * NV + tid];
-    partials[(size_t)tid * gridDim.x + blk] = s;
+    partials[(size_t)tid * nblk + blk] = s;
   }
 }
 
 // Sum partials[q*nblk + b] over b for q < nv into out[q]: wave w handles
 // q = w, w + 16, ...; lane l adds b = l, l + 64, ... then the wave adds its
 // lanes.  The order is fixed, so the result is bitwise reproducible.
-constexpr int FT = 1024;  // threads of a finishing kernel
+constexpr int FT = 1024;    // threads of a finishing kernel
 constexpr int FCHUNK = 32;  // partials per lane loaded back to back
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int nblk,
                                                 int nv, double* out) {
@@ -74,8 +76,8 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ parti
   __syncthreads();
 }
 
-// Publish the summary to the host slot: fields first, then (after a
-// system-scope fence) the sequence number the host polls for.
+// Publish a summary to a host slot: fields first, then (after a system-scope
+// fence) the sequence number the host polls for.
 __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int seq) {
   if (host == nullptr) return;
   host->bnorm = sm.bnorm;
@@ -90,27 +92,48 @@ __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int 
 }
 
 // ---------------------------------------------------------------------------
-// matvec: y = M x (MODE 0), y = b - M x with norms (MODE 1),
-//         y = M x with dots against V_0..V_{nv-1} (MODE 2, first CGS pass)
+// matvec: y = M x (MODE 0, one instance: x = xo, y = yo),
+//         r = b - M x into V_0 with ||r||^2, ||b||^2 (MODE 1: x = xo + off,
+//         unread when x_zero; b = bo + off),
+//         w = M z_j with dots against V_0..V_j (MODE 2, first CGS pass)
+// Each thread marches down the time levels of one spatial column.
 // ---------------------------------------------------------------------------
 template <typename TX, int MODE, int NV>
-__global__ __launch_bounds__(KT) void k_matvec(KArgs a, const TX* __restrict__ x,
-                                               const double* __restrict__ b,
-                                               double* __restrict__ y) {
-  __shared__ double red[(KT / 64) * (NV > 2 ? NV : 2)];
-  GState* st = a.st;
-  if (MODE == 2 && st->sum.done) return;
-  const int nx = a.nx;
-  const int col_blocks = (nx + KT - 1) / KT;
-  const int blk = blockIdx.x;
-  const int cb = blk % col_blocks, rb = blk / col_blocks;
+__global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
+                                               const int2* __restrict__ items, int j,
+                                               const TX* __restrict__ xo,
+                                               const double* __restrict__ bo,
+                                               double* __restrict__ yo, int x_zero) {
+  constexpr int NA = NV > 2 ? NV : 2;
+  __shared__ double red[(KT / 64) * NA];
+  const int2 wi = items[blockIdx.x];
+  const InstDesc& d = D[wi.x];
+  if (MODE == 2 && d.st->sum.done) return;
+  const TX* __restrict__ x;
+  const double* __restrict__ b = nullptr;
+  double* __restrict__ y;
+  if (MODE == 0) {
+    x = xo;
+    y = yo;
+  } else if (MODE == 1) {
+    x = x_zero ? nullptr : xo + d.off;
+    b = bo + d.off;
+    y = d.V;
+  } else {
+    x = (const TX*)d.Z + (size_t)j * d.vstride;
+    y = d.w;
+  }
+  const int nv = j + 1;
+  const int nx = d.nx;
+  const int blk = wi.y;
+  const int cb = blk % d.mv_cols, rb = blk / d.mv_cols;
   const int i = cb * KT + threadIdx.x;
-  const int k0 = rb * a.rows, k1 = min(a.nt, k0 + a.rows);
-  double acc[NV > 2 ? NV : 2];
+  const int k0 = rb * d.rows, k1 = min(d.nt, k0 + d.rows);
+  double acc[NA];
 #pragma unroll
-  for (int q = 0; q < (NV > 2 ? NV : 2); ++q) acc[q] = 0.0;
+  for (int q = 0; q < NA; ++q) acc[q] = 0.0;
   if (i < nx) {
-    const double lo = a.lo[i], di = a.di[i], up = a.up[i];
+    const double lo = d.pl.lo[i], di = d.pl.di[i], up = d.pl.up[i];
     const bool hl = i > 0, hr = i < nx - 1;
     double pm = 0.0, pc = 0.0, pp = 0.0;  // previous level at i-1, i, i+1
     if (k0 > 0 && x != nullptr) {
@@ -127,7 +150,7 @@ __global__ __launch_bounds__(KT) void k_matvec(KArgs a, const TX* __restrict__ x
         if (hl) cm = (double)x[off + i - 1];
         if (hr) cp = (double)x[off + i + 1];
       }
-      const double w = a.dw != nullptr ? a.dw[k] : 1.0;
+      const double w = d.dw != nullptr ? d.dw[k] : 1.0;
       // (M x)^k = (x^k - x^{k-1}) - (w/2) A~ (x^k + x^{k-1})
       const double sm = cm + pm, s0 = cc + pc, sp = cp + pp;
       const double ax = lo * sm + di * s0 + up * sp;
@@ -142,7 +165,7 @@ __global__ __launch_bounds__(KT) void k_matvec(KArgs a, const TX* __restrict__ x
       if (MODE == 2) {
 #pragma unroll
         for (int q = 0; q < NV; ++q)
-          if (q < a.nv) acc[q] += a.V[(size_t)q * a.vstride + off + i] * yv;
+          if (q < nv) acc[q] += d.V[(size_t)q * d.vstride + off + i] * yv;
       }
       pm = cm;
       pc = cc;
@@ -150,85 +173,99 @@ __global__ __launch_bounds__(KT) void k_matvec(KArgs a, const TX* __restrict__ x
     }
   }
   if (MODE == 0) return;
-  const int nacc = MODE == 1 ? 2 : a.nv;
-  block_partials<(NV > 2 ? NV : 2)>(acc, nacc, red, a.partials, blk);
+  block_partials<NA>(acc, MODE == 1 ? 2 : nv, red, d.partials, blk, d.mv_grid);
 }
 
 // ---------------------------------------------------------------------------
-// CGS2 second pass: h2 = V^T (w - V c1)
+// CGS2 second pass: h2 = V^T (w - V c1), w - V c1 is never stored
 // ---------------------------------------------------------------------------
 template <int NV>
-__global__ __launch_bounds__(KT) void k_cgs_pass1(KArgs a, const double* __restrict__ w) {
+__global__ __launch_bounds__(KT) void k_cgs_pass1(const InstDesc* __restrict__ D,
+                                                  const int2* __restrict__ items, int j) {
   __shared__ double red[(KT / 64) * NV];
-  GState* st = a.st;
+  const int2 wi = items[blockIdx.x];
+  const InstDesc& d = D[wi.x];
+  const GState* st = d.st;
   if (st->sum.done) return;
+  const int nv = j + 1;
   double c[NV], acc[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    c[q] = q < a.nv ? st->c1[q] : 0.0;
+    c[q] = q < nv ? st->c1[q] : 0.0;
     acc[q] = 0.0;
   }
-  const long long stride = (long long)gridDim.x * KT;
-  for (long long e = (long long)blockIdx.x * KT + threadIdx.x; e < a.n; e += stride) {
+  const double* __restrict__ w = d.w;
+  const double* __restrict__ V = d.V;
+  const long long stride = (long long)d.st_grid * KT;
+  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.n; e += stride) {
     double vq[NV];
     double wv = w[e];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      vq[q] = q < a.nv ? a.V[(size_t)q * a.vstride + e] : 0.0;
+      vq[q] = q < nv ? V[(size_t)q * d.vstride + e] : 0.0;
       wv -= c[q] * vq[q];
     }
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] += vq[q] * wv;
   }
-  block_partials<NV>(acc, a.nv, red, a.partials, blockIdx.x);
+  block_partials<NV>(acc, nv, red, d.partials, wi.y, d.st_grid);
 }
 
 // ---------------------------------------------------------------------------
-// CGS2 update: v_{j+1} = w - V (c1 + c2), its norm, the Hessenberg column,
-// Givens rotations and the residual estimate (last workgroup).
+// CGS2 update: v_{j+1} = w - V (c1 + c2) and its norm
 // ---------------------------------------------------------------------------
 template <int NV>
-__global__ __launch_bounds__(KT) void k_cgs_pass2(KArgs a, const double* __restrict__ w,
-                                                  double* __restrict__ vout) {
+__global__ __launch_bounds__(KT) void k_cgs_pass2(const InstDesc* __restrict__ D,
+                                                  const int2* __restrict__ items, int j) {
   __shared__ double red[(KT / 64) * 2];
-  GState* st = a.st;
+  const int2 wi = items[blockIdx.x];
+  const InstDesc& d = D[wi.x];
+  const GState* st = d.st;
   if (st->sum.done) return;
+  const int nv = j + 1;
   double c[NV];
 #pragma unroll
-  for (int q = 0; q < NV; ++q) c[q] = q < a.nv ? st->c1[q] + st->c2[q] : 0.0;
+  for (int q = 0; q < NV; ++q) c[q] = q < nv ? st->c1[q] + st->c2[q] : 0.0;
   double acc[2] = {0.0, 0.0};
-  const long long stride = (long long)gridDim.x * KT;
-  for (long long e = (long long)blockIdx.x * KT + threadIdx.x; e < a.n; e += stride) {
+  const double* __restrict__ w = d.w;
+  const double* __restrict__ V = d.V;
+  double* __restrict__ vout = d.V + (size_t)(j + 1) * d.vstride;
+  const long long stride = (long long)d.st_grid * KT;
+  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.n; e += stride) {
     double wv = w[e];
 #pragma unroll
     for (int q = 0; q < NV; ++q)
-      if (q < a.nv) wv -= c[q] * a.V[(size_t)q * a.vstride + e];
+      if (q < nv) wv -= c[q] * V[(size_t)q * d.vstride + e];
     vout[e] = wv;
     acc[0] += wv * wv;
   }
-  block_partials<2>(acc, 1, red, a.partials, blockIdx.x);
+  block_partials<2>(acc, 1, red, d.partials, wi.y, d.st_grid);
 }
 
 // ---------------------------------------------------------------------------
-// finishing kernels (one workgroup): fixed-order sums of the partials
-// ---------------------------------------------------------------------------
+// finishing kernels, one workgroup per instance (blockIdx.x):
 // FIN 1: residual r = b - M x -> ||b||, beta, v_0 scale, g, relres, stop flag
 // FIN 2: first Gram-Schmidt dots -> h1, c1
 // FIN 3: second Gram-Schmidt dots -> h2, c2
 // FIN 4: ||v_{j+1}|| -> Hessenberg column, Givens rotation, residual estimate
+// FIN 1 and FIN 4 publish the summary to host slot `slot` of the instance.
+// ---------------------------------------------------------------------------
 template <int FIN>
-__global__ __launch_bounds__(FT) void k_finish(GState* __restrict__ st,
-                                               const double* __restrict__ partials, int nblk,
-                                               int nv, int j, int stop_iter, double rtol,
-                                               GSummary* __restrict__ host, int seq) {
+__global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, int j,
+                                               int stop_iter, double rtol, int slot, int seq) {
   __shared__ double out[NVMAX];
+  const InstDesc& d = D[blockIdx.x];
+  GState* st = d.st;
+  GSummary* host = d.host != nullptr ? d.host + slot : nullptr;
   if (FIN != 1 && st->sum.done) {
     // the cycle already stopped: still tell a polling host so
     if (FIN == 4 && threadIdx.x == 0) publish(host, st->sum, seq);
     return;
   }
+  const int nv = j + 1;
   const int nq = FIN == 1 ? 2 : (FIN == 4 ? 1 : nv);
-  reduce_partials(partials, nblk, nq, out);
+  const int nblk = (FIN == 1 || FIN == 2) ? d.mv_grid : d.st_grid;
+  reduce_partials(d.partials, nblk, nq, out);
   if (threadIdx.x != 0) return;
   GSummary& sm = st->sum;
   if (FIN == 1) {
@@ -287,30 +324,39 @@ __global__ __launch_bounds__(FT) void k_finish(GState* __restrict__ st,
   }
 }
 
-// End of a cycle: solve the k x k triangular system R y = g; copy the
-// cycle's summary (k, estimate) to the host slot.
-__global__ void k_cycle_finish(GState* st, GSummary* host, int seq) {
-  if (threadIdx.x != 0) return;
-  publish(host, st->sum, seq);
+// End of a cycle, one thread per instance: solve R y = g (k x k upper
+// triangular) and publish the cycle's summary (k, estimate) to host slot.
+__global__ void k_cycle_finish(const InstDesc* __restrict__ D, int ninst, int slot, int seq) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= ninst) return;
+  const InstDesc& d = D[inst];
+  GState* st = d.st;
+  publish(d.host != nullptr ? d.host + slot : nullptr, st->sum, seq);
   const int k = st->sum.k;
   for (int q = k - 1; q >= 0; --q) {
     double s = st->g[q];
     for (int r = q + 1; r < k; ++r) s -= st->H[r * (MMAX + 1) + q] * st->y[r];
-    const double d = st->H[q * (MMAX + 1) + q];
-    st->y[q] = d != 0.0 ? s / d : 0.0;
+    const double dd = st->H[q * (MMAX + 1) + q];
+    st->y[q] = dd != 0.0 ? s / dd : 0.0;
   }
 }
 
-// x += sum_q y_q z_q
+// x += sum_q y_q z_q (x = sum_q y_q z_q when the initial guess was zero)
 template <typename TZ>
-__global__ __launch_bounds__(KT) void k_update(const GState* __restrict__ st,
-                                               const TZ* __restrict__ Z, long long zstride,
-                                               double* __restrict__ x, long long n,
-                                               int x_zero) {
+__global__ __launch_bounds__(KT) void k_update(const InstDesc* __restrict__ D,
+                                               const int2* __restrict__ items,
+                                               double* __restrict__ xb, int x_zero) {
+  const int2 wi = items[blockIdx.x];
+  const InstDesc& d = D[wi.x];
+  const GState* st = d.st;
   const int k = st->sum.k;
+  if (k == 0 && !x_zero) return;
   const double* y = st->y;
-  const long long stride = (long long)gridDim.x * KT;
-  for (long long e = (long long)blockIdx.x * KT + threadIdx.x; e < n; e += stride) {
+  const TZ* __restrict__ Z = (const TZ*)d.Z;
+  double* __restrict__ x = xb + d.off;
+  const long long zstride = d.vstride;
+  const long long stride = (long long)d.st_grid * KT;
+  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.n; e += stride) {
     double s = x_zero ? 0.0 : x[e];
     int q = 0;
     for (; q + 4 <= k; q += 4) {
@@ -321,6 +367,41 @@ __global__ __launch_bounds__(KT) void k_update(const GState* __restrict__ st,
     }
     for (; q < k; ++q) s += y[q] * (double)Z[(size_t)q * zstride + e];
     x[e] = s;
+  }
+}
+
+// Number of instances still iterating, published with a sequence number
+// taken from a device counter (so the launch has no per-call arguments).
+__global__ __launch_bounds__(256) void k_batch_summary(const InstDesc* __restrict__ D,
+                                                       int ninst, int* __restrict__ counter,
+                                                       GSummary* __restrict__ host) {
+  __shared__ int s_active[256];
+  __shared__ double s_est[256];
+  int act = 0;
+  double est = 0.0;
+  for (int i = threadIdx.x; i < ninst; i += 256) {
+    const GSummary& sm = D[i].st->sum;
+    if (!sm.done) act += 1;
+    est = fmax(est, sm.est);
+  }
+  s_active[threadIdx.x] = act;
+  s_est[threadIdx.x] = est;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      s_active[threadIdx.x] += s_active[threadIdx.x + off];
+      s_est[threadIdx.x] = fmax(s_est[threadIdx.x], s_est[threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int seq = *counter + 1;
+    *counter = seq;
+    GSummary sm{};
+    sm.k = s_active[0];
+    sm.est = s_est[0];
+    sm.done = s_active[0] == 0 ? 1 : 0;
+    publish(host, sm, seq);
   }
 }
 
@@ -363,11 +444,6 @@ int matvec_rows(int nx, int nt) {
   return (nt + rb - 1) / rb;
 }
 
-int matvec_grid(int nx, int nt) {
-  const int rows = matvec_rows(nx, nt);
-  return ((nx + KT - 1) / KT) * ((nt + rows - 1) / rows);
-}
-
 int stream_grid(long long n) {
   long long g = (n + KT * 4 - 1) / (KT * 4);
   if (g > KGRID) g = KGRID;
@@ -375,82 +451,76 @@ int stream_grid(long long n) {
   return (int)g;
 }
 
-hipError_t launch_matvec(const KArgs& a, const void* x, int x_is_float, const double* b,
-                         double* y, int mode, hipStream_t s, double rtol, GSummary* host,
-                         int seq, bool finish) {
-  const int grid = ((a.nx + KT - 1) / KT) * ((a.nt + a.rows - 1) / a.rows);
-  if (mode == 0) {
-    if (x_is_float)
-      hipLaunchKernelGGL((k_matvec<float, 0, 2>), dim3(grid), dim3(KT), 0, s, a, (const float*)x, b, y);
-    else
-      hipLaunchKernelGGL((k_matvec<double, 0, 2>), dim3(grid), dim3(KT), 0, s, a, (const double*)x, b, y);
-    return hipGetLastError();
-  }
-  if (mode == 1) {
-    hipLaunchKernelGGL((k_matvec<double, 1, 2>), dim3(grid), dim3(KT), 0, s, a, (const double*)x, b, y);
-    hipLaunchKernelGGL((k_finish<1>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, 2, 0, 0,
-                       rtol, host, seq);
-    return hipGetLastError();
-  }
-  const int bk = nv_bucket(a.nv);
-#define MV(NVB)                                                                                    \
-  case NVB:                                                                                        \
-    if (x_is_float)                                                                                \
-      hipLaunchKernelGGL((k_matvec<float, 2, NVB>), dim3(grid), dim3(KT), 0, s, a, (const float*)x, b, y); \
-    else                                                                                           \
-      hipLaunchKernelGGL((k_matvec<double, 2, NVB>), dim3(grid), dim3(KT), 0, s, a, (const double*)x, b, y); \
-    break;
-  switch (bk) {
-    MV(1) MV(2) MV(4) MV(8) MV(16) MV(32) MV(64)
-    default:
-      return hipErrorInvalidValue;
-  }
-#undef MV
-  if (finish)
-    hipLaunchKernelGGL((k_finish<2>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, a.nv, 0,
-                       0, rtol, nullptr, 0);
+hipError_t launch_matvec_plain(const Launch& L, const Items& mv, const double* x, double* y,
+                               hipStream_t s) {
+  hipLaunchKernelGGL((k_matvec<double, 0, 2>), dim3(mv.n), dim3(KT), 0, s, L.D, mv.it, 0, x,
+                     nullptr, y, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_cgs(const KArgs& a, const double* w, double* vout, int j, int stop_iter,
-                      hipStream_t s, int passes, double rtol, GSummary* host, int seq,
-                      bool finish) {
-  const int grid = stream_grid(a.n);
-  const int bk = nv_bucket(a.nv);
-  if ((passes & 2) && vout == nullptr) return hipErrorInvalidValue;
+hipError_t launch_residual(const Launch& L, const Items& mv, const double* b_base,
+                           double* x_base, int x_zero, double rtol, int slot, int seq,
+                           hipStream_t s) {
+  hipLaunchKernelGGL((k_matvec<double, 1, 2>), dim3(mv.n), dim3(KT), 0, s, L.D, mv.it, 0,
+                     (const double*)x_base, b_base, nullptr, x_zero);
+  hipLaunchKernelGGL((k_finish<1>), dim3(L.ninst), dim3(FT), 0, s, L.D, 0, 0, rtol, slot, seq);
+  return hipGetLastError();
+}
+
+hipError_t launch_arnoldi(const Launch& L, const Items& mv, const Items& stv, int j, int stop_iter,
+                          double rtol, int slot, int seq, hipStream_t s, int passes,
+                          bool finish) {
+  const int bk = nv_bucket(j + 1);
   switch (bk) {
-#define CG(NVB)                                                                            \
-  case NVB:                                                                                \
-    if (passes & 1) {                                                                      \
-      hipLaunchKernelGGL((k_cgs_pass1<NVB>), dim3(grid), dim3(KT), 0, s, a, w);            \
-      if (finish)                                                                          \
-        hipLaunchKernelGGL((k_finish<3>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, \
-                           a.nv, j, stop_iter, rtol, nullptr, 0);                          \
-    }                                                                                      \
-    if (passes & 2) {                                                                      \
-      hipLaunchKernelGGL((k_cgs_pass2<NVB>), dim3(grid), dim3(KT), 0, s, a, w, vout);      \
-      if (finish)                                                                          \
-        hipLaunchKernelGGL((k_finish<4>), dim3(1), dim3(FT), 0, s, a.st, a.partials, grid, \
-                           a.nv, j, stop_iter, rtol, host, seq);                           \
-    }                                                                                      \
+#define AR(NVB)                                                                               \
+  case NVB:                                                                                   \
+    if (passes & 1) {                                                                         \
+      if (L.zf)                                                                               \
+        hipLaunchKernelGGL((k_matvec<float, 2, NVB>), dim3(mv.n), dim3(KT), 0, s, L.D, mv.it, \
+                           j, (const float*)nullptr, nullptr, nullptr, 0);                    \
+      else                                                                                    \
+        hipLaunchKernelGGL((k_matvec<double, 2, NVB>), dim3(mv.n), dim3(KT), 0, s, L.D,       \
+                           mv.it, j, (const double*)nullptr, nullptr, nullptr, 0);            \
+      if (finish)                                                                             \
+        hipLaunchKernelGGL((k_finish<2>), dim3(L.ninst), dim3(FT), 0, s, L.D, j, stop_iter,  \
+                           rtol, slot, seq);                                                  \
+    }                                                                                         \
+    if (passes & 2) {                                                                         \
+      hipLaunchKernelGGL((k_cgs_pass1<NVB>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, j);    \
+      if (finish)                                                                             \
+        hipLaunchKernelGGL((k_finish<3>), dim3(L.ninst), dim3(FT), 0, s, L.D, j, stop_iter,  \
+                           rtol, slot, seq);                                                  \
+    }                                                                                         \
+    if (passes & 4) {                                                                         \
+      hipLaunchKernelGGL((k_cgs_pass2<NVB>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, j);    \
+      if (finish)                                                                             \
+        hipLaunchKernelGGL((k_finish<4>), dim3(L.ninst), dim3(FT), 0, s, L.D, j, stop_iter,  \
+                           rtol, slot, seq);                                                  \
+    }                                                                                         \
     break;
-    CG(1) CG(2) CG(4) CG(8) CG(16) CG(32) CG(64)
-#undef CG
+    AR(1) AR(2) AR(4) AR(8) AR(16) AR(32) AR(64)
+#undef AR
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_finish_update(GState* st, const void* Z, int z_is_float, long long zstride,
-                                double* x, long long n, int x_zero, GSummary* host, int seq,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_finish, dim3(1), dim3(64), 0, s, st, host, seq);
-  const int grid = stream_grid(n);
-  if (z_is_float)
-    hipLaunchKernelGGL((k_update<float>), dim3(grid), dim3(KT), 0, s, st, (const float*)Z, zstride, x, n, x_zero);
+hipError_t launch_cycle_end(const Launch& L, const Items& stv, double* x_base, int x_zero,
+                            int slot, int seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_finish, dim3((L.ninst + 63) / 64), dim3(64), 0, s, L.D, L.ninst,
+                     slot, seq);
+  if (L.zf)
+    hipLaunchKernelGGL((k_update<float>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, x_base,
+                       x_zero);
   else
-    hipLaunchKernelGGL((k_update<double>), dim3(grid), dim3(KT), 0, s, st, (const double*)Z, zstride, x, n, x_zero);
+    hipLaunchKernelGGL((k_update<double>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, x_base,
+                       x_zero);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_summary(const Launch& L, int* counter, GSummary* host, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_summary, dim3(1), dim3(256), 0, s, L.D, L.ninst, counter, host);
   return hipGetLastError();
 }
 

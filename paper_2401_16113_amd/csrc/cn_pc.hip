@@ -60,15 +60,24 @@ __device__ __forceinline__ void affine_scan(Cx<double>& A, Cx<double>& Bv, Cx<do
 }
 
 template <typename R>
-__global__ __launch_bounds__(K2_THREADS) void k_pc_reduced(
-    const Cx<R>* __restrict__ iface, Cx<R>* __restrict__ sep,
-    const Cx<double>* __restrict__ ra, const Cx<double>* __restrict__ rap,
-    const Cx<double>* __restrict__ rinv, Cx<double>* __restrict__ rtmp,
-    const double* __restrict__ lo, const double* __restrict__ up, int P, int NS, int B,
-    const int* __restrict__ done) {
+__global__ __launch_bounds__(K2_THREADS) void k_pc_reduced(const InstDesc* __restrict__ D,
+                                                           const int2* __restrict__ items,
+                                                           int standalone) {
   __shared__ Cx<double> sA[K2_THREADS], sB[K2_THREADS];
-  if (done != nullptr && *done) return;
-  const int j = blockIdx.x;
+  const int2 wi = items[blockIdx.x];
+  const InstDesc& d = D[wi.x];
+  const PcPlan& pl = d.pl;
+  if (!standalone && d.st->sum.done) return;
+  const Cx<R>* __restrict__ iface = (const Cx<R>*)pl.iface;
+  Cx<R>* __restrict__ sep = (Cx<R>*)pl.sep;
+  const Cx<double>* __restrict__ ra = pl.red_a;
+  const Cx<double>* __restrict__ rap = pl.red_ap;
+  const Cx<double>* __restrict__ rinv = pl.red_inv;
+  Cx<double>* __restrict__ rtmp = pl.red_tmp;
+  const double* __restrict__ lo = pl.lo;
+  const double* __restrict__ up = pl.up;
+  const int P = pl.P, NS = pl.NS, B = pl.B;
+  const int j = wi.y;
   const int tid = threadIdx.x, n = blockDim.x;
   const int chunk = (NS + n - 1) / n;
   const int s0 = min(NS, tid * chunk), s1 = min(NS, s0 + chunk);
@@ -226,10 +235,10 @@ __global__ void k_setup_reduced(const double* __restrict__ lo, const double* __r
 // ---------------------------------------------------------------------------
 // launchers: the transform kernels live in cn_pc_f64.hip / cn_pc_f32.hip
 // ---------------------------------------------------------------------------
-hipError_t pc_forward_f64(const PcPlan&, const double*, const double*, const int*, hipStream_t);
-hipError_t pc_forward_f32(const PcPlan&, const double*, const double*, const int*, hipStream_t);
-hipError_t pc_inverse_f64(const PcPlan&, void*, int, const int*, hipStream_t);
-hipError_t pc_inverse_f32(const PcPlan&, void*, int, const int*, hipStream_t);
+hipError_t pc_forward_f64(int, int, const Launch&, const Items&, int, const double*, hipStream_t);
+hipError_t pc_forward_f32(int, int, const Launch&, const Items&, int, const double*, hipStream_t);
+hipError_t pc_inverse_f64(int, int, const Launch&, const Items&, int, void*, int, hipStream_t);
+hipError_t pc_inverse_f32(int, int, const Launch&, const Items&, int, void*, int, hipStream_t);
 bool pc_candidate_f64(int log2n, int ci, int* B, int* T);
 bool pc_candidate_f32(int log2n, int ci, int* B, int* T);
 
@@ -237,27 +246,28 @@ bool pc_candidate(int prec, int log2n, int ci, int* B, int* T) {
   return prec ? pc_candidate_f32(log2n, ci, B, T) : pc_candidate_f64(log2n, ci, B, T);
 }
 
-hipError_t pc_forward(const PcPlan& pl, const double* v, const double* scale, const int* done,
-                      hipStream_t s) {
-  return pl.prec ? pc_forward_f32(pl, v, scale, done, s) : pc_forward_f64(pl, v, scale, done, s);
+hipError_t pc_forward(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
+                      const double* v, hipStream_t s) {
+  return prec ? pc_forward_f32(log2n, cand, L, it, j, v, s)
+              : pc_forward_f64(log2n, cand, L, it, j, v, s);
 }
 
-hipError_t pc_inverse(const PcPlan& pl, void* z, int zf, const int* done, hipStream_t s) {
-  return pl.prec ? pc_inverse_f32(pl, z, zf, done, s) : pc_inverse_f64(pl, z, zf, done, s);
+hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
+                      void* z, int zf, hipStream_t s) {
+  return prec ? pc_inverse_f32(log2n, cand, L, it, j, z, zf, s)
+              : pc_inverse_f64(log2n, cand, L, it, j, z, zf, s);
 }
 
-hipError_t pc_reduced(const PcPlan& pl, const int* done, hipStream_t s) {
-  if (pl.NS <= 0) return hipSuccess;
-  int thr = 64;
-  while (thr < K2_THREADS && thr < pl.NS) thr *= 2;
-  if (pl.prec)
-    hipLaunchKernelGGL((k_pc_reduced<float>), dim3(pl.F), dim3(thr), 0, s,
-                       (const Cx<float>*)pl.iface, (Cx<float>*)pl.sep, pl.red_a, pl.red_ap,
-                       pl.red_inv, pl.red_tmp, pl.lo, pl.up, pl.P, pl.NS, pl.B, done);
+hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int threads, int j,
+                      int standalone, hipStream_t s) {
+  (void)j;
+  if (it.n <= 0) return hipSuccess;
+  if (prec)
+    hipLaunchKernelGGL((k_pc_reduced<float>), dim3(it.n), dim3(threads), 0, s, L.D, it.it,
+                       standalone);
   else
-    hipLaunchKernelGGL((k_pc_reduced<double>), dim3(pl.F), dim3(thr), 0, s,
-                       (const Cx<double>*)pl.iface, (Cx<double>*)pl.sep, pl.red_a, pl.red_ap,
-                       pl.red_inv, pl.red_tmp, pl.lo, pl.up, pl.P, pl.NS, pl.B, done);
+    hipLaunchKernelGGL((k_pc_reduced<double>), dim3(it.n), dim3(threads), 0, s, L.D, it.it,
+                       standalone);
   return hipGetLastError();
 }
 

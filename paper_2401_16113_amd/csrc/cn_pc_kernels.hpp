@@ -23,24 +23,19 @@ namespace cn {
 // K1
 // ---------------------------------------------------------------------------
 template <typename R, int LOG2N, int BB, int TT>
-__global__ __launch_bounds__(TT) void k_pc_forward(
-    const double* __restrict__ v, const double* __restrict__ scale,
-    const int* __restrict__ done, const double* __restrict__ lo,
+__device__ __forceinline__ void pc_forward_tile(
+    int p, const double* __restrict__ v, double sc, const double* __restrict__ lo,
     const double* __restrict__ di, const double* __restrict__ up,
     const double* __restrict__ wfw, const Cx<R>* __restrict__ tw,
     const Cx<double>* __restrict__ mu, const Cx<double>* __restrict__ il2,
-    Cx<R>* __restrict__ spec, Cx<R>* __restrict__ iface, int nx, int P, int nwg_pad) {
+    Cx<R>* __restrict__ spec, Cx<R>* __restrict__ iface, int nx, int P) {
   using Cfg = PcCfg<R, LOG2N, BB, TT>;
   constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
   __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
   __shared__ R co[3 * B];
-  if (done != nullptr && *done) return;
-  const int p = xcd_tile(blockIdx.x, nwg_pad);
-  if (p >= P) return;
   const int tid = threadIdx.x;
   const int i0 = p * B;
   const int ncols = min(B, nx - i0);
-  const double sc = scale != nullptr ? *scale : 1.0;
   if (tid < 3 * B) {
     const int b = tid / 3, c = tid % 3;
     R val = R(0);
@@ -147,24 +142,39 @@ __global__ __launch_bounds__(TT) void k_pc_forward(
   }
 }
 
+template <typename R, int LOG2N, int BB, int TT>
+__global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ D,
+                                                   const int2* __restrict__ items, int nitems,
+                                                   int nitems_pad, int jv,
+                                                   const double* __restrict__ v_ovr) {
+  const int itx = xcd_tile(blockIdx.x, nitems_pad);
+  if (itx >= nitems) return;
+  const int2 wi = items[itx];
+  const InstDesc& d = D[wi.x];
+  const PcPlan& pl = d.pl;
+  // inside a solve: input V_j scaled by 1/||v_j||, skipped once the cycle stopped
+  if (v_ovr == nullptr && d.st->sum.done) return;
+  const double* v = v_ovr != nullptr ? v_ovr : d.V + (size_t)jv * d.vstride;
+  const double sc = v_ovr != nullptr ? 1.0 : d.st->vscale[jv];
+  const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
+  pc_forward_tile<R, LOG2N, BB, TT>(wi.y, v, sc, pl.lo, pl.di, pl.up, pl.wfw, tw, pl.mu, pl.il2,
+                                    (Cx<R>*)pl.spec, (Cx<R>*)pl.iface, pl.nx, pl.P);
+}
+
 // ---------------------------------------------------------------------------
 // K3
 // ---------------------------------------------------------------------------
 template <typename R, int LOG2N, int BB, int TT, typename TZ>
-__global__ __launch_bounds__(TT) void k_pc_inverse(
-    const Cx<R>* __restrict__ spec, const Cx<R>* __restrict__ sep,
-    const int* __restrict__ done, const double* __restrict__ lo,
-    const double* __restrict__ di, const double* __restrict__ up,
-    const double* __restrict__ winv, const Cx<R>* __restrict__ tw,
-    const Cx<double>* __restrict__ mu, TZ* __restrict__ z, int nx, int P, int NS,
-    int nwg_pad) {
+__device__ __forceinline__ void pc_inverse_tile(
+    int p, const Cx<R>* __restrict__ spec, const Cx<R>* __restrict__ sep,
+    const double* __restrict__ lo, const double* __restrict__ di,
+    const double* __restrict__ up, const double* __restrict__ winv,
+    const Cx<R>* __restrict__ tw, const Cx<double>* __restrict__ mu, TZ* __restrict__ z, int nx,
+    int P, int NS) {
   using Cfg = PcCfg<R, LOG2N, BB, TT>;
   constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
   __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
   __shared__ R co[3 * B];
-  if (done != nullptr && *done) return;
-  const int p = xcd_tile(blockIdx.x, nwg_pad);
-  if (p >= P) return;
   const int tid = threadIdx.x;
   const int i0 = p * B;
   const int ncols = min(B, nx - i0);
@@ -264,6 +274,21 @@ __global__ __launch_bounds__(TT) void k_pc_inverse(
   }
 }
 
+template <typename R, int LOG2N, int BB, int TT, typename TZ>
+__global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ D,
+                                                   const int2* __restrict__ items, int nitems,
+                                                   int nitems_pad, int jv, TZ* __restrict__ z_ovr) {
+  const int itx = xcd_tile(blockIdx.x, nitems_pad);
+  if (itx >= nitems) return;
+  const int2 wi = items[itx];
+  const InstDesc& d = D[wi.x];
+  const PcPlan& pl = d.pl;
+  if (z_ovr == nullptr && d.st->sum.done) return;
+  TZ* z = z_ovr != nullptr ? z_ovr : (TZ*)d.Z + (size_t)jv * d.vstride;
+  const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
+  pc_inverse_tile<R, LOG2N, BB, TT, TZ>(wi.y, (const Cx<R>*)pl.spec, (const Cx<R>*)pl.sep, pl.lo,
+                                        pl.di, pl.up, pl.winv, tw, pl.mu, z, pl.nx, pl.P, pl.NS);
+}
 
 // ---------------------------------------------------------------------------
 // launch one compiled (B, T) candidate; dispatch over candidates and log2(N_t)
@@ -271,61 +296,58 @@ __global__ __launch_bounds__(TT) void k_pc_inverse(
 static inline int pad8(int v) { return (v + 7) / 8 * 8; }
 
 template <typename R, int L, int CI>
-static hipError_t launch_fwd_c(const PcPlan& pl, const double* v, const double* scale,
-                               const int* done, hipStream_t s) {
-  using C = PcCand<R, L, CI>;
-  if constexpr (!C::ok) {
-    return hipErrorInvalidValue;
-  } else {
-    const int nwg = pad8(pl.P);
-    const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
-    hipLaunchKernelGGL((k_pc_forward<R, L, C::B, C::T>), dim3(nwg), dim3(C::T), 0, s, v, scale,
-                       done, pl.lo, pl.di, pl.up, pl.wfw, tw, pl.mu, pl.il2, (Cx<R>*)pl.spec,
-                       (Cx<R>*)pl.iface, pl.nx, pl.P, nwg);
-    return hipGetLastError();
-  }
-}
-
-template <typename R, int L, int CI>
-static hipError_t launch_inv_c(const PcPlan& pl, void* z, int zf, const int* done,
+static hipError_t launch_fwd_c(const Launch& Lc, const Items& it, int j, const double* v,
                                hipStream_t s) {
   using C = PcCand<R, L, CI>;
   if constexpr (!C::ok) {
     return hipErrorInvalidValue;
   } else {
-    const int nwg = pad8(pl.P);
-    const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
+    if (it.n <= 0) return hipSuccess;
+    const int nwg = pad8(it.n);
+    hipLaunchKernelGGL((k_pc_forward<R, L, C::B, C::T>), dim3(nwg), dim3(C::T), 0, s, Lc.D, it.it,
+                       it.n, nwg, j, v);
+    return hipGetLastError();
+  }
+}
+
+template <typename R, int L, int CI>
+static hipError_t launch_inv_c(const Launch& Lc, const Items& it, int j, void* z, int zf,
+                               hipStream_t s) {
+  using C = PcCand<R, L, CI>;
+  if constexpr (!C::ok) {
+    return hipErrorInvalidValue;
+  } else {
+    if (it.n <= 0) return hipSuccess;
+    const int nwg = pad8(it.n);
     if (zf)
       hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, float>), dim3(nwg), dim3(C::T), 0, s,
-                         (const Cx<R>*)pl.spec, (const Cx<R>*)pl.sep, done, pl.lo, pl.di, pl.up,
-                         pl.winv, tw, pl.mu, (float*)z, pl.nx, pl.P, pl.NS, nwg);
+                         Lc.D, it.it, it.n, nwg, j, (float*)z);
     else
       hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, double>), dim3(nwg), dim3(C::T), 0, s,
-                         (const Cx<R>*)pl.spec, (const Cx<R>*)pl.sep, done, pl.lo, pl.di, pl.up,
-                         pl.winv, tw, pl.mu, (double*)z, pl.nx, pl.P, pl.NS, nwg);
+                         Lc.D, it.it, it.n, nwg, j, (double*)z);
     return hipGetLastError();
   }
 }
 
 template <typename R, int L, int CI = 0>
-static hipError_t fwd_cand(int ci, const PcPlan& pl, const double* v, const double* scale,
-                           const int* done, hipStream_t s) {
-  if constexpr (CI >= kNumCand) {
-    return hipErrorInvalidValue;
-  } else {
-    if (ci == CI) return launch_fwd_c<R, L, CI>(pl, v, scale, done, s);
-    return fwd_cand<R, L, CI + 1>(ci, pl, v, scale, done, s);
-  }
-}
-
-template <typename R, int L, int CI = 0>
-static hipError_t inv_cand(int ci, const PcPlan& pl, void* z, int zf, const int* done,
+static hipError_t fwd_cand(int ci, const Launch& Lc, const Items& it, int j, const double* v,
                            hipStream_t s) {
   if constexpr (CI >= kNumCand) {
     return hipErrorInvalidValue;
   } else {
-    if (ci == CI) return launch_inv_c<R, L, CI>(pl, z, zf, done, s);
-    return inv_cand<R, L, CI + 1>(ci, pl, z, zf, done, s);
+    if (ci == CI) return launch_fwd_c<R, L, CI>(Lc, it, j, v, s);
+    return fwd_cand<R, L, CI + 1>(ci, Lc, it, j, v, s);
+  }
+}
+
+template <typename R, int L, int CI = 0>
+static hipError_t inv_cand(int ci, const Launch& Lc, const Items& it, int j, void* z, int zf,
+                           hipStream_t s) {
+  if constexpr (CI >= kNumCand) {
+    return hipErrorInvalidValue;
+  } else {
+    if (ci == CI) return launch_inv_c<R, L, CI>(Lc, it, j, z, zf, s);
+    return inv_cand<R, L, CI + 1>(ci, Lc, it, j, z, zf, s);
   }
 }
 
@@ -347,16 +369,16 @@ static bool cand_info(int ci, int* B, int* T) {
   X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13)
 
 #define CN_DEFINE_PC_PRECISION(R, SUF)                                                        \
-  hipError_t pc_forward_##SUF(const PcPlan& pl, const double* v, const double* scale,         \
-                              const int* done, hipStream_t s) {                              \
-    switch (pl.log2n) {                                                                       \
+  hipError_t pc_forward_##SUF(int log2n, int cand, const Launch& Lc, const Items& it, int j,  \
+                              const double* v, hipStream_t s) {                               \
+    switch (log2n) {                                                                          \
       CN_LOG2N_CASES(CN_FWD_CASE_##SUF)                                                       \
     }                                                                                         \
     return hipErrorInvalidValue;                                                              \
   }                                                                                           \
-  hipError_t pc_inverse_##SUF(const PcPlan& pl, void* z, int zf, const int* done,             \
-                              hipStream_t s) {                                               \
-    switch (pl.log2n) {                                                                       \
+  hipError_t pc_inverse_##SUF(int log2n, int cand, const Launch& Lc, const Items& it, int j,  \
+                              void* z, int zf, hipStream_t s) {                               \
+    switch (log2n) {                                                                          \
       CN_LOG2N_CASES(CN_INV_CASE_##SUF)                                                       \
     }                                                                                         \
     return hipErrorInvalidValue;                                                              \

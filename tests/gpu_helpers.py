@@ -30,3 +30,15 @@ def rel_inf(x, ref):
 
 def banner(msg):
     print(f"\n[gpu-case] {msg}", flush=True)
+
+
+def batch(insts, pc_prec="fp32", m_max=20):
+    probs = [dict(a_lo=T(i.a_lo), a_di=T(i.a_di), a_up=T(i.a_up), nt=i.nt, T=i.T,
+                  alpha=i.alpha, m_max=m_max) for i in insts]
+    return B.Batch(probs, pc_prec=pc_prec)
+
+
+def packed(insts, attr):
+    if attr == "u0":
+        return T(np.concatenate([i.u0 for i in insts]))
+    return T(np.concatenate([i.f.reshape(-1) for i in insts]))
