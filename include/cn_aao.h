@@ -106,7 +106,9 @@ cn_status cn_pc_apply(cn_aao *h, const double *v, double *z);
 typedef struct {
     int32_t m;              /* restart length, 1 <= m <= m_max                 */
     int32_t max_iters;      /* total inner-iteration budget, >= 1              */
-    int32_t use_x0;         /* nonzero: x holds the initial guess; else x0 = 0 */
+    int32_t use_x0;         /* 0: x0 = 0; 1: x holds the initial guess;        */
+                            /* 2: as 1, but an instance whose initial residual */
+                            /*    is no smaller than ||b|| starts from x0 = 0  */
     int32_t reserved;
     double rtol;            /* stop when ||b - M x||_2 / ||b||_2 <= rtol       */
 } cn_gmres_opts;
@@ -116,6 +118,8 @@ typedef struct {
     int32_t restarts;       /* completed cycles that did not converge         */
     int32_t matvecs;        /* all products with M, residual checks included  */
     int32_t pc_applies;     /* preconditioner applications                    */
+    int32_t x0_rejected;    /* 1: use_x0 = 2 replaced the initial guess by 0  */
+    int32_t reserved;
     double relres_true;     /* ||b - M x|| / ||b|| at return (recomputed)      */
     double relres_est;      /* last least-squares residual estimate / ||b||   */
     double seconds;         /* wall time of the call                          */

@@ -45,6 +45,7 @@ class CnGmresOpts(ctypes.Structure):
 class CnGmresInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("matvecs", ctypes.c_int32), ("pc_applies", ctypes.c_int32),
+                ("x0_rejected", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
 
@@ -86,6 +87,20 @@ def load():
                                           ctypes.POINTER(CnGmresInfo)]),
         "cn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "cn_last_error": (ctypes.c_char_p, []),
+        # learned initial guess (cn_warmstart.h)
+        "cn_mlp_create": (ctypes.c_int, [i32, i32, i32, i32, vp, ctypes.POINTER(vp)]),
+        "cn_mlp_destroy": (ctypes.c_int, [vp]),
+        "cn_mlp_num_params": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64)]),
+        "cn_mlp_set_params": (ctypes.c_int, [vp, vp]),
+        "cn_mlp_get_params": (ctypes.c_int, [vp, vp]),
+        "cn_mlp_set_normalization": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "cn_mlp_forward": (ctypes.c_int, [vp, vp, i32, vp]),
+        "cn_mlp_loss_grad": (ctypes.c_int, [vp, vp, vp, i32, vp, vp]),
+        "cn_mlp_adam_step": (ctypes.c_int, [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                            ctypes.c_float]),
+        "cn_ws_restrict": (ctypes.c_int, [vp, i32, i32, i32, vp, vp, vp]),
+        "cn_ws_interpolate": (ctypes.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "cn_ws_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -98,20 +113,22 @@ def load():
 class CnError(RuntimeError):
     def __init__(self, status: int, where: str):
         lib = load()
-        msg = lib.cn_last_error().decode()
+        last = lib.cn_ws_last_error if where.startswith(("cn_mlp", "cn_ws")) else lib.cn_last_error
+        msg = last().decode()
         super().__init__(f"{where}: {lib.cn_status_string(status).decode()} ({status}): {msg}")
         self.status = status
 
 
-def _ptr(t):
+def _ptr(t, dtype=None):
     if t is None:
         return None
     if not isinstance(t, torch.Tensor):
         raise TypeError("expected a torch tensor")
     if t.device.type != "cuda":
         raise ValueError("tensor must live on the GPU")
-    if t.dtype != torch.float64:
-        raise TypeError("tensor must be float64")
+    dtype = torch.float64 if dtype is None else dtype
+    if t.dtype != dtype:
+        raise TypeError(f"tensor must be {dtype}")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
@@ -133,6 +150,7 @@ class SolveResult:
     relres_true: float
     relres_est: float
     seconds: float
+    x0_rejected: int = 0
 
 
 class Solver:
@@ -201,14 +219,14 @@ class Solver:
 
     def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
               use_x0: bool = False, allow_not_converged: bool = True) -> SolveResult:
-        opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=1 if use_x0 else 0,
+        opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=int(use_x0),
                            reserved=0, rtol=float(rtol))
         info = CnGmresInfo()
         ok = (CN_OK, CN_NOT_CONVERGED) if allow_not_converged else (CN_OK,)
         st = _check(self._lib.cn_gmres_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(opts),
                                              ctypes.byref(info)), "cn_gmres_solve", ok)
         return SolveResult(st, info.iters, info.restarts, info.matvecs, info.pc_applies,
-                           info.relres_true, info.relres_est, info.seconds)
+                           info.relres_true, info.relres_est, info.seconds, info.x0_rejected)
 
 
 class Batch:
@@ -262,7 +280,7 @@ class Batch:
 
     def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
               use_x0: bool = False):
-        opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=1 if use_x0 else 0,
+        opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=int(use_x0),
                            reserved=0, rtol=float(rtol))
         infos = (CnGmresInfo * self.count)()
         total = CnGmresInfo()
@@ -271,7 +289,86 @@ class Batch:
                     (CN_OK, CN_NOT_CONVERGED))
         per = [SolveResult(CN_OK if i.relres_true <= rtol else CN_NOT_CONVERGED, i.iters,
                            i.restarts, i.matvecs, i.pc_applies, i.relres_true, i.relres_est,
-                           i.seconds) for i in infos]
+                           i.seconds, i.x0_rejected) for i in infos]
         tot = SolveResult(st, total.iters, total.restarts, total.matvecs, total.pc_applies,
-                          total.relres_true, total.relres_est, total.seconds)
+                          total.relres_true, total.relres_est, total.seconds, total.x0_rejected)
         return tot, per
+
+
+# ---------------------------------------------------------------------------
+# learned initial guess
+# ---------------------------------------------------------------------------
+COARSE_X, COARSE_T = 128, 64
+
+
+def _f32(t):
+    return _ptr(t, torch.float32)
+
+
+class Mlp:
+    """The warm-start network (wraps a cn_mlp handle): n_in -> w -> w -> w ->
+    n_out with ReLU, bf16 matrix-core products with float32 accumulation,
+    float32 masters and Adam.  Tensors: float32, contiguous, on the GPU."""
+
+    def __init__(self, n_in: int, width: int, n_out: int, max_batch: int, stream=None):
+        self._lib = load()
+        self.n_in, self.width, self.n_out, self.max_batch = n_in, width, n_out, max_batch
+        h = ctypes.c_void_p()
+        s = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(self._lib.cn_mlp_create(n_in, width, n_out, max_batch, s, ctypes.byref(h)),
+               "cn_mlp_create")
+        self._h = h
+        n = ctypes.c_int64()
+        _check(self._lib.cn_mlp_num_params(self._h, ctypes.byref(n)), "cn_mlp_num_params")
+        self.num_params = n.value
+
+    def close(self):
+        if self._h:
+            _check(self._lib.cn_mlp_destroy(self._h), "cn_mlp_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        _check(self._lib.cn_mlp_set_params(self._h, _f32(p)), "cn_mlp_set_params")
+
+    def get_params(self, out):
+        _check(self._lib.cn_mlp_get_params(self._h, _f32(out)), "cn_mlp_get_params")
+        return out
+
+    def set_normalization(self, in_mean, in_scale, out_mean, out_scale):
+        _check(self._lib.cn_mlp_set_normalization(self._h, _f32(in_mean), _f32(in_scale),
+                                                  _f32(out_mean), _f32(out_scale)),
+               "cn_mlp_set_normalization")
+
+    def forward(self, X, Y):
+        _check(self._lib.cn_mlp_forward(self._h, _f32(X), int(X.shape[0]), _f32(Y)),
+               "cn_mlp_forward")
+        return Y
+
+    def loss_grad(self, X, Yt, grads=None, loss=None):
+        _check(self._lib.cn_mlp_loss_grad(self._h, _f32(X), _f32(Yt), int(X.shape[0]),
+                                          _f32(grads), _f32(loss)), "cn_mlp_loss_grad")
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(self._lib.cn_mlp_adam_step(self._h, lr, beta1, beta2, eps), "cn_mlp_adam_step")
+
+
+def ws_restrict(x, count: int, nx: int, nt: int, inv_scale, coarse, stream=None):
+    lib = load()
+    s = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(lib.cn_ws_restrict(_ptr(x), count, nx, nt, _ptr(inv_scale), _f32(coarse), s),
+           "cn_ws_restrict")
+    return coarse
+
+
+def ws_interpolate(coarse, count: int, nx: int, nt: int, u0, gl, gr, scale, x0, stream=None):
+    lib = load()
+    s = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(lib.cn_ws_interpolate(_f32(coarse), count, nx, nt, _ptr(u0), _ptr(gl), _ptr(gr),
+                                 _ptr(scale), _ptr(x0), s), "cn_ws_interpolate")
+    return x0

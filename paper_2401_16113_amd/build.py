@@ -13,7 +13,8 @@ INC = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libcn_aao.so")
 OBJ = os.path.join(ROOT, "_build")
 
-SOURCES = ["cn_api.hip", "cn_krylov.hip", "cn_pc.hip", "cn_pc_f64.hip", "cn_pc_f32.hip"]
+SOURCES = ["cn_api.hip", "cn_krylov.hip", "cn_pc.hip", "cn_pc_f64.hip", "cn_pc_f32.hip",
+           "cn_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -209,6 +209,7 @@ static cn_status wait_slot(hipStream_t stream, GSummary* slot, int seq, GSummary
   out->k = v->k;
   out->done = v->done;
   out->breakdown = v->breakdown;
+  out->x0_rejected = v->x0_rejected;
   out->seq = seq;
   return CN_OK;
 }
@@ -652,7 +653,8 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
   // r_0 = b - M x_0 into v_0 (x_0 = 0 is never read); the stop flag covers
   // instances that already meet rtol, so nothing waits here
   int seq_res = c.batched ? 0 : ++(*c.seqc);
-  HIP_TRY(launch_residual(c.L, c.mv, b, x, opts->use_x0 ? 0 : 1, rtol, 2, seq_res, c.s));
+  HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, opts->use_x0 ? 0 : 1, rtol, 2, seq_res, c.s,
+                          opts->use_x0 == 2 ? 2 : 1));
   bool x_zero = !opts->use_x0;
   int done_iters = 0;
   int seqs[MMAX];
@@ -700,7 +702,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
     HIP_TRY(launch_cycle_end(c.L, c.stv, x, x_zero ? 1 : 0, 3, seq_fin, c.s));
     x_zero = false;
     seq_res = c.batched ? 0 : ++(*c.seqc);
-    HIP_TRY(launch_residual(c.L, c.mv, b, x, 0, rtol, 2, seq_res, c.s));
+    HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, seq_res, c.s, 0));
     if (c.batched) {
       int sq = 0;
       CN_TRY(batch_publish(c, 2, &sq));
@@ -713,6 +715,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
         fin[i].est = f3->est;
         cur[i].relres = f2->relres;
         cur[i].bnorm = f2->bnorm;
+        cur[i].x0_rejected = f2->x0_rejected;
       }
     } else {
       CN_TRY(wait_slot(c.s, c.hs + 3, seq_fin, &fin[0]));
@@ -745,13 +748,15 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
   HIP_TRY(hipStreamSynchronize(c.s));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
   bool ok = true;
-  cn_gmres_info tot{0, 0, 0, 0, 0.0, 0.0, secs};
+  cn_gmres_info tot{0, 0, 0, 0, 0, 0, 0.0, 0.0, secs};
   for (int i = 0; i < ninst; ++i) {
     cn_gmres_info in;
     in.iters = iters[i];
     in.restarts = rest[i];
     in.matvecs = mvs[i];
     in.pc_applies = pcs[i];
+    in.x0_rejected = cur[i].x0_rejected;
+    in.reserved = 0;
     in.relres_true = cur[i].relres;
     in.relres_est = iters[i] > 0 ? est[i] : cur[i].relres;
     in.seconds = secs;
@@ -761,6 +766,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
     tot.restarts = std::max(tot.restarts, in.restarts);
     tot.matvecs += in.matvecs;
     tot.pc_applies += in.pc_applies;
+    tot.x0_rejected += in.x0_rejected;
     tot.relres_true = std::max(tot.relres_true, in.relres_true);
     tot.relres_est = std::max(tot.relres_est, in.relres_est);
   }
@@ -868,6 +874,7 @@ cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_o
     return fail(CN_EINVAL, "NULL argument");
   if (opts->m < 1 || opts->m > h->m_max) return fail(CN_EINVAL, "opts->m must be in [1, m_max]");
   if (opts->max_iters < 1) return fail(CN_EINVAL, "opts->max_iters must be >= 1");
+  if (opts->use_x0 < 0 || opts->use_x0 > 2) return fail(CN_EINVAL, "opts->use_x0 must be 0, 1 or 2");
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
   if (overlaps(b, x, h->n * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
@@ -1052,6 +1059,7 @@ cn_status cn_batch_solve(cn_batch* b, const double* bp, double* xp, const cn_gmr
   if (opts->m < 1 || opts->m > b->m_min)
     return fail(CN_EINVAL, "opts->m must be in [1, smallest m_max of the batch]");
   if (opts->max_iters < 1) return fail(CN_EINVAL, "opts->max_iters must be >= 1");
+  if (opts->use_x0 < 0 || opts->use_x0 > 2) return fail(CN_EINVAL, "opts->use_x0 must be 0, 1 or 2");
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
   if (overlaps(bp, xp, b->off.back() * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");

@@ -46,6 +46,8 @@ struct GSummary {
   int k;          // inner iterations completed in the current cycle
   int done;       // nonzero: the cycle has stopped, remaining kernels return
   int breakdown;  // lucky breakdown (h_{j+1,j} == 0)
+  int x0_rejected;  // the initial guess was replaced by zero (fallback start)
+  int pad;
   int seq;        // sequence number of the write (host polling), written last
 };
 
@@ -118,10 +120,13 @@ int stream_grid(long long n);
 hipError_t launch_matvec_plain(const Launch& L, const Items& mv, const double* x, double* y,
                                hipStream_t s);
 // r = b - M x into V_0 of every instance (x = 0 is not read when x_zero), then
-// the per-instance cycle start (norms, stop flag, summary to the host slot)
-hipError_t launch_residual(const Launch& L, const Items& mv, const double* b_base,
-                           double* x_base, int x_zero, double rtol, int slot, int seq,
-                           hipStream_t s);
+// the per-instance cycle start (norms, stop flag, summary to the host slot).
+// start: 0 restart of a solve, 1 first residual of a solve, 2 first residual
+// with fallback (an instance whose ||r|| >= ||b|| restarts from x = 0: its
+// V_0 becomes b and its x is cleared, on the device)
+hipError_t launch_residual(const Launch& L, const Items& mv, const Items& stv,
+                           const double* b_base, double* x_base, int x_zero, double rtol,
+                           int slot, int seq, hipStream_t s, int start = 0);
 // one inner iteration's Krylov part: w = M z_j with the first dots, the two
 // CGS2 passes and the Givens update (`finish` = false leaves out the
 // finishing kernels, for timing the streaming kernels alone)

@@ -87,6 +87,7 @@ __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int 
   host->k = sm.k;
   host->done = sm.done;
   host->breakdown = sm.breakdown;
+  host->x0_rejected = sm.x0_rejected;
   __threadfence_system();
   *(volatile int*)&host->seq = seq;
 }
@@ -244,7 +245,9 @@ __global__ __launch_bounds__(KT) void k_cgs_pass2(const InstDesc* __restrict__ D
 
 // ---------------------------------------------------------------------------
 // finishing kernels, one workgroup per instance (blockIdx.x):
-// FIN 1: residual r = b - M x -> ||b||, beta, v_0 scale, g, relres, stop flag
+// FIN 1: residual r = b - M x -> ||b||, beta, v_0 scale, g, relres, stop flag;
+//        j = start mode: 0 restart, 1 first residual, 2 first residual with
+//        fallback to x = 0 when ||r|| >= ||b|| (then beta = ||b||)
 // FIN 2: first Gram-Schmidt dots -> h1, c1
 // FIN 3: second Gram-Schmidt dots -> h2, c2
 // FIN 4: ||v_{j+1}|| -> Hessenberg column, Givens rotation, residual estimate
@@ -271,7 +274,12 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
   if (FIN == 1) {
     // start of a cycle: beta = ||r||, v_0 = r / beta (stored unnormalised)
     sm.bnorm = sqrt(out[1]);
-    const double beta = sqrt(out[0]);
+    double beta = sqrt(out[0]);
+    if (j >= 1) sm.x0_rejected = 0;
+    if (j == 2 && beta >= sm.bnorm && sm.bnorm > 0.0) {
+      sm.x0_rejected = 1;
+      beta = sm.bnorm;
+    }
     sm.beta = beta;
     st->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
     st->g[0] = beta;
@@ -321,6 +329,25 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
     sm.breakdown = brk ? 1 : 0;
     if (est <= rtol * sm.bnorm || brk || j + 1 >= stop_iter) sm.done = 1;
     publish(host, sm, seq);
+  }
+}
+
+// Fallback start: an instance whose initial guess was rejected by the first
+// residual's finishing kernel gets v_0 = b and x = 0.
+__global__ __launch_bounds__(KT) void k_fallback(const InstDesc* __restrict__ D,
+                                                 const int2* __restrict__ items,
+                                                 const double* __restrict__ bb,
+                                                 double* __restrict__ xb) {
+  const int2 wi = items[blockIdx.x];
+  const InstDesc& d = D[wi.x];
+  if (!d.st->sum.x0_rejected) return;
+  const double* __restrict__ b = bb + d.off;
+  double* __restrict__ x = xb + d.off;
+  double* __restrict__ v = d.V;
+  const long long stride = (long long)d.st_grid * KT;
+  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.n; e += stride) {
+    v[e] = b[e];
+    x[e] = 0.0;
   }
 }
 
@@ -458,12 +485,15 @@ hipError_t launch_matvec_plain(const Launch& L, const Items& mv, const double* x
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const Launch& L, const Items& mv, const double* b_base,
-                           double* x_base, int x_zero, double rtol, int slot, int seq,
-                           hipStream_t s) {
+hipError_t launch_residual(const Launch& L, const Items& mv, const Items& stv,
+                           const double* b_base, double* x_base, int x_zero, double rtol,
+                           int slot, int seq, hipStream_t s, int start) {
   hipLaunchKernelGGL((k_matvec<double, 1, 2>), dim3(mv.n), dim3(KT), 0, s, L.D, mv.it, 0,
                      (const double*)x_base, b_base, nullptr, x_zero);
-  hipLaunchKernelGGL((k_finish<1>), dim3(L.ninst), dim3(FT), 0, s, L.D, 0, 0, rtol, slot, seq);
+  hipLaunchKernelGGL((k_finish<1>), dim3(L.ninst), dim3(FT), 0, s, L.D, start, 0, rtol, slot,
+                     seq);
+  if (start == 2)
+    hipLaunchKernelGGL(k_fallback, dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, b_base, x_base);
   return hipGetLastError();
 }
 

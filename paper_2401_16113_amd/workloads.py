@@ -84,10 +84,11 @@ def left_boundary(t, K: float, r: float, x_min: float = X_MIN):
     return K * np.exp(-r * np.asarray(t, dtype=np.float64)) - np.exp(x_min)
 
 
-def make_instance(nx: int, nt: int, T: float, r: float, K: float,
-                  sigma_fn: Callable[[np.ndarray], np.ndarray], alpha: float,
-                  m: int = 20, rtol: float = 1e-8, pc_prec: str = "fp64",
-                  name: str = "", params: Optional[dict] = None) -> Instance:
+def family_rows(nx: int, nt: int, T: float, r: float, K: float,
+                sigma_fn: Callable[[np.ndarray], np.ndarray]):
+    """Operator rows, initial condition and the one non-zero column of the
+    forcing of one put instance: (sigma, lo, di, up, u0, f_col, x, h), with
+    f^{k+1/2} = f_col[k] e_1."""
     x, h = grid(nx)
     sigma = np.asarray(sigma_fn(x), dtype=np.float64)
     if sigma.min() < 0.02:
@@ -99,8 +100,17 @@ def make_instance(nx: int, nt: int, T: float, r: float, K: float,
     u0 = np.maximum(K - np.exp(x), 0.0)
     tau = T / nt
     th = (np.arange(nt, dtype=np.float64) + 0.5) * tau
+    f_col = a10 * left_boundary(th, K, r)
+    return sigma, lo, di, up, u0, f_col, x, h
+
+
+def make_instance(nx: int, nt: int, T: float, r: float, K: float,
+                  sigma_fn: Callable[[np.ndarray], np.ndarray], alpha: float,
+                  m: int = 20, rtol: float = 1e-8, pc_prec: str = "fp64",
+                  name: str = "", params: Optional[dict] = None) -> Instance:
+    sigma, lo, di, up, u0, f_col, x, h = family_rows(nx, nt, T, r, K, sigma_fn)
     f = np.zeros((nt, nx), dtype=np.float64)
-    f[:, 0] = a10 * left_boundary(th, K, r)
+    f[:, 0] = f_col
     return Instance(nx=nx, nt=nt, T=T, r=r, K=K, alpha=alpha, sigma=sigma,
                     a_lo=lo, a_di=di, a_up=up, u0=u0, f=f, x=x, h=h, m=m,
                     rtol=rtol, pc_prec=pc_prec, name=name, params=params or {})
@@ -190,6 +200,15 @@ def config4_instance(p, nx: int = WS_NX, nt: int = WS_NT) -> Instance:
     return make_instance(nx, nt, T=T, r=r, K=K, sigma_fn=local_vol(a1, a2),
                          alpha=0.01, m=20, rtol=1e-8, pc_prec="fp32",
                          name="ws", params={"a1": a1, "a2": a2})
+
+
+def config4_rows(p, nx: int = WS_NX, nt: int = WS_NT):
+    """family_rows of one warm-start instance plus its Dirichlet data at the
+    fine levels t_{k+1} (left: discounted put asymptote, right: 0)."""
+    a1, a2, r, T, K = (float(v) for v in p)
+    rows = family_rows(nx, nt, T=T, r=r, K=K, sigma_fn=local_vol(a1, a2))
+    tk = (np.arange(nt, dtype=np.float64) + 1.0) * (T / nt)
+    return rows, left_boundary(tk, K, r), np.zeros(nt)
 
 
 def config4_features(params: np.ndarray) -> np.ndarray:

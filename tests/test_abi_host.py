@@ -82,3 +82,31 @@ def test_null_arguments(lib):
     assert lib.cn_rhs(None, None, None, None) == B.CN_EINVAL
     assert lib.cn_gmres_solve(None, None, None, None, None) == B.CN_EINVAL
     assert lib.cn_aao_query(None, None, None, None) == B.CN_EINVAL
+
+
+def test_mlp_create_rejects_bad_sizes(lib):
+    h = ctypes.c_void_p(1234)
+    for args in ((0, 8, 4, 4), (4, 0, 4, 4), (4, 8, 0, 4), (4, 8, 4, 0)):
+        assert lib.cn_mlp_create(*args, None, ctypes.byref(h)) == B.CN_EINVAL
+        assert h.value is None
+    assert lib.cn_mlp_create(4, 8, 4, 4, None, None) == B.CN_EINVAL
+    assert lib.cn_mlp_destroy(None) == B.CN_EINVAL
+    assert lib.cn_mlp_adam_step(None, 1e-3, 0.9, 0.999, 1e-8) == B.CN_EINVAL
+
+
+def test_ws_grid_calls_reject_bad_arguments(lib):
+    p = ctypes.c_void_p(4096)
+    # NULL pointers
+    assert lib.cn_ws_restrict(None, 1, 255, 64, p, p, None) == B.CN_EINVAL
+    assert lib.cn_ws_interpolate(p, 1, 255, 64, p, p, None, p, p, None) == B.CN_EINVAL
+    # incompatible grids are refused before any device work
+    for nx, nt in ((127, 64), (256, 64), (255, 60), (255, 0)):
+        assert lib.cn_ws_restrict(p, 1, nx, nt, p, p, None) == B.CN_EINVAL
+        assert b"multiple" in lib.cn_ws_last_error()
+    assert lib.cn_ws_restrict(p, 0, 255, 64, p, p, None) == B.CN_EINVAL
+
+
+def test_gmres_info_layout():
+    # six 32-bit fields then three doubles, as include/cn_aao.h declares
+    assert ctypes.sizeof(B.CnGmresInfo) == 48
+    assert B.CnGmresInfo.relres_true.offset == 24
