@@ -16,7 +16,16 @@ exact CN solution is reported by the cpu_baseline leg).
 
 Also reported: the roofline position of the dominant kernel (HIP-event
 timing of each kernel of one inner iteration, algorithmic bytes per launch
-against the 8 TB/s HBM peak) and the CPU oracle timed on the host.
+against the 8 TB/s HBM peak), the CPU oracle timed on the host, and the
+production forms on their own workloads ("forms"):
+  batch_uneven -- 512 uneven constant-volatility puts (N_x in 255..2047,
+                  N_t in 64..512) in one batched solve, float32 preconditioner;
+  warm_start   -- held-out local-volatility puts, N_x = 2047, N_t = 512:
+                  plain (float64 preconditioner, one instance at a time, zero
+                  start) against batched + float32 preconditioner, from zero
+                  and from the learned initial guess (network trained here on
+                  plain solves; inference and interpolation inside the timed
+                  region).
 """
 import argparse
 import hashlib
@@ -106,6 +115,138 @@ def run_variant(B, W, inst, prec, steps, warmup, dev, torch):
     return out, prof, x_host
 
 
+def timed(fn, reps, torch):
+    """Median wall time of fn() over reps calls (fn synchronises)."""
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return statistics.median(ts), out
+
+
+def form_batch_uneven(B, W, torch, reps):
+    import numpy as np
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    insts = W.config3()
+    probs = [dict(a_lo=t(i.a_lo), a_di=t(i.a_di), a_up=t(i.a_up), nt=i.nt, T=i.T,
+                  alpha=i.alpha, m_max=20) for i in insts]
+    t0 = time.perf_counter()
+    bat = B.Batch(probs, pc_prec="fp32")
+    create_s = time.perf_counter() - t0
+    b = torch.empty(bat.n, dtype=torch.float64, device=dev)
+    bat.rhs(t(np.concatenate([i.u0 for i in insts])),
+            t(np.concatenate([i.f.reshape(-1) for i in insts])), b)
+    x = torch.empty_like(b)
+    bat.solve(b, x, m=20, rtol=RTOL)
+    sec, (tot, per) = timed(lambda: bat.solve(b, x, m=20, rtol=RTOL), reps, torch)
+    if tot.status != B.CN_OK:
+        raise RuntimeError(f"uneven batch did not converge: {tot}")
+    bat.close()
+    return {"instances": len(insts), "unknowns": int(bat.n), "ms_per_solve": sec * 1e3,
+            "unknowns_per_s": bat.n / sec, "max_iters": tot.iters,
+            "mean_iters": sum(r.iters for r in per) / len(per),
+            "max_relres": tot.relres_true, "create_s": create_s}
+
+
+def form_warm_start(B, W, torch, n_train, n_held, epochs, reps):
+    import numpy as np
+    from paper_2401_16113_amd import warmstart as WS
+    dev = torch.device("cuda:0")
+    chunk = 128
+    t0 = time.perf_counter()
+    X, Y, worst = WS.generate(W.config4_params(n_train, seed=4), chunk=chunk)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, hist = WS.train(X, Y, epochs=epochs, batch=128, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del X, Y
+    held = W.config4_params(n_held, seed=40)
+    acc = {k: {"sec": 0.0, "iters": [], "relres": 0.0} for k in
+           ("plain_fp64", "batched_fp32", "batched_fp32_warm", "perfect_coarse")}
+    rejected, unknowns, dev_plain = 0, 0, 0.0
+    for c0 in range(0, n_held, chunk):
+        fb = WS.family_batch(held[c0:c0 + chunk])
+        n1 = fb.nx * fb.nt
+        unknowns += fb.count * n1
+        bat = B.Batch(fb.probs, pc_prec="fp32")
+        b = torch.empty(bat.n, dtype=torch.float64, device=dev)
+        bat.rhs(fb.u0, fb.f, b)
+        x = torch.zeros_like(b)
+        bat.solve(b, x, m=20, rtol=RTOL)
+        sec, (tot, per) = timed(lambda: bat.solve(b, x, m=20, rtol=RTOL), reps, torch)
+        a = acc["batched_fp32"]
+        a["sec"] += sec
+        a["iters"] += [r.iters for r in per]
+        a["relres"] = max(a["relres"], tot.relres_true)
+        x_ref = x.clone()
+        coarse = torch.empty((fb.count, WS.N_OUT), dtype=torch.float32, device=dev)
+        xw = torch.empty_like(b)
+
+        def warm():
+            WS.initial_guess(net, fb, coarse=coarse, x0=xw)
+            return bat.solve(b, xw, m=20, rtol=RTOL, use_x0=2)
+        warm()
+        sec, (tot, per) = timed(warm, reps, torch)
+        a = acc["batched_fp32_warm"]
+        a["sec"] += sec
+        a["iters"] += [r.iters for r in per]
+        a["relres"] = max(a["relres"], tot.relres_true)
+        rejected += sum(r.x0_rejected for r in per)
+        # ceiling: the restriction of the converged solution as the guess
+        ones = torch.ones(fb.count, dtype=torch.float64, device=dev)
+        B.ws_restrict(x_ref, fb.count, fb.nx, fb.nt, ones, coarse)
+        xp = torch.empty_like(b)
+        B.ws_interpolate(coarse, fb.count, fb.nx, fb.nt, fb.u0, fb.gl, fb.gr, ones, xp)
+        tot, per = bat.solve(b, xp, m=20, rtol=RTOL, use_x0=2)
+        a = acc["perfect_coarse"]
+        a["iters"] += [r.iters for r in per]
+        a["relres"] = max(a["relres"], tot.relres_true)
+        bat.close()
+        # plain: float64 preconditioner, one instance at a time, zero start
+        a = acc["plain_fp64"]
+        err = 0.0
+        for q, pr in enumerate(fb.probs):
+            s = B.Solver(pr["a_lo"], pr["a_di"], pr["a_up"], fb.nt, pr["T"], 0.01, m_max=20,
+                         pc_prec="fp64")
+            bq = b[q * n1:(q + 1) * n1]
+            xq = torch.zeros_like(bq)
+            s.solve(bq, xq, m=20, rtol=RTOL)
+            sec, r = timed(lambda: s.solve(bq, xq, m=20, rtol=RTOL), 1, torch)
+            a["sec"] += sec
+            a["iters"].append(r.iters)
+            a["relres"] = max(a["relres"], r.relres_true)
+            dev_plain += r.seconds
+            ref = xq.abs().max()
+            err = max(err, float((xw[q * n1:(q + 1) * n1] - xq).abs().max() / ref))
+            s.close()
+        acc["batched_fp32_warm"]["max_err_vs_plain"] = max(
+            acc["batched_fp32_warm"].get("max_err_vs_plain", 0.0), err)
+        del fb, bat, b, x, x_ref, xw, xp
+    out = {"train_instances": n_train, "heldout_instances": n_held, "nx": W.WS_NX,
+           "nt": W.WS_NT, "unknowns": unknowns, "data_gen_s": gen_s, "train_s": train_s,
+           "epochs": epochs, "final_loss": hist[-1], "worst_training_relres": worst,
+           "rejected_guesses": rejected}
+    for k, a in acc.items():
+        it = a["iters"]
+        e = {"mean_iters": sum(it) / len(it), "max_iters": max(it), "max_relres": a["relres"]}
+        if a["sec"] > 0:
+            e["ms_per_instance"] = a["sec"] / n_held * 1e3
+            e["unknowns_per_s"] = unknowns / a["sec"]
+        if "max_err_vs_plain" in a:
+            e["max_err_vs_plain"] = a["max_err_vs_plain"]
+        out[k] = e
+    out["speedup_vs_plain"] = {k: out[k]["unknowns_per_s"] / out["plain_fp64"]["unknowns_per_s"]
+                               for k in ("batched_fp32", "batched_fp32_warm")}
+    net.close()
+    return out
+
+
 def cpu_baseline(inst, x_gpu):
     import numpy as np
     from oracle import cn_oracle as O
@@ -141,6 +282,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--alpha", type=float, default=0.01)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batch and warm-start forms")
+    ap.add_argument("--ws-train", type=int, default=2048,
+                    help="training instances of the warm-start network (full recipe: 20000)")
+    ap.add_argument("--ws-heldout", type=int, default=256,
+                    help="held-out instances of the warm-start comparison (full recipe: 1024)")
+    ap.add_argument("--ws-epochs", type=int, default=150)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 256 MiB device copies (hardware-counter calibration)")
     args = ap.parse_args()
@@ -190,6 +337,22 @@ def main():
         "variants": variants,
         "roofline": roof,
     }
+    if not args.no_forms:
+        log("[bench] form: uneven batch of 512 instances")
+        forms = {"batch_uneven": form_batch_uneven(B, W, torch, reps=5)}
+        log(f"[bench] batch: {forms['batch_uneven']['ms_per_solve']:.2f} ms, "
+            f"{forms['batch_uneven']['unknowns_per_s']:.3e} unknowns/s")
+        log(f"[bench] form: warm start ({args.ws_train} training solves, "
+            f"{args.ws_heldout} held-out)")
+        forms["warm_start"] = form_warm_start(B, W, torch, args.ws_train, args.ws_heldout,
+                                              args.ws_epochs, reps=3)
+        ws = forms["warm_start"]
+        log(f"[bench] warm start: plain {ws['plain_fp64']['unknowns_per_s']:.3e}, batched "
+            f"{ws['batched_fp32']['unknowns_per_s']:.3e}, batched+warm "
+            f"{ws['batched_fp32_warm']['unknowns_per_s']:.3e} unknowns/s; iterations "
+            f"{ws['plain_fp64']['mean_iters']:.2f} / {ws['batched_fp32']['mean_iters']:.2f} / "
+            f"{ws['batched_fp32_warm']['mean_iters']:.2f}")
+        out["forms"] = forms
     if args.calibrate_copy:
         log("[bench] calibration: 5 device copies of 256 MiB")
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
