@@ -116,6 +116,35 @@ def sequential_cn(lo, di, up, T, nt, u0, f, d=None):
     return out.reshape(-1)
 
 
+def sequential_cn_banded(lo, di, up, T, nt, u0, f_col=None, f=None):
+    """sequential_cn for production sizes: the same CN steps with every
+    tridiagonal solve done by LAPACK's banded solver (scipy.linalg.solve_banded)
+    instead of the Python-loop Thomas elimination.  The forcing is either
+    dense (f, nt x nx) or only in the first spatial entry of every level
+    (f_col, nt values).  Constant weights only."""
+    from scipy.linalg import solve_banded
+    nx = len(di)
+    tau = T / nt
+    lo = np.asarray(lo, dtype=np.float64)
+    di = np.asarray(di, dtype=np.float64)
+    up = np.asarray(up, dtype=np.float64)
+    ab = np.zeros((3, nx))
+    ab[0, 1:] = -0.5 * tau * up[:-1]
+    ab[1, :] = 1.0 - 0.5 * tau * di
+    ab[2, :-1] = -0.5 * tau * lo[1:]
+    u = np.asarray(u0, dtype=np.float64).copy()
+    out = np.empty((nt, nx))
+    for k in range(nt):
+        rhs = u + 0.5 * tau * tridiag_mul(lo, di, up, u)
+        if f is not None:
+            rhs += tau * np.asarray(f[k], dtype=np.float64)
+        elif f_col is not None:
+            rhs[0] += tau * f_col[k]
+        u = solve_banded((1, 1), ab, rhs, overwrite_b=True, check_finite=False)
+        out[k] = u
+    return out.reshape(-1)
+
+
 def thomas(lo, di, up, rhs):
     """Plain Thomas elimination (no pivoting) for one tridiagonal system with
     rows (lo[i], di[i], up[i]); works for real or complex data.  rhs may carry
@@ -182,6 +211,22 @@ def pc_matrix_dense(lo, di, up, T, nt, alpha):
     C1, C2 = alpha_circulants(alpha, nt)
     nx = At.shape[0]
     return np.kron(C1, np.eye(nx)) - np.kron(C2, At)
+
+
+def pc_matvec(lo, di, up, T, nt, alpha, z):
+    """y = P_alpha z block by block (eq. (3.1)): y^k = z^k - z^{k-1} -
+    (A~/2)(z^k + z^{k-1}), where for the first block the previous block is
+    alpha z^{N_t} (the wrap-around entries of C1, C2).  Vectorised over the
+    time levels, for full-size residual checks of the preconditioner."""
+    nx = len(di)
+    tau = T / nt
+    Z = np.asarray(z, dtype=np.float64).reshape(nt, nx)
+    Zp = np.roll(Z, 1, axis=0)
+    Zp[0] *= alpha
+    S = Z + Zp
+    Y = Z - Zp
+    Y -= 0.5 * tau * tridiag_mul(np.asarray(lo), np.asarray(di), np.asarray(up), S)
+    return Y.reshape(-1)
 
 
 def coupling_matrix_dense(lo, di, up, T, nt):

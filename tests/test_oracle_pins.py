@@ -393,3 +393,33 @@ def test_planted_matvec_half_is_caught(monkeypatch):
     monkeypatch.setattr(O, "aao_matvec", wrong)
     res = O.cn_gmres_solve(*args, inst.alpha, b, m=20, rtol=1e-12, max_iters=60)
     assert np.max(np.abs(res.x - u)) / np.max(np.abs(u)) > 1e-6
+
+
+def test_banded_sequential_cn_equals_thomas_stepping():
+    """The production-size stepping (LAPACK banded solves) reproduces the
+    Thomas-based stepping, with dense forcing and with the first-entry
+    forcing column."""
+    for inst in (W.config1(63, 32), W.config2(nx=255, nt=16)):
+        args = (inst.a_lo, inst.a_di, inst.a_up, inst.T, inst.nt)
+        ref = O.sequential_cn(*args, inst.u0, inst.f)
+        a = O.sequential_cn_banded(*args, inst.u0, f=inst.f)
+        b = O.sequential_cn_banded(*args, inst.u0, f_col=inst.f[:, 0])
+        assert np.max(np.abs(a - ref)) <= 1e-13 * np.max(np.abs(ref))
+        assert np.max(np.abs(b - ref)) <= 1e-13 * np.max(np.abs(ref))
+        # a dropped forcing is visible
+        c = O.sequential_cn_banded(*args, inst.u0)
+        assert np.max(np.abs(c - ref)) > 1e-6
+
+
+def test_pc_matvec_equals_dense_preconditioner_and_inverts_pc_apply():
+    inst = W.config1(15, 8)
+    args = (inst.a_lo, inst.a_di, inst.a_up, inst.T, inst.nt)
+    z = np.random.default_rng(3).standard_normal(inst.n)
+    for alpha in (0.01, 0.3, 1.0):
+        P = O.pc_matrix_dense(*args, alpha)
+        assert np.allclose(O.pc_matvec(*args, alpha, z), P @ z, rtol=0, atol=1e-12)
+    v = np.random.default_rng(4).standard_normal(inst.n)
+    zz = O.pc_apply(*args, 0.05, v)
+    assert np.max(np.abs(O.pc_matvec(*args, 0.05, zz) - v)) <= 1e-12
+    # a missing alpha on the wrap-around block is visible
+    assert np.max(np.abs(O.pc_matvec(*args, 1.0, zz) - v)) > 1e-3
