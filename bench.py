@@ -145,8 +145,10 @@ def form_batch_uneven(B, W, torch, reps):
     sec, (tot, per) = timed(lambda: bat.solve(b, x, m=20, rtol=RTOL), reps, torch)
     if tot.status != B.CN_OK:
         raise RuntimeError(f"uneven batch did not converge: {tot}")
+    sec_ng, _ = timed(lambda: bat.solve(b, x, m=20, rtol=RTOL, graphs=False), reps, torch)
     bat.close()
     return {"instances": len(insts), "unknowns": int(bat.n), "ms_per_solve": sec * 1e3,
+            "ms_per_solve_without_graphs": sec_ng * 1e3,
             "unknowns_per_s": bat.n / sec, "max_iters": tot.iters,
             "mean_iters": sum(r.iters for r in per) / len(per),
             "max_relres": tot.relres_true, "create_s": create_s}

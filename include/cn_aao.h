@@ -109,9 +109,14 @@ typedef struct {
     int32_t use_x0;         /* 0: x0 = 0; 1: x holds the initial guess;        */
                             /* 2: as 1, but an instance whose initial residual */
                             /*    is no smaller than ||b|| starts from x0 = 0  */
-    int32_t reserved;
+    int32_t flags;          /* CN_SOLVE_* bits, 0 for the defaults             */
     double rtol;            /* stop when ||b - M x||_2 / ||b||_2 <= rtol       */
 } cn_gmres_opts;
+
+/* cn_batch_solve launches each inner iteration as one captured HIP graph
+ * (captured on first use per iteration index, restart length and rtol, and
+ * kept with the batch); this flag launches the same kernels one by one. */
+#define CN_SOLVE_NO_GRAPHS 1
 
 typedef struct {
     int32_t iters;          /* inner iterations (= preconditioned matvecs)    */

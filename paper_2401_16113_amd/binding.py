@@ -23,6 +23,7 @@ CN_EHIP = -3
 CN_ESINGULAR = -4
 
 CN_PC_FP64 = 0
+CN_SOLVE_NO_GRAPHS = 1
 CN_PC_FP32 = 1
 CN_FLAG_ALLOW_ALPHA_ONE = 1
 
@@ -38,7 +39,7 @@ class CnProblem(ctypes.Structure):
 
 class CnGmresOpts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("max_iters", ctypes.c_int32),
-                ("use_x0", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("use_x0", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("rtol", ctypes.c_double)]
 
 
@@ -220,7 +221,7 @@ class Solver:
     def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
               use_x0: bool = False, allow_not_converged: bool = True) -> SolveResult:
         opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=int(use_x0),
-                           reserved=0, rtol=float(rtol))
+                           flags=0, rtol=float(rtol))
         info = CnGmresInfo()
         ok = (CN_OK, CN_NOT_CONVERGED) if allow_not_converged else (CN_OK,)
         st = _check(self._lib.cn_gmres_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(opts),
@@ -279,9 +280,11 @@ class Batch:
         return out
 
     def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
-              use_x0: bool = False):
+              use_x0: int = 0, graphs: bool = True):
+        """use_x0: 0 zero start, 1 x holds the guess, 2 guess with fallback
+        to zero; graphs: launch each inner iteration as a captured graph."""
         opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=int(use_x0),
-                           reserved=0, rtol=float(rtol))
+                           flags=0 if graphs else CN_SOLVE_NO_GRAPHS, rtol=float(rtol))
         infos = (CnGmresInfo * self.count)()
         total = CnGmresInfo()
         st = _check(self._lib.cn_batch_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(opts), infos,

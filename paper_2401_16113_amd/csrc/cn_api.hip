@@ -620,6 +620,32 @@ struct SolveCtx {
   int* bseq = nullptr;
   std::vector<GSummary*> inst_host;  // per-instance host slots
   std::vector<long long> off, len;   // packed offsets and lengths
+  // batch: captured inner iterations (null: launch kernel by kernel)
+  struct GraphCache* graphs = nullptr;
+};
+
+// One captured graph per inner-iteration index j of a batch: the transform
+// launches of every N_t group, the interface solves, the Krylov kernels with
+// their finishing reductions and the batch summary.  Every argument of those
+// launches is fixed for a batch except (j, stop_iter, rtol), the cache key.
+struct GraphCache {
+  hipStream_t cap = nullptr;  // capture stream (the solve stream may be the null stream)
+  struct Entry {
+    int j, stop_iter;
+    double rtol;
+    hipGraph_t g;
+    hipGraphExec_t x;
+  };
+  std::vector<Entry> entries;
+  void release() {
+    for (Entry& e : entries) {
+      (void)hipGraphExecDestroy(e.x);
+      (void)hipGraphDestroy(e.g);
+    }
+    entries.clear();
+    if (cap != nullptr) (void)hipStreamDestroy(cap);
+    cap = nullptr;
+  }
 };
 
 static hipError_t enqueue_iteration(SolveCtx& c, int j, int stop_iter, double rtol, int slot,
@@ -639,6 +665,35 @@ static hipError_t enqueue_iteration(SolveCtx& c, int j, int stop_iter, double rt
 static cn_status batch_publish(SolveCtx& c, int slot, int* seq) {
   HIP_TRY(launch_batch_summary(c.L, c.dcounter, c.bh_dev + slot, c.s));
   *seq = ++(*c.bseq);
+  return CN_OK;
+}
+
+// Launch the captured graph of inner iteration j (capturing it on first use):
+// the same launches as enqueue_iteration + batch_publish on slot j & 1.
+static cn_status launch_iteration_graph(SolveCtx& c, int j, int stop_iter, double rtol) {
+  GraphCache& gc = *c.graphs;
+  for (const GraphCache::Entry& e : gc.entries)
+    if (e.j == j && e.stop_iter == stop_iter && e.rtol == rtol) {
+      HIP_TRY(hipGraphLaunch(e.x, c.s));
+      return CN_OK;
+    }
+  if (gc.cap == nullptr) HIP_TRY(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
+  SolveCtx cc = c;
+  cc.s = gc.cap;
+  HIP_TRY(hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_iteration(cc, j, stop_iter, rtol, j & 1, 0);
+  if (e == hipSuccess) e = launch_batch_summary(cc.L, cc.dcounter, cc.bh_dev + (j & 1), gc.cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(gc.cap, &g);
+  if (e == hipSuccess) e = e2;
+  hipGraphExec_t x = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (g != nullptr) (void)hipGraphDestroy(g);
+    return fail(CN_EHIP, std::string("iteration graph: ") + hipGetErrorString(e));
+  }
+  gc.entries.push_back(GraphCache::Entry{j, stop_iter, rtol, g, x});
+  HIP_TRY(hipGraphLaunch(x, c.s));
   return CN_OK;
 }
 
@@ -665,8 +720,13 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
     int known = 0;  // iterations of this cycle whose summary the host has read
     for (int j = 0; j < m_eff; ++j) {
       seqs[j] = c.batched ? 0 : ++(*c.seqc);
-      HIP_TRY(enqueue_iteration(c, j, m_eff, rtol, j & 1, seqs[j]));
-      if (c.batched) CN_TRY(batch_publish(c, j & 1, &seqs[j]));
+      if (c.graphs != nullptr) {
+        CN_TRY(launch_iteration_graph(c, j, m_eff, rtol));
+        seqs[j] = ++(*c.bseq);
+      } else {
+        HIP_TRY(enqueue_iteration(c, j, m_eff, rtol, j & 1, seqs[j]));
+        if (c.batched) CN_TRY(batch_publish(c, j & 1, &seqs[j]));
+      }
       GSummary* slots = c.batched ? c.bh : c.hs;
       if (j >= 1) {
         if (known < j) {
@@ -810,11 +870,13 @@ struct cn_batch {
   GSummary* bh_dev = nullptr;
   int* dcounter = nullptr;
   int bseq = 0;
+  GraphCache graphs;
 };
 
 static void batch_release(cn_batch* b) {
   if (b == nullptr) return;
   (void)hipStreamSynchronize(b->stream);
+  b->graphs.release();
   for (cn_aao* h : b->inst) release(h);
   b->wl.release();
   for (int2* p : b->pc_lists) (void)hipFree(p);
@@ -875,6 +937,7 @@ cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_o
   if (opts->m < 1 || opts->m > h->m_max) return fail(CN_EINVAL, "opts->m must be in [1, m_max]");
   if (opts->max_iters < 1) return fail(CN_EINVAL, "opts->max_iters must be >= 1");
   if (opts->use_x0 < 0 || opts->use_x0 > 2) return fail(CN_EINVAL, "opts->use_x0 must be 0, 1 or 2");
+  if (opts->flags & ~CN_SOLVE_NO_GRAPHS) return fail(CN_EINVAL, "unknown bits in opts->flags");
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
   if (overlaps(b, x, h->n * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
@@ -1060,6 +1123,7 @@ cn_status cn_batch_solve(cn_batch* b, const double* bp, double* xp, const cn_gmr
     return fail(CN_EINVAL, "opts->m must be in [1, smallest m_max of the batch]");
   if (opts->max_iters < 1) return fail(CN_EINVAL, "opts->max_iters must be >= 1");
   if (opts->use_x0 < 0 || opts->use_x0 > 2) return fail(CN_EINVAL, "opts->use_x0 must be 0, 1 or 2");
+  if (opts->flags & ~CN_SOLVE_NO_GRAPHS) return fail(CN_EINVAL, "unknown bits in opts->flags");
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
   if (overlaps(bp, xp, b->off.back() * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
@@ -1077,6 +1141,7 @@ cn_status cn_batch_solve(cn_batch* b, const double* bp, double* xp, const cn_gmr
   c.bh_dev = b->bh_dev;
   c.dcounter = b->dcounter;
   c.bseq = &b->bseq;
+  if (!(opts->flags & CN_SOLVE_NO_GRAPHS)) c.graphs = &b->graphs;
   for (size_t i = 0; i < b->inst.size(); ++i) {
     c.inst_host.push_back(b->inst[i]->hsum);
     c.off.push_back(b->off[i]);
