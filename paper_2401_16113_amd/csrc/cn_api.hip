@@ -77,11 +77,6 @@ static hipError_t upload_items(const std::vector<int2>& v, int2** dptr, Items* i
   return e;
 }
 
-static int k2_threads_for(int ns) {
-  int thr = 64;
-  while (thr < 256 && thr < ns) thr *= 2;
-  return thr;
-}
 
 struct cn_aao {
   int nx = 0, nt = 0, m_max = 0, flags = 0;
@@ -105,7 +100,7 @@ struct cn_aao {
   InstDesc* d_desc = nullptr;
   WorkLists wl;
   Launch L{};
-  int k2_thr = 64;
+  int k2_thr = 32 * 16;  // interface-solve variant (k2_chunk_class)
   std::vector<void*> dev_allocs;
 };
 
@@ -181,7 +176,16 @@ static hipError_t build_launch(cn_aao* h) {
   if (e == hipSuccess) e = upload_items(mv, &h->wl.mv, &h->wl.I_mv);
   if (e == hipSuccess) e = upload_items(stv, &h->wl.st, &h->wl.I_st);
   h->L = Launch{h->d_desc, 1, h->prec};
-  h->k2_thr = k2_threads_for(h->pl.NS);
+  h->k2_thr = k2_chunk_class(h->pl.NS);
+  // CN_K2_CLASS=32W+CH forces an interface-solve variant (tests); a
+  // register variant too small for the chunk falls back to the default
+  if (const char* f = getenv("CN_K2_CLASS")) {
+    const int c = atoi(f), w = c / 32, ch = c % 32;
+    const int chunk = (h->pl.NS + 64 * w - 1) / (64 * std::max(w, 1));
+    const bool known = (w == 1 || w == 4 || w == 16) &&
+                       (ch == 0 ? w == 16 : (ch == 1 || ch == 2 || ch == 4 || (ch == 8 && w < 16)));
+    if (known && (ch == 0 || chunk <= ch)) h->k2_thr = c;
+  }
   return e;
 }
 
@@ -607,7 +611,7 @@ struct SolveCtx {
   Launch L{};
   std::vector<PcGroup> groups;  // transform launches (one per N_t group)
   Items k2, mv, stv;
-  int k2_thr = 64;
+  int k2_thr = 32 * 16;  // interface-solve variant (k2_chunk_class)
   int prec = 0;
   bool batched = false;
   // one instance: its host slots and sequence counter
@@ -865,7 +869,7 @@ struct cn_batch {
   WorkLists wl;                    // k2, mv, st lists (pc lists per group below)
   std::vector<int2*> pc_lists;
   std::vector<PcGroup> groups;
-  int k2_thr = 64;
+  int k2_thr = 32 * 16;  // interface-solve variant (k2_chunk_class)
   GSummary* bh = nullptr;          // 3 batch-summary slots (pinned coherent)
   GSummary* bh_dev = nullptr;
   int* dcounter = nullptr;
@@ -1070,7 +1074,7 @@ cn_status cn_batch_create(const cn_problem* probs, int32_t count, cn_batch** out
     b->pc_lists.push_back(dptr);
     b->groups.push_back(PcGroup{b->prec, kv.first, group_cand[kv.first], it});
   }
-  b->k2_thr = k2_threads_for(max_ns);
+  b->k2_thr = k2_chunk_class(max_ns);
   if (e == hipSuccess) e = hipMalloc((void**)&b->dcounter, sizeof(int));
   if (e == hipSuccess) e = hipMemset(b->dcounter, 0, sizeof(int));
   if (e == hipSuccess)

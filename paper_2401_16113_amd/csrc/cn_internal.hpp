@@ -105,7 +105,9 @@ struct Items {
 hipError_t pc_setup(PcPlan& pl, Cx<double>* spk, int* err_dev, hipStream_t s);
 hipError_t pc_forward(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
                       const double* v, hipStream_t s);
-hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int threads, int j,
+// chunk_class: k2_chunk_class(largest NS of the launch)
+int k2_chunk_class(int ns);
+hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int chunk_class, int j,
                       int standalone, hipStream_t s);
 hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
                       void* z, int zf, hipStream_t s);

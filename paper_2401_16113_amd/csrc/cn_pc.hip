@@ -25,64 +25,78 @@
 namespace cn {
 
 // ---------------------------------------------------------------------------
-// K2: interface (separator) systems, one workgroup per frequency line j.
+// K2: interface (separator) systems, one line (frequency j) per W wavefronts:
 //   rho_s = d_s + lo_s y_last(s) + up_s y_first(s+1)           (s = 0..NS-1)
 //   forward  rho'_s = a_s rho'_{s-1} + rho_s,       a_s  = -m_s
 //   backward S_s    = ap_s S_{s+1} + inv_s rho'_s,  ap_s = -c_s inv_s
-// Each recurrence is an affine scan: chunk-local composition, a Hillis-Steele
-// scan of the chunk maps in LDS, then a replay with the carried value.
+// Each recurrence is an affine scan: every lane composes the maps of its
+// chunk of consecutive separators, a Hillis-Steele scan of the lane maps runs
+// on cross-lane shuffles, the W wave aggregates are chained through LDS
+// (W > 1), then every lane replays its chunk from the carried value.  With
+// CH > 0 a lane loads its whole chunk (<= CH separators) up front and keeps
+// rho' in registers; CH = 0 (very wide instances) streams through the rho'
+// scratch array.  W = 1 packs four lines into a 256-thread workgroup.
 // ---------------------------------------------------------------------------
 constexpr int K2_THREADS = 256;
 
-__device__ __forceinline__ void affine_scan(Cx<double>& A, Cx<double>& Bv, Cx<double>* sA,
-                                            Cx<double>* sB, int pos, int n) {
-  sA[pos] = A;
-  sB[pos] = Bv;
-  __syncthreads();
-  for (int off = 1; off < n; off <<= 1) {
-    Cx<double> pa{1.0, 0.0}, pb{0.0, 0.0};
-    const bool has = pos >= off;
+__device__ __forceinline__ Cx<double> shfl_up_c(Cx<double> v, int off) {
+  return Cx<double>{__shfl_up(v.x, off, 64), __shfl_up(v.y, off, 64)};
+}
+__device__ __forceinline__ Cx<double> shfl_down_c(Cx<double> v, int off) {
+  return Cx<double>{__shfl_down(v.x, off, 64), __shfl_down(v.y, off, 64)};
+}
+
+// Scan of the maps r -> A r + Bv held by the line's lanes in lane order (UP)
+// or in reverse order; returns the value carried into the lane's chunk (the
+// composed map of all preceding lanes applied to 0).
+template <bool UP, int W>
+__device__ __forceinline__ Cx<double> line_carry(Cx<double> A, Cx<double> Bv, int lane, int wave,
+                                                 Cx<double>* sA, Cx<double>* sB) {
+  const Cx<double> one{1.0, 0.0}, zero{0.0, 0.0};
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const Cx<double> pa = UP ? shfl_up_c(A, off) : shfl_down_c(A, off);
+    const Cx<double> pb = UP ? shfl_up_c(Bv, off) : shfl_down_c(Bv, off);
+    const bool has = UP ? lane >= off : lane + off < 64;
     if (has) {
-      pa = sA[pos - off];
-      pb = sB[pos - off];
+      Bv = A * pb + Bv;
+      A = A * pa;
+    }
+  }
+  Cx<double> eA = UP ? shfl_up_c(A, 1) : shfl_down_c(A, 1);
+  Cx<double> eB = UP ? shfl_up_c(Bv, 1) : shfl_down_c(Bv, 1);
+  if (UP ? lane == 0 : lane == 63) {
+    eA = one;
+    eB = zero;
+  }
+  if constexpr (W == 1) {
+    return eB;
+  } else {
+    __syncthreads();  // earlier readers of sA/sB are done
+    if (UP ? lane == 63 : lane == 0) {
+      sA[wave] = A;
+      sB[wave] = Bv;
     }
     __syncthreads();
-    if (has) {
-      const Cx<double> nA = A * pa;
-      const Cx<double> nB = A * pb + Bv;
-      A = nA;
-      Bv = nB;
-      sA[pos] = A;
-      sB[pos] = Bv;
+    Cx<double> c = zero;
+    if (UP) {
+      for (int u = 0; u < wave; ++u) c = sA[u] * c + sB[u];
+    } else {
+      for (int u = W - 1; u > wave; --u) c = sA[u] * c + sB[u];
     }
-    __syncthreads();
+    return eA * c + eB;
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(K2_THREADS) void k_pc_reduced(const InstDesc* __restrict__ D,
-                                                           const int2* __restrict__ items,
-                                                           int standalone) {
-  __shared__ Cx<double> sA[K2_THREADS], sB[K2_THREADS];
-  const int2 wi = items[blockIdx.x];
-  const InstDesc& d = D[wi.x];
-  const PcPlan& pl = d.pl;
-  if (!standalone && d.st->sum.done) return;
-  const Cx<R>* __restrict__ iface = (const Cx<R>*)pl.iface;
-  Cx<R>* __restrict__ sep = (Cx<R>*)pl.sep;
-  const Cx<double>* __restrict__ ra = pl.red_a;
-  const Cx<double>* __restrict__ rap = pl.red_ap;
-  const Cx<double>* __restrict__ rinv = pl.red_inv;
-  Cx<double>* __restrict__ rtmp = pl.red_tmp;
-  const double* __restrict__ lo = pl.lo;
-  const double* __restrict__ up = pl.up;
-  const int P = pl.P, NS = pl.NS, B = pl.B;
-  const int j = wi.y;
-  const int tid = threadIdx.x, n = blockDim.x;
-  const int chunk = (NS + n - 1) / n;
-  const int s0 = min(NS, tid * chunk), s1 = min(NS, s0 + chunk);
-  const size_t row = (size_t)j * NS;
-  const Cx<R>* f = iface + (size_t)j * P * 3;
+template <typename R, int W, int CH>
+__device__ __forceinline__ void reduced_line(
+    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const Cx<double>* __restrict__ ra,
+    const Cx<double>* __restrict__ rap, const Cx<double>* __restrict__ rinv,
+    Cx<double>* __restrict__ rtmp, const double* __restrict__ lo,
+    const double* __restrict__ up, int NS, int B, int t, Cx<double>* sA, Cx<double>* sB) {
+  const int lane = t & 63, wave = t >> 6;
+  const int chunk = (NS + 64 * W - 1) / (64 * W);
+  const int s0 = min(NS, t * chunk), s1 = min(NS, s0 + chunk);
   auto rho = [&](int s) -> Cx<double> {
     const int is = (s + 1) * B - 1;
     const Cx<R> d = f[(size_t)s * 3 + 0], yl = f[(size_t)s * 3 + 1], yf = f[(size_t)(s + 1) * 3 + 2];
@@ -90,35 +104,97 @@ __global__ __launch_bounds__(K2_THREADS) void k_pc_reduced(const InstDesc* __res
     return Cx<double>{(double)d.x + l * (double)yl.x + u * (double)yf.x,
                       (double)d.y + l * (double)yl.y + u * (double)yf.y};
   };
-  // forward sweep
-  Cx<double> A{1.0, 0.0}, Bv{0.0, 0.0};
-  for (int s = s0; s < s1; ++s) {
-    const Cx<double> a = ra[row + s];
-    Bv = a * Bv + rho(s);
-    A = a * A;
+  const Cx<double> one{1.0, 0.0}, zero{0.0, 0.0};
+  if constexpr (CH > 0) {
+    // every operand of the lane's chunk is loaded up front (independent
+    // loads, one memory latency); padding entries are identity maps
+    Cx<double> a[CH], rh[CH], ap[CH], iv[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int s = s0 + q;
+      a[q] = s < s1 ? ra[s] : one;
+      rh[q] = s < s1 ? rho(s) : zero;
+    }
+    Cx<double> A = one, Bv = zero;
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      Bv = a[q] * Bv + rh[q];
+      A = a[q] * A;
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int s = s0 + q;
+      ap[q] = s < s1 ? rap[s] : one;
+      iv[q] = s < s1 ? rinv[s] : zero;
+    }
+    Cx<double> r = line_carry<true, W>(A, Bv, lane, wave, sA, sB);
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      r = a[q] * r + rh[q];
+      rh[q] = r;  // rho'_s
+    }
+    A = one;
+    Bv = zero;
+#pragma unroll
+    for (int q = CH - 1; q >= 0; --q) {
+      Bv = ap[q] * Bv + iv[q] * rh[q];
+      A = ap[q] * A;
+    }
+    Cx<double> S = line_carry<false, W>(A, Bv, lane, wave, sA, sB);
+#pragma unroll
+    for (int q = CH - 1; q >= 0; --q) {
+      S = ap[q] * S + iv[q] * rh[q];
+      const int s = s0 + q;
+      if (s < s1) sep[s] = Cx<R>{(R)S.x, (R)S.y};
+    }
+  } else {
+    Cx<double> A = one, Bv = zero;
+#pragma unroll 4
+    for (int s = s0; s < s1; ++s) {
+      const Cx<double> a = ra[s];
+      Bv = a * Bv + rho(s);
+      A = a * A;
+    }
+    Cx<double> r = line_carry<true, W>(A, Bv, lane, wave, sA, sB);
+#pragma unroll 4
+    for (int s = s0; s < s1; ++s) {
+      r = ra[s] * r + rho(s);
+      rtmp[s] = r;
+    }
+    A = one;
+    Bv = zero;
+#pragma unroll 4
+    for (int s = s1 - 1; s >= s0; --s) {
+      const Cx<double> a = rap[s];
+      Bv = a * Bv + rinv[s] * rtmp[s];
+      A = a * A;
+    }
+    Cx<double> S = line_carry<false, W>(A, Bv, lane, wave, sA, sB);
+#pragma unroll 4
+    for (int s = s1 - 1; s >= s0; --s) {
+      S = rap[s] * S + rinv[s] * rtmp[s];
+      sep[s] = Cx<R>{(R)S.x, (R)S.y};
+    }
   }
-  affine_scan(A, Bv, sA, sB, tid, n);
-  Cx<double> r = tid > 0 ? sB[tid - 1] : Cx<double>{0.0, 0.0};
-  for (int s = s0; s < s1; ++s) {
-    r = ra[row + s] * r + rho(s);
-    rtmp[row + s] = r;
-  }
-  __syncthreads();
-  // backward sweep, scanned from the last chunk
-  const int pos = n - 1 - tid;
-  A = Cx<double>{1.0, 0.0};
-  Bv = Cx<double>{0.0, 0.0};
-  for (int s = s1 - 1; s >= s0; --s) {
-    const Cx<double> a = rap[row + s];
-    Bv = a * Bv + rinv[row + s] * rtmp[row + s];
-    A = a * A;
-  }
-  affine_scan(A, Bv, sA, sB, pos, n);
-  Cx<double> S = pos > 0 ? sB[pos - 1] : Cx<double>{0.0, 0.0};
-  for (int s = s1 - 1; s >= s0; --s) {
-    S = rap[row + s] * S + rinv[row + s] * rtmp[row + s];
-    sep[row + s] = Cx<R>{(R)S.x, (R)S.y};
-  }
+}
+
+template <typename R, int W, int CH>
+__global__ __launch_bounds__(W == 1 ? K2_THREADS : 64 * W) void k_pc_reduced(
+    const InstDesc* __restrict__ D, const int2* __restrict__ items, int nitems, int standalone) {
+  __shared__ Cx<double> sA[W], sB[W];
+  // W == 1: four lines per workgroup, one per wavefront; else one line
+  const int item = W == 1 ? blockIdx.x * (K2_THREADS / 64) + (threadIdx.x >> 6) : blockIdx.x;
+  const int t = W == 1 ? (threadIdx.x & 63) : threadIdx.x;
+  if (item >= nitems) return;  // uniform over the line
+  const int2 wi = items[item];
+  const InstDesc& d = D[wi.x];
+  const PcPlan& pl = d.pl;
+  if (!standalone && d.st->sum.done) return;
+  const int j = wi.y;
+  const size_t row = (size_t)j * pl.NS;
+  reduced_line<R, W, CH>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 3, (Cx<R>*)pl.sep + row,
+                         pl.red_a + row, pl.red_ap + row, pl.red_inv + row, pl.red_tmp + row,
+                         pl.lo, pl.up, pl.NS, pl.B, t, sA, sB);
 }
 
 // ---------------------------------------------------------------------------
@@ -258,16 +334,42 @@ hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Item
               : pc_inverse_f64(log2n, cand, L, it, j, z, zf, s);
 }
 
-hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int threads, int j,
+// Interface-solve variant for separator systems of up to `ns` unknowns:
+// 32 W + CH with W wavefronts per line and CH separators per lane held in
+// registers (CH = 0: streamed), the fewest wavefronts that keep the chunk in
+// registers without spilling (CH <= 8; <= 4 with 1024-thread workgroups).
+int k2_chunk_class(int ns) {
+  for (int w : {1, 4, 16}) {
+    const int chunk = (ns + 64 * w - 1) / (64 * w);
+    for (int c = 1; c <= (w == 16 ? 4 : 8); c *= 2)
+      if (chunk <= c) return 32 * w + c;
+  }
+  return 32 * 16;
+}
+
+hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int chunk_class, int j,
                       int standalone, hipStream_t s) {
   (void)j;
   if (it.n <= 0) return hipSuccess;
-  if (prec)
-    hipLaunchKernelGGL((k_pc_reduced<float>), dim3(it.n), dim3(threads), 0, s, L.D, it.it,
-                       standalone);
-  else
-    hipLaunchKernelGGL((k_pc_reduced<double>), dim3(it.n), dim3(threads), 0, s, L.D, it.it,
-                       standalone);
+  switch (chunk_class) {
+#define K2(W, CH)                                                                              \
+  case 32 * W + CH: {                                                                          \
+    const dim3 grid(W == 1 ? (it.n + 3) / 4 : it.n), block(W == 1 ? K2_THREADS : 64 * W);    \
+    if (prec)                                                                                  \
+      hipLaunchKernelGGL((k_pc_reduced<float, W, CH>), grid, block, 0, s, L.D, it.it, it.n,   \
+                         standalone);                                                          \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_pc_reduced<double, W, CH>), grid, block, 0, s, L.D, it.it, it.n,  \
+                         standalone);                                                          \
+    break;                                                                                     \
+  }
+    K2(1, 1) K2(1, 2) K2(1, 4) K2(1, 8)
+    K2(4, 1) K2(4, 2) K2(4, 4) K2(4, 8)
+    K2(16, 1) K2(16, 2) K2(16, 4) K2(16, 0)
+#undef K2
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

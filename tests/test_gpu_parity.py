@@ -62,6 +62,25 @@ def pc_tol(alpha, prec, nt):
     return max(0.1 * nt * EPS32 / alpha, 1e-5)
 
 
+def shifted_condition(inst):
+    """Condition estimate of the worst shifted system of step (b) (Sec. 3.1):
+    the lowest mode solves (mu_0 I - A~) with mu_0 = lambda_{1,0}/lambda_{2,0}
+    = 2 (1 - alpha^{1/N_t}) / (1 + alpha^{1/N_t}), so kappa ~ 1 + ||A~|| / mu_0.
+    It grows like N_x^2 N_t; on wide grids it, not N_t/alpha, sets the
+    rounding floor of both the kernels and the oracle."""
+    q = inst.alpha ** (1.0 / inst.nt)
+    mu0 = 2.0 * (1.0 - q) / (1.0 + q)
+    tau = inst.T / inst.nt
+    norm = tau * np.max(np.abs(inst.a_lo) + np.abs(inst.a_di) + np.abs(inst.a_up))
+    return 1.0 + norm / mu0
+
+
+def pc_tol_wide(inst, prec):
+    """pc_tol plus the shifted systems' conditioning times the precision."""
+    eps = EPS64 if prec == "fp64" else EPS32
+    return pc_tol(inst.alpha, prec, inst.nt) + eps * shifted_condition(inst)
+
+
 # ---------------------------------------------------------------------------
 # matvec and right-hand side
 # ---------------------------------------------------------------------------
@@ -344,3 +363,57 @@ def test_pc_apply_every_variant(nx, nt, prec, monkeypatch):
         s.close()
         ran += 1
     assert ran >= 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nx,nt,tile", [(16383, 64, "16,256"), (16383, 64, "8,256"),
+                                        (16383, 128, "4,256"), (65535, 128, "4,256")])
+def test_interface_solve_variants(nx, nt, tile, prec, monkeypatch):
+    """Wide instances select the interface-solve layouts with 4 and 16
+    wavefronts per frequency line, separators held in registers or streamed
+    (1023, 2047, 4095 and 16383 separators).  Every element against the
+    oracle for N_x = 16383 (bound: pc_tol plus precision times the shifted
+    systems' condition number, which reaches ~1e6 on this grid); the widest
+    through the defining operator of eq. (3.1) (P_alpha z = v)."""
+    monkeypatch.setenv("CN_PC_TILE", tile)
+    inst = localvol(nx, nt)
+    banner(f"interface solve {prec} nx={nx} tile={tile}")
+    s = solver(inst, pc_prec=prec)
+    v = W.random_vector(inst.n, 21)
+    z = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+    s.pc_apply(T(v), z)
+    zh = z.cpu().numpy()
+    if nx <= 16383:
+        ref = O.pc_apply(*oracle_args(inst), inst.alpha, v)
+        err = rel_inf(zh, ref)
+    else:
+        # residual in the defining operator; a backward-stable solve keeps it
+        # below eps ||mu I - A~|| ||y||, i.e. eps kappa ||r|| when a random
+        # right-hand side excites the lowest modes: same bound
+        err = np.linalg.norm(O.pc_matvec(*oracle_args(inst), inst.alpha, zh) - v) / np.linalg.norm(v)
+    tol = pc_tol_wide(inst, prec)
+    print(f"  err={err:.3e} bound={tol:.3e} kappa={shifted_condition(inst):.3e} "
+          f"tiles={s.query()}")
+    assert err <= tol
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_interface_solve_variant_matches_oracle(prec, monkeypatch):
+    """Each layout of the interface solve (1, 4 or 16 wavefronts per line;
+    2..8 separators per lane in registers, or streamed) forced on the same
+    255-separator system, every element against the oracle."""
+    monkeypatch.setenv("CN_PC_TILE", "16,256")
+    inst = localvol(4095, 64)
+    v = W.random_vector(inst.n, 23)
+    ref = O.pc_apply(*oracle_args(inst), inst.alpha, v)
+    for cls in (36, 40, 129, 130, 132, 136, 513, 514, 516, 512):
+        monkeypatch.setenv("CN_K2_CLASS", str(cls))
+        banner(f"interface variant {cls} {prec}")
+        s = solver(inst, pc_prec=prec)
+        assert s.query()["tiles"] == 256
+        z = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+        s.pc_apply(T(v), z)
+        err = rel_inf(z.cpu().numpy(), ref)
+        assert err <= pc_tol_wide(inst, prec), (cls, err)
+        s.close()
