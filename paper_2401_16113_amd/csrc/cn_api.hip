@@ -176,6 +176,9 @@ static hipError_t build_launch(cn_aao* h) {
   if (e == hipSuccess) e = upload_items(mv, &h->wl.mv, &h->wl.I_mv);
   if (e == hipSuccess) e = upload_items(stv, &h->wl.st, &h->wl.I_st);
   h->L = Launch{h->d_desc, 1, h->prec};
+  // one instance: kernels derive the work items from the block index, which
+  // saves a dependent load at the start of every workgroup
+  h->wl.I_pc.it = h->wl.I_k2.it = h->wl.I_mv.it = h->wl.I_st.it = nullptr;
   h->k2_thr = k2_chunk_class(h->pl.NS);
   // CN_K2_CLASS=32W+CH forces an interface-solve variant (tests); a
   // register variant too small for the chunk falls back to the default

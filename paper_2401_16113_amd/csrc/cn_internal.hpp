@@ -96,9 +96,14 @@ struct Launch {
 
 // Work list of one kernel kind: items[i] = (instance, local block).
 struct Items {
-  const int2* it = nullptr;
+  const int2* it = nullptr;  // null: one instance, item i = (0, i) (no list to read)
   int n = 0;
 };
+
+// Work item i of a launch (instance, local block).
+__device__ __forceinline__ int2 work_item(const int2* __restrict__ items, int i) {
+  return items != nullptr ? items[i] : make_int2(0, i);
+}
 
 // Launchers (cn_pc.hip, cn_pc_f64.hip, cn_pc_f32.hip).  `v`/`z` override the
 // basis vector V_j / Z_j of a single instance (standalone apply, no stop flag).

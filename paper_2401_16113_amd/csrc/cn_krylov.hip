@@ -107,7 +107,7 @@ __global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
                                                double* __restrict__ yo, int x_zero) {
   constexpr int NA = NV > 2 ? NV : 2;
   __shared__ double red[(KT / 64) * NA];
-  const int2 wi = items[blockIdx.x];
+  const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
   if (MODE == 2 && d.st->sum.done) return;
   const TX* __restrict__ x;
@@ -184,7 +184,7 @@ template <int NV>
 __global__ __launch_bounds__(KT) void k_cgs_pass1(const InstDesc* __restrict__ D,
                                                   const int2* __restrict__ items, int j) {
   __shared__ double red[(KT / 64) * NV];
-  const int2 wi = items[blockIdx.x];
+  const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
   const GState* st = d.st;
   if (st->sum.done) return;
@@ -219,7 +219,7 @@ template <int NV>
 __global__ __launch_bounds__(KT) void k_cgs_pass2(const InstDesc* __restrict__ D,
                                                   const int2* __restrict__ items, int j) {
   __shared__ double red[(KT / 64) * 2];
-  const int2 wi = items[blockIdx.x];
+  const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
   const GState* st = d.st;
   if (st->sum.done) return;
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(KT) void k_fallback(const InstDesc* __restrict__ D,
                                                  const int2* __restrict__ items,
                                                  const double* __restrict__ bb,
                                                  double* __restrict__ xb) {
-  const int2 wi = items[blockIdx.x];
+  const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
   if (!d.st->sum.x0_rejected) return;
   const double* __restrict__ b = bb + d.off;
@@ -373,7 +373,7 @@ template <typename TZ>
 __global__ __launch_bounds__(KT) void k_update(const InstDesc* __restrict__ D,
                                                const int2* __restrict__ items,
                                                double* __restrict__ xb, int x_zero) {
-  const int2 wi = items[blockIdx.x];
+  const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
   const GState* st = d.st;
   const int k = st->sum.k;

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(W == 1 ? K2_THREADS : 64 * W) void k_pc_reduced(
   const int item = W == 1 ? blockIdx.x * (K2_THREADS / 64) + (threadIdx.x >> 6) : blockIdx.x;
   const int t = W == 1 ? (threadIdx.x & 63) : threadIdx.x;
   if (item >= nitems) return;  // uniform over the line
-  const int2 wi = items[item];
+  const int2 wi = work_item(items, item);
   const InstDesc& d = D[wi.x];
   const PcPlan& pl = d.pl;
   if (!standalone && d.st->sum.done) return;

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
                                                    const double* __restrict__ v_ovr) {
   const int itx = xcd_tile(blockIdx.x, nitems_pad);
   if (itx >= nitems) return;
-  const int2 wi = items[itx];
+  const int2 wi = work_item(items, itx);
   const InstDesc& d = D[wi.x];
   const PcPlan& pl = d.pl;
   // inside a solve: input V_j scaled by 1/||v_j||, skipped once the cycle stopped
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ 
                                                    int nitems_pad, int jv, TZ* __restrict__ z_ovr) {
   const int itx = xcd_tile(blockIdx.x, nitems_pad);
   if (itx >= nitems) return;
-  const int2 wi = items[itx];
+  const int2 wi = work_item(items, itx);
   const InstDesc& d = D[wi.x];
   const PcPlan& pl = d.pl;
   if (z_ovr == nullptr && d.st->sum.done) return;
