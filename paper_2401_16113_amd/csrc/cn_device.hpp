@@ -137,7 +137,18 @@ struct PcCfg {
   // padded LDS layout: one spare complex slot every 16, plus one per sequence
   static constexpr int SSTRIDE = N + N / 16 + 1;
   static constexpr int LDS_ELEMS = NSEQ * SSTRIDE;
-  static constexpr int LDS_BYTES = LDS_ELEMS * 2 * (int)sizeof(R) + 3 * B * (int)sizeof(R);
+  static constexpr int LDS_BASE = LDS_ELEMS * 2 * (int)sizeof(R) + 3 * B * (int)sizeof(R);
+  // the twiddle table e^{-2 pi i m/N} is staged in LDS when it fits beside
+  // the tile (its global reads would otherwise sit on every FFT pass): the
+  // whole table, else its first half (w^{m+N/2} = -w^m), else none
+  static constexpr int TW_BYTES = N * 2 * (int)sizeof(R);
+  static constexpr int TWMODE = LDS_BASE + TW_BYTES <= 150 * 1024       ? 2
+                                : LDS_BASE + TW_BYTES / 2 <= 150 * 1024 ? 1
+                                                                        : 0;
+  static constexpr bool TWL = TWMODE > 0;
+  static constexpr int TWN = TWMODE == 2 ? N : (TWMODE == 1 ? (N > 1 ? N / 2 : 1) : 1);
+  static constexpr int LDS_BYTES = LDS_BASE + (TWL ? TWN * 2 * (int)sizeof(R) : 0);
+  static constexpr int TWPT = (TWN + T - 1) / T;            // table entries per thread
   static constexpr int TASKS = N >= 2 ? N / 2 : 1;          // step-(b) tasks
 };
 
@@ -168,8 +179,8 @@ __device__ __forceinline__ int lidx(int s, int e) {
 // One Stockham radix-2^LR pass over NSEQ sequences of length N held in LDS.
 // p is the product of the radices of earlier passes.  All inputs of the pass
 // are read to registers before a barrier, so the pass runs in place.
-template <typename R, int N, int NSEQ, int T, bool INV, int LR, int P>
-__device__ __forceinline__ void fft_pass(Cx<R>* lds, const Cx<R>* __restrict__ tw) {
+template <typename R, int N, int NSEQ, int T, bool INV, int LR, int P, typename TW>
+__device__ __forceinline__ void fft_pass(Cx<R>* lds, const TW& tw) {
   constexpr int RAD = 1 << LR;
   constexpr int NQ = N / RAD;             // butterflies per sequence
   constexpr int NB = NSEQ * NQ;           // butterflies in the pass
@@ -197,7 +208,7 @@ __device__ __forceinline__ void fft_pass(Cx<R>* lds, const Cx<R>* __restrict__ t
         constexpr int SCL = N / (P * RAD);
 #pragma unroll
         for (int r = 1; r < RAD; ++r) {
-          Cx<R> w = tw[r * k * SCL];
+          Cx<R> w = tw(r * k * SCL);
           if (INV) w.y = -w.y;
           u[q][r] = u[q][r] * w;
         }
@@ -211,12 +222,63 @@ __device__ __forceinline__ void fft_pass(Cx<R>* lds, const Cx<R>* __restrict__ t
   __syncthreads();
 }
 
-template <typename R, int LOG2N, int NSEQ, int T, bool INV, int MAXLOG, int DONE>
-__device__ __forceinline__ void fft_run(Cx<R>* lds, const Cx<R>* __restrict__ tw) {
+// Twiddle staging in two halves so that the table's global reads can be
+// issued after (and overlap) the tile's own loads: fetch the first TWN
+// entries, then store them to LDS (visible after the next barrier).
+template <typename R, int TWN, int T, int TWPT>
+struct TwStage {
+  Cx<R> v[TWPT];
+  __device__ __forceinline__ void fetch(const Cx<R>* __restrict__ tw) {
+#pragma unroll
+    for (int q = 0; q < TWPT; ++q) {
+      const int m = threadIdx.x + q * T;
+      if (TWN % T == 0 || m < TWN) v[q] = tw[m];
+    }
+  }
+  __device__ __forceinline__ void store(Cx<R>* ltw) {
+#pragma unroll
+    for (int q = 0; q < TWPT; ++q) {
+      const int m = threadIdx.x + q * T;
+      if (TWN % T == 0 || m < TWN) ltw[m] = v[q];
+    }
+  }
+};
+
+// Twiddle w^m, m in [0, N), from a full table (HALF = false) or from its
+// first half (w^{m+N/2} = -w^m).
+template <typename R, int N, bool HALF>
+struct TwTab {
+  const Cx<R>* t;
+  __device__ __forceinline__ Cx<R> operator()(int m) const {
+    if constexpr (HALF) {
+      const bool up = m >= N / 2;
+      const Cx<R> w = t[up ? m - N / 2 : m];
+      return up ? Cx<R>{-w.x, -w.y} : w;
+    } else {
+      return t[m];
+    }
+  }
+};
+
+template <typename R, int LOG2N, int NSEQ, int T, bool INV, int MAXLOG, int DONE, typename TW>
+__device__ __forceinline__ void fft_run(Cx<R>* lds, const TW& tw) {
   if constexpr (DONE < LOG2N) {
     constexpr int LR = (DONE == 0 && (LOG2N % MAXLOG) != 0) ? (LOG2N % MAXLOG) : MAXLOG;
     fft_pass<R, (1 << LOG2N), NSEQ, T, INV, LR, (1 << DONE)>(lds, tw);
     fft_run<R, LOG2N, NSEQ, T, INV, MAXLOG, DONE + LR>(lds, tw);
+  }
+}
+
+// FFT with the twiddles from LDS (staged as Cfg says) or from global memory.
+template <typename Cfg, typename R, int LOG2N, bool INV>
+__device__ __forceinline__ void fft_tile(Cx<R>* lds, const Cx<R>* ltw, const Cx<R>* __restrict__ tw) {
+  constexpr int N = 1 << LOG2N;
+  if constexpr (Cfg::TWMODE == 2) {
+    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, false>{ltw});
+  } else if constexpr (Cfg::TWMODE == 1) {
+    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, true>{ltw});
+  } else {
+    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, false>{tw});
   }
 }
 

@@ -32,18 +32,14 @@ __device__ __forceinline__ void pc_forward_tile(
   using Cfg = PcCfg<R, LOG2N, BB, TT>;
   constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
   __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
+  __shared__ Cx<R> ltw[Cfg::TWN];
   __shared__ R co[3 * B];
   const int tid = threadIdx.x;
   const int i0 = p * B;
   const int ncols = min(B, nx - i0);
-  if (tid < 3 * B) {
-    const int b = tid / 3, c = tid % 3;
-    R val = R(0);
-    if (b < ncols) val = (R)(c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]));
-    co[tid] = val;
-  }
   // step (a): alpha-weighted tile, columns (2s, 2s+1) packed as one complex
-  // sequence.  All of a thread's loads are issued before any is consumed.
+  // sequence.  All of a thread's loads (tile, then twiddles) are issued
+  // before any is consumed.
   R* ldsr = reinterpret_cast<R*>(lds);
   {
     constexpr int LPT = (N * B + T - 1) / T;
@@ -54,6 +50,14 @@ __device__ __forceinline__ void pc_forward_tile(
       const int k = e / B, b = e % B;
       xv[q] = ((N * B) % T == 0 || e < N * B) && b < ncols ? v[(size_t)k * nx + i0 + b] : 0.0;
     }
+    TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
+    if constexpr (Cfg::TWL) tws.fetch(tw);
+    if (tid < 3 * B) {
+      const int b = tid / 3, c = tid % 3;
+      R val = R(0);
+      if (b < ncols) val = (R)(c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]));
+      co[tid] = val;
+    }
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int e = tid + q * T;
@@ -62,9 +66,10 @@ __device__ __forceinline__ void pc_forward_tile(
         ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] = (R)(xv[q] * (wfw[k] * sc));
       }
     }
+    if constexpr (Cfg::TWL) tws.store(ltw);
   }
   __syncthreads();
-  fft_run<R, LOG2N, NSEQ, T, false, Cfg::MAXLOG, 0>(lds, tw);
+  fft_tile<Cfg, R, LOG2N, false>(lds, ltw, tw);
 
   // step (b), tile-local part
   const bool has_sep = p < P - 1;
@@ -174,16 +179,11 @@ __device__ __forceinline__ void pc_inverse_tile(
   using Cfg = PcCfg<R, LOG2N, BB, TT>;
   constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
   __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
+  __shared__ Cx<R> ltw[Cfg::TWN];
   __shared__ R co[3 * B];
   const int tid = threadIdx.x;
   const int i0 = p * B;
   const int ncols = min(B, nx - i0);
-  if (tid < 3 * B) {
-    const int b = tid / 3, c = tid % 3;
-    R val = R(0);
-    if (b < ncols) val = (R)(c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]));
-    co[tid] = val;
-  }
   const Cx<R>* img = spec + (size_t)p * NSEQ * N;
   {
     constexpr int SPT = (NSEQ * N + T - 1) / T;
@@ -193,11 +193,20 @@ __device__ __forceinline__ void pc_inverse_tile(
       const int e = tid + q * T;
       if ((NSEQ * N) % T == 0 || e < NSEQ * N) iv[q] = img[e];
     }
+    TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
+    if constexpr (Cfg::TWL) tws.fetch(tw);
+    if (tid < 3 * B) {
+      const int b = tid / 3, c = tid % 3;
+      R val = R(0);
+      if (b < ncols) val = (R)(c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]));
+      co[tid] = val;
+    }
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int e = tid + q * T;
       if ((NSEQ * N) % T == 0 || e < NSEQ * N) lds[lidx<N>(e / N, e % N)] = iv[q];
     }
+    if constexpr (Cfg::TWL) tws.store(ltw);
   }
   __syncthreads();
   const bool has_sep = p < P - 1;
@@ -258,7 +267,7 @@ __device__ __forceinline__ void pc_inverse_tile(
     }
   }
   __syncthreads();
-  fft_run<R, LOG2N, NSEQ, T, true, Cfg::MAXLOG, 0>(lds, tw);
+  fft_tile<Cfg, R, LOG2N, true>(lds, ltw, tw);
   const R* ldsr = reinterpret_cast<const R*>(lds);
   {
     constexpr int LPT = (N * B + T - 1) / T;
