@@ -160,11 +160,12 @@ def form_warm_start(B, W, torch, n_train, n_held, epochs, reps):
     dev = torch.device("cuda:0")
     chunk = 128
     t0 = time.perf_counter()
-    X, Y, worst = WS.generate(W.config4_params(n_train, seed=4), chunk=chunk)
+    X, Y, worst = WS.generate(W.config4_params(n_train, seed=4), chunk=chunk,
+                              log=log if n_train > 4096 else None)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    net, hist = WS.train(X, Y, epochs=epochs, batch=128, lr=2e-3, seed=0)
+    net, hist = WS.train(X, Y, epochs=epochs, batch=128, lr=2e-3, seed=0, log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del X, Y
@@ -285,11 +286,11 @@ def main():
     ap.add_argument("--alpha", type=float, default=0.01)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batch and warm-start forms")
-    ap.add_argument("--ws-train", type=int, default=2048,
+    ap.add_argument("--ws-train", type=int, default=4096,
                     help="training instances of the warm-start network (full recipe: 20000)")
     ap.add_argument("--ws-heldout", type=int, default=256,
                     help="held-out instances of the warm-start comparison (full recipe: 1024)")
-    ap.add_argument("--ws-epochs", type=int, default=150)
+    ap.add_argument("--ws-epochs", type=int, default=120)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 256 MiB device copies (hardware-counter calibration)")
     args = ap.parse_args()

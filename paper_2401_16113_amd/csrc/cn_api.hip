@@ -725,7 +725,11 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
   while (true) {
     const int m_eff = std::min(opts->m, opts->max_iters - done_iters);
     int known = 0;  // iterations of this cycle whose summary the host has read
+    // speculative cycle end queued behind the iteration the host waits for
+    bool spec = false, spec_taken = false;
+    int spec_fin = 0, spec_res = 0;
     for (int j = 0; j < m_eff; ++j) {
+      spec = false;
       seqs[j] = c.batched ? 0 : ++(*c.seqc);
       if (c.graphs != nullptr) {
         CN_TRY(launch_iteration_graph(c, j, m_eff, rtol));
@@ -756,20 +760,38 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
         }
         const double rate = prev > 0.0 ? ests[j - 1] / prev : 1.0;
         if (j + 1 < m_eff && ests[j - 1] * rate < 50.0 * rtol) {
+          // one instance: queue the cycle end behind iteration j before
+          // waiting (its kernels return at entry unless the cycle stopped),
+          // so a converged solve goes on without a host round trip
+          if (!c.batched) {
+            spec_fin = ++(*c.seqc);
+            HIP_TRY(launch_cycle_end(c.L, c.stv, x, x_zero ? 1 : 0, 3, spec_fin, c.s, true));
+            spec_res = ++(*c.seqc);
+            HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, spec_res, c.s, 0, true));
+            spec = true;
+          }
           CN_TRY(wait_slot(c.s, slots + (j & 1), seqs[j], &it));
           ests[j] = it.est;
           known = j + 1;
-          if (it.done) break;
+          if (it.done) {
+            spec_taken = spec;
+            break;
+          }
         }
       }
     }
     // y from the triangular factors (cycle summaries -> slot 3), x += Z y,
-    // then the true residuals (-> slot 2)
-    const int seq_fin = c.batched ? 0 : ++(*c.seqc);
-    HIP_TRY(launch_cycle_end(c.L, c.stv, x, x_zero ? 1 : 0, 3, seq_fin, c.s));
+    // then the true residuals (-> slot 2), unless already queued
+    int seq_fin = spec_fin;
+    if (spec_taken) {
+      seq_res = spec_res;
+    } else {
+      seq_fin = c.batched ? 0 : ++(*c.seqc);
+      HIP_TRY(launch_cycle_end(c.L, c.stv, x, x_zero ? 1 : 0, 3, seq_fin, c.s));
+      seq_res = c.batched ? 0 : ++(*c.seqc);
+      HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, seq_res, c.s, 0));
+    }
     x_zero = false;
-    seq_res = c.batched ? 0 : ++(*c.seqc);
-    HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, seq_res, c.s, 0));
     if (c.batched) {
       int sq = 0;
       CN_TRY(batch_publish(c, 2, &sq));

@@ -131,9 +131,11 @@ hipError_t launch_matvec_plain(const Launch& L, const Items& mv, const double* x
 // start: 0 restart of a solve, 1 first residual of a solve, 2 first residual
 // with fallback (an instance whose ||r|| >= ||b|| restarts from x = 0: its
 // V_0 becomes b and its x is cleared, on the device)
+// guard: speculative (queued before the host knows the cycle stopped): every
+// kernel returns at entry for an instance whose cycle is still running
 hipError_t launch_residual(const Launch& L, const Items& mv, const Items& stv,
                            const double* b_base, double* x_base, int x_zero, double rtol,
-                           int slot, int seq, hipStream_t s, int start = 0);
+                           int slot, int seq, hipStream_t s, int start = 0, bool guard = false);
 // one inner iteration's Krylov part: w = M z_j with the first dots, the two
 // CGS2 passes and the Givens update (`finish` = false leaves out the
 // finishing kernels, for timing the streaming kernels alone)
@@ -143,7 +145,7 @@ hipError_t launch_arnoldi(const Launch& L, const Items& mv, const Items& stv, in
                           bool finish = true);
 // end of a cycle: triangular solve, x += Z y
 hipError_t launch_cycle_end(const Launch& L, const Items& stv, double* x_base, int x_zero,
-                            int slot, int seq, hipStream_t s);
+                            int slot, int seq, hipStream_t s, bool guard = false);
 // publish the number of instances still iterating (batch polling)
 hipError_t launch_batch_summary(const Launch& L, int* counter, GSummary* host, hipStream_t s);
 hipError_t launch_rhs(const double* lo, const double* di, const double* up, const double* dw,

@@ -95,7 +95,8 @@ __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int 
 // ---------------------------------------------------------------------------
 // matvec: y = M x (MODE 0, one instance: x = xo, y = yo),
 //         r = b - M x into V_0 with ||r||^2, ||b||^2 (MODE 1: x = xo + off,
-//         unread when x_zero; b = bo + off),
+//         unread when bit 0 of x_zero is set; bit 1: only for instances whose
+//         cycle has stopped; b = bo + off),
 //         w = M z_j with dots against V_0..V_j (MODE 2, first CGS pass)
 // Each thread marches down the time levels of one spatial column.
 // ---------------------------------------------------------------------------
@@ -110,6 +111,8 @@ __global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
   const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
   if (MODE == 2 && d.st->sum.done) return;
+  // MODE 1, bit 1 of x_zero: speculative residual, only for a stopped cycle
+  if (MODE == 1 && (x_zero & 2) && !d.st->sum.done) return;
   const TX* __restrict__ x;
   const double* __restrict__ b = nullptr;
   double* __restrict__ y;
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
     x = xo;
     y = yo;
   } else if (MODE == 1) {
-    x = x_zero ? nullptr : xo + d.off;
+    x = (x_zero & 1) ? nullptr : xo + d.off;
     b = bo + d.off;
     y = d.V;
   } else {
@@ -260,6 +263,8 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
   const InstDesc& d = D[blockIdx.x];
   GState* st = d.st;
   GSummary* host = d.host != nullptr ? d.host + slot : nullptr;
+  // FIN 1 with stop_iter != 0: speculative cycle start, only after a stopped cycle
+  if (FIN == 1 && stop_iter != 0 && !st->sum.done) return;
   if (FIN != 1 && st->sum.done) {
     // the cycle already stopped: still tell a polling host so
     if (FIN == 4 && threadIdx.x == 0) publish(host, st->sum, seq);
@@ -353,11 +358,13 @@ __global__ __launch_bounds__(KT) void k_fallback(const InstDesc* __restrict__ D,
 
 // End of a cycle, one thread per instance: solve R y = g (k x k upper
 // triangular) and publish the cycle's summary (k, estimate) to host slot.
-__global__ void k_cycle_finish(const InstDesc* __restrict__ D, int ninst, int slot, int seq) {
+__global__ void k_cycle_finish(const InstDesc* __restrict__ D, int ninst, int slot, int seq,
+                               int guard) {
   const int inst = blockIdx.x * blockDim.x + threadIdx.x;
   if (inst >= ninst) return;
   const InstDesc& d = D[inst];
   GState* st = d.st;
+  if (guard && !st->sum.done) return;  // speculative: the cycle has not stopped
   publish(d.host != nullptr ? d.host + slot : nullptr, st->sum, seq);
   const int k = st->sum.k;
   for (int q = k - 1; q >= 0; --q) {
@@ -376,15 +383,16 @@ __global__ __launch_bounds__(KT) void k_update(const InstDesc* __restrict__ D,
   const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
   const GState* st = d.st;
+  if ((x_zero & 2) && !st->sum.done) return;  // speculative: the cycle has not stopped
   const int k = st->sum.k;
-  if (k == 0 && !x_zero) return;
+  if (k == 0 && !(x_zero & 1)) return;
   const double* y = st->y;
   const TZ* __restrict__ Z = (const TZ*)d.Z;
   double* __restrict__ x = xb + d.off;
   const long long zstride = d.vstride;
   const long long stride = (long long)d.st_grid * KT;
   for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.n; e += stride) {
-    double s = x_zero ? 0.0 : x[e];
+    double s = (x_zero & 1) ? 0.0 : x[e];
     int q = 0;
     for (; q + 4 <= k; q += 4) {
       s += y[q] * (double)Z[(size_t)q * zstride + e] +
@@ -487,11 +495,11 @@ hipError_t launch_matvec_plain(const Launch& L, const Items& mv, const double* x
 
 hipError_t launch_residual(const Launch& L, const Items& mv, const Items& stv,
                            const double* b_base, double* x_base, int x_zero, double rtol,
-                           int slot, int seq, hipStream_t s, int start) {
+                           int slot, int seq, hipStream_t s, int start, bool guard) {
   hipLaunchKernelGGL((k_matvec<double, 1, 2>), dim3(mv.n), dim3(KT), 0, s, L.D, mv.it, 0,
-                     (const double*)x_base, b_base, nullptr, x_zero);
-  hipLaunchKernelGGL((k_finish<1>), dim3(L.ninst), dim3(FT), 0, s, L.D, start, 0, rtol, slot,
-                     seq);
+                     (const double*)x_base, b_base, nullptr, (x_zero ? 1 : 0) | (guard ? 2 : 0));
+  hipLaunchKernelGGL((k_finish<1>), dim3(L.ninst), dim3(FT), 0, s, L.D, start, guard ? 1 : 0,
+                     rtol, slot, seq);
   if (start == 2)
     hipLaunchKernelGGL(k_fallback, dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, b_base, x_base);
   return hipGetLastError();
@@ -537,9 +545,10 @@ hipError_t launch_arnoldi(const Launch& L, const Items& mv, const Items& stv, in
 }
 
 hipError_t launch_cycle_end(const Launch& L, const Items& stv, double* x_base, int x_zero,
-                            int slot, int seq, hipStream_t s) {
+                            int slot, int seq, hipStream_t s, bool guard) {
   hipLaunchKernelGGL(k_cycle_finish, dim3((L.ninst + 63) / 64), dim3(64), 0, s, L.D, L.ninst,
-                     slot, seq);
+                     slot, seq, guard ? 1 : 0);
+  x_zero = (x_zero ? 1 : 0) | (guard ? 2 : 0);
   if (L.zf)
     hipLaunchKernelGGL((k_update<float>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, x_base,
                        x_zero);
