@@ -20,6 +20,8 @@ against the 8 TB/s HBM peak), the CPU oracle timed on the host, and the
 production forms on their own workloads ("forms"):
   batch_uneven -- 512 uneven constant-volatility puts (N_x in 255..2047,
                   N_t in 64..512) in one batched solve, float32 preconditioner;
+  production   -- the 65535 x 4096 local-volatility put (2.7e8 unknowns),
+                  float32 preconditioner, GMRES(20), with per-kernel rates;
   warm_start   -- held-out local-volatility puts, N_x = 2047, N_t = 512:
                   plain (float64 preconditioner, one instance at a time, zero
                   start) against batched + float32 preconditioner, from zero
@@ -250,6 +252,37 @@ def form_warm_start(B, W, torch, n_train, n_held, epochs, reps):
     return out
 
 
+def form_production(B, W, torch, reps):
+    """The production shape (2.7e8 unknowns) with the float32 preconditioner:
+    whole-solve throughput and the per-kernel rates of inner iteration 1."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    inst = W.config5()
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    s = B.Solver(t(inst.a_lo), t(inst.a_di), t(inst.a_up), inst.nt, inst.T, inst.alpha,
+                 m_max=20, pc_prec="fp32")
+    b = torch.empty(inst.n, dtype=torch.float64, device=dev)
+    s.rhs(t(inst.u0), t(inst.f.reshape(-1)), b)
+    del inst.f
+    x = torch.empty_like(b)
+    s.solve(b, x, m=20, rtol=RTOL)
+    sec, r = timed(lambda: s.solve(b, x, m=20, rtol=RTOL), reps, torch)
+    if r.status != B.CN_OK:
+        raise RuntimeError(f"production shape did not converge: {r}")
+    prof = s.profile_step(j=1, reps=5)
+    pc_ms = sum(prof[k]["ms"] for k in ("pc_forward", "pc_reduced", "pc_inverse"))
+    pc_bytes = sum(prof[k]["bytes"] for k in ("pc_forward", "pc_reduced", "pc_inverse"))
+    out = {"nx": inst.nx, "nt": inst.nt, "unknowns": inst.n, "pc_variant": s.query(),
+           "ms_per_solve": sec * 1e3, "unknowns_per_s": inst.n / sec, "iters": r.iters,
+           "relres": r.relres_true,
+           "kernels_step1": {k: {"us": v["ms"] * 1e3, "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+                             for k, v in prof.items()},
+           "pc_apply_GBps": pc_bytes / (pc_ms * 1e-3) / 1e9,
+           "pc_apply_frac_of_peak": pc_bytes / (pc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    s.close()
+    return out
+
+
 def cpu_baseline(inst, x_gpu):
     import numpy as np
     from oracle import cn_oracle as O
@@ -355,6 +388,11 @@ def main():
             f"{ws['batched_fp32_warm']['unknowns_per_s']:.3e} unknowns/s; iterations "
             f"{ws['plain_fp64']['mean_iters']:.2f} / {ws['batched_fp32']['mean_iters']:.2f} / "
             f"{ws['batched_fp32_warm']['mean_iters']:.2f}")
+        log("[bench] form: production shape 65535x4096")
+        forms["production"] = form_production(B, W, torch, reps=3)
+        pr = forms["production"]
+        log(f"[bench] production: {pr['ms_per_solve']:.2f} ms, {pr['unknowns_per_s']:.3e} unknowns/s, "
+            f"{pr['iters']} iters, preconditioner apply {pr['pc_apply_GBps']:.0f} GB/s")
         out["forms"] = forms
     if args.calibrate_copy:
         log("[bench] calibration: 5 device copies of 256 MiB")

@@ -179,15 +179,21 @@ static hipError_t build_launch(cn_aao* h) {
   // one instance: kernels derive the work items from the block index, which
   // saves a dependent load at the start of every workgroup
   h->wl.I_pc.it = h->wl.I_k2.it = h->wl.I_mv.it = h->wl.I_st.it = nullptr;
-  h->k2_thr = k2_chunk_class(h->pl.NS);
+  h->k2_thr = k2_chunk_class(h->pl.NS, h->prec);
   // CN_K2_CLASS=32W+CH forces an interface-solve variant (tests); a
   // register variant too small for the chunk falls back to the default
   if (const char* f = getenv("CN_K2_CLASS")) {
-    const int c = atoi(f), w = c / 32, ch = c % 32;
-    const int chunk = (h->pl.NS + 64 * w - 1) / (64 * std::max(w, 1));
-    const bool known = (w == 1 || w == 4 || w == 16) &&
-                       (ch == 0 ? w == 16 : (ch == 1 || ch == 2 || ch == 4 || (ch == 8 && w < 16)));
-    if (known && (ch == 0 || chunk <= ch)) h->k2_thr = c;
+    const int c = atoi(f);
+    if (c >= 4096) {  // strided layout: blocks of 1024 separators per lane set
+      const int ch = c - 4096, blocks = (h->pl.NS + 1023) / 1024;
+      if ((ch == 1 || ch == 2 || ch == 4 || ch == 8 || ch == 16) && blocks <= ch) h->k2_thr = c;
+    } else {
+      const int w = c / 32, ch = c % 32;
+      const int chunk = (h->pl.NS + 64 * w - 1) / (64 * std::max(w, 1));
+      const bool known = (w == 1 || w == 4 || w == 8 || w == 16) &&
+                         (ch == 0 ? w == 16 : (ch == 1 || ch == 2 || ch == 4 || (ch == 8 && w < 16)));
+      if (known && (ch == 0 || chunk <= ch)) h->k2_thr = c;
+    }
   }
   return e;
 }
@@ -488,9 +494,7 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   TRY(dalloc(h, &pl.spec, spec_elems * rsz));
   TRY(dalloc(h, &pl.iface, (size_t)pl.F * ptile_max * 3 * 2 * rsz));
   TRY(dalloc(h, &pl.sep, (size_t)pl.F * nsep_max * 2 * rsz));
-  TRY(dalloc(h, &pl.red_a, (size_t)pl.F * nsep_max * sizeof(Cx<double>)));
-  TRY(dalloc(h, &pl.red_ap, (size_t)pl.F * nsep_max * sizeof(Cx<double>)));
-  TRY(dalloc(h, &pl.red_inv, (size_t)pl.F * nsep_max * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.red, (size_t)pl.F * nsep_max * 3 * 2 * rsz));
   TRY(dalloc(h, &pl.red_tmp, (size_t)pl.F * nsep_max * sizeof(Cx<double>)));
   {
     Cx<double>* spk = nullptr;
@@ -993,7 +997,7 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   const double nimg = (double)pl.P * pl.B * pl.nt;
   const double nsep = (double)pl.F * pl.NS;
   bytes[0] = n * 8 + nimg * rsz + (double)pl.F * pl.P * 6 * rsz;
-  bytes[1] = nsep * (6 * rsz + 3 * 16 + 2 * 16 + 2 * rsz);
+  bytes[1] = nsep * (6 * rsz + 6 * rsz + 2 * rsz);  // interface values, factor records, S
   bytes[2] = nimg * rsz + (double)pl.F * pl.P * 4 * rsz + n * zes;
   bytes[3] = n * zes + n * 8 + (double)(j + 1) * n * 8;
   bytes[4] = (double)(j + 2) * n * 8;
@@ -1099,7 +1103,7 @@ cn_status cn_batch_create(const cn_problem* probs, int32_t count, cn_batch** out
     b->pc_lists.push_back(dptr);
     b->groups.push_back(PcGroup{b->prec, kv.first, group_cand[kv.first], it});
   }
-  b->k2_thr = k2_chunk_class(max_ns);
+  b->k2_thr = k2_chunk_class(max_ns, b->prec);
   if (e == hipSuccess) e = hipMalloc((void**)&b->dcounter, sizeof(int));
   if (e == hipSuccess) e = hipMemset(b->dcounter, 0, sizeof(int));
   if (e == hipSuccess)

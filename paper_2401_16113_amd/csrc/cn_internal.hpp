@@ -27,9 +27,7 @@ struct PcPlan {
   Cx<float>* tw_f = nullptr;
   Cx<double>* mu = nullptr;                             // lambda1/lambda2, [F]
   Cx<double>* il2 = nullptr;                            // 1/lambda2, [F]
-  Cx<double>* red_a = nullptr;                          // interface system factors [F][NS]
-  Cx<double>* red_ap = nullptr;
-  Cx<double>* red_inv = nullptr;
+  void* red = nullptr;  // interface system factors [F][NS] x {a, ap, inv}, precision of the PC
   Cx<double>* red_tmp = nullptr;
   void* spec = nullptr;                                 // tile images
   void* iface = nullptr;                                // [F][P][3]
@@ -110,8 +108,8 @@ __device__ __forceinline__ int2 work_item(const int2* __restrict__ items, int i)
 hipError_t pc_setup(PcPlan& pl, Cx<double>* spk, int* err_dev, hipStream_t s);
 hipError_t pc_forward(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
                       const double* v, hipStream_t s);
-// chunk_class: k2_chunk_class(largest NS of the launch)
-int k2_chunk_class(int ns);
+// chunk_class: k2_chunk_class(largest NS of the launch, precision)
+int k2_chunk_class(int ns, int prec);
 hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int chunk_class, int j,
                       int standalone, hipStream_t s);
 hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,

@@ -38,6 +38,7 @@ namespace cn {
 // scratch array.  W = 1 packs four lines into a 256-thread workgroup.
 // ---------------------------------------------------------------------------
 constexpr int K2_THREADS = 256;
+constexpr int K2_STRIDED = 4096;  // variant code offset of the strided layout
 
 __device__ __forceinline__ Cx<double> shfl_up_c(Cx<double> v, int off) {
   return Cx<double>{__shfl_up(v.x, off, 64), __shfl_up(v.y, off, 64)};
@@ -88,10 +89,21 @@ __device__ __forceinline__ Cx<double> line_carry(Cx<double> A, Cx<double> Bv, in
   }
 }
 
+template <typename R>
+__device__ __forceinline__ Cx<double> wide(Cx<R> v) {
+  return Cx<double>{(double)v.x, (double)v.y};
+}
+
+// Factor record of separator s: {a_s, ap_s, inv_s} in the preconditioner's
+// precision (the substitutions run in float64).
+template <typename R>
+struct RedRec {
+  Cx<R> a, ap, inv;
+};
+
 template <typename R, int W, int CH>
 __device__ __forceinline__ void reduced_line(
-    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const Cx<double>* __restrict__ ra,
-    const Cx<double>* __restrict__ rap, const Cx<double>* __restrict__ rinv,
+    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const RedRec<R>* __restrict__ rec,
     Cx<double>* __restrict__ rtmp, const double* __restrict__ lo,
     const double* __restrict__ up, int NS, int B, int t, Cx<double>* sA, Cx<double>* sB) {
   const int lane = t & 63, wave = t >> 6;
@@ -106,44 +118,51 @@ __device__ __forceinline__ void reduced_line(
   };
   const Cx<double> one{1.0, 0.0}, zero{0.0, 0.0};
   if constexpr (CH > 0) {
-    // every operand of the lane's chunk is loaded up front (independent
-    // loads, one memory latency); padding entries are identity maps
-    Cx<double> a[CH], rh[CH], ap[CH], iv[CH];
+    // the forward operands of the lane's chunk are loaded up front
+    // (independent loads, one memory latency), the backward ones once the
+    // forward sweep is done (fewer live registers); padding entries are
+    // identity maps
+    Cx<R> a[CH];
+    Cx<double> rh[CH];
+    const Cx<R> onef{R(1), R(0)}, zerof{R(0), R(0)};
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int s = s0 + q;
-      a[q] = s < s1 ? ra[s] : one;
+      a[q] = s < s1 ? rec[s].a : onef;
       rh[q] = s < s1 ? rho(s) : zero;
     }
     Cx<double> A = one, Bv = zero;
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
-      Bv = a[q] * Bv + rh[q];
-      A = a[q] * A;
-    }
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int s = s0 + q;
-      ap[q] = s < s1 ? rap[s] : one;
-      iv[q] = s < s1 ? rinv[s] : zero;
+      const Cx<double> aw = wide(a[q]);
+      Bv = aw * Bv + rh[q];
+      A = aw * A;
     }
     Cx<double> r = line_carry<true, W>(A, Bv, lane, wave, sA, sB);
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
-      r = a[q] * r + rh[q];
+      r = wide(a[q]) * r + rh[q];
       rh[q] = r;  // rho'_s
+    }
+    Cx<R> ap[CH], iv[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int s = s0 + q;
+      ap[q] = s < s1 ? rec[s].ap : onef;
+      iv[q] = s < s1 ? rec[s].inv : zerof;
     }
     A = one;
     Bv = zero;
 #pragma unroll
     for (int q = CH - 1; q >= 0; --q) {
-      Bv = ap[q] * Bv + iv[q] * rh[q];
-      A = ap[q] * A;
+      const Cx<double> apw = wide(ap[q]);
+      Bv = apw * Bv + wide(iv[q]) * rh[q];
+      A = apw * A;
     }
     Cx<double> S = line_carry<false, W>(A, Bv, lane, wave, sA, sB);
 #pragma unroll
     for (int q = CH - 1; q >= 0; --q) {
-      S = ap[q] * S + iv[q] * rh[q];
+      S = wide(ap[q]) * S + wide(iv[q]) * rh[q];
       const int s = s0 + q;
       if (s < s1) sep[s] = Cx<R>{(R)S.x, (R)S.y};
     }
@@ -151,31 +170,190 @@ __device__ __forceinline__ void reduced_line(
     Cx<double> A = one, Bv = zero;
 #pragma unroll 4
     for (int s = s0; s < s1; ++s) {
-      const Cx<double> a = ra[s];
+      const Cx<double> a = wide(rec[s].a);
       Bv = a * Bv + rho(s);
       A = a * A;
     }
     Cx<double> r = line_carry<true, W>(A, Bv, lane, wave, sA, sB);
 #pragma unroll 4
     for (int s = s0; s < s1; ++s) {
-      r = ra[s] * r + rho(s);
+      r = wide(rec[s].a) * r + rho(s);
       rtmp[s] = r;
     }
     A = one;
     Bv = zero;
 #pragma unroll 4
     for (int s = s1 - 1; s >= s0; --s) {
-      const Cx<double> a = rap[s];
-      Bv = a * Bv + rinv[s] * rtmp[s];
-      A = a * A;
+      const RedRec<R> q = rec[s];
+      const Cx<double> ap = wide(q.ap);
+      Bv = ap * Bv + wide(q.inv) * rtmp[s];
+      A = ap * A;
     }
     Cx<double> S = line_carry<false, W>(A, Bv, lane, wave, sA, sB);
 #pragma unroll 4
     for (int s = s1 - 1; s >= s0; --s) {
-      S = rap[s] * S + rinv[s] * rtmp[s];
+      const RedRec<R> q = rec[s];
+      S = wide(q.ap) * S + wide(q.inv) * rtmp[s];
       sep[s] = Cx<R>{(R)S.x, (R)S.y};
     }
   }
+}
+
+// Strided layout for very wide grids: lane t of the line's L = 64 W lanes
+// owns separators s = q L + t (q < CH), so every load and store is
+// coalesced.  Each block q of L consecutive separators is scanned across
+// the workgroup (shuffles within a wavefront, the W wavefront aggregates
+// through LDS, double-buffered so one barrier per block suffices), and the
+// value carried between blocks is the block's total map applied to the
+// previous carry.
+template <bool UP, int W>
+__device__ __forceinline__ void block_affine(Cx<double>& A, Cx<double>& Bv, Cx<double>& At,
+                                             Cx<double>& Bt, int lane, int wave, Cx<double>* sA,
+                                             Cx<double>* sB) {
+  const Cx<double> one{1.0, 0.0}, zero{0.0, 0.0};
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const Cx<double> pa = UP ? shfl_up_c(A, off) : shfl_down_c(A, off);
+    const Cx<double> pb = UP ? shfl_up_c(Bv, off) : shfl_down_c(Bv, off);
+    const bool has = UP ? lane >= off : lane + off < 64;
+    if (has) {
+      Bv = A * pb + Bv;
+      A = A * pa;
+    }
+  }
+  // sA/sB[0..W): wavefront aggregates; [W..2W): their exclusive prefixes in
+  // scan order; [2W]: the block total
+  if (UP ? lane == 63 : lane == 0) {
+    sA[wave] = A;
+    sB[wave] = Bv;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // one wavefront scans the W aggregates (lane u holds aggregate u, in scan
+    // order: reversed for the backward sweep)
+    const int u = UP ? lane : W - 1 - lane;
+    Cx<double> wa = lane < W ? sA[u] : one, wb = lane < W ? sB[u] : zero;
+#pragma unroll
+    for (int off = 1; off < W; off <<= 1) {
+      const Cx<double> pa = shfl_up_c(wa, off), pb = shfl_up_c(wb, off);
+      if (lane >= off) {
+        wb = wa * pb + wb;
+        wa = wa * pa;
+      }
+    }
+    Cx<double> ea = shfl_up_c(wa, 1), eb = shfl_up_c(wb, 1);
+    if (lane == 0) {
+      ea = one;
+      eb = zero;
+    }
+    if (lane < W) {
+      sA[W + u] = ea;
+      sB[W + u] = eb;
+    }
+    if (lane == W - 1) {
+      sA[2 * W] = wa;
+      sB[2 * W] = wb;
+    }
+  }
+  __syncthreads();
+  const Cx<double> pA = sA[W + wave], pB = sB[W + wave];
+  At = sA[2 * W];
+  Bt = sB[2 * W];
+  Bv = A * pB + Bv;
+  A = A * pA;
+}
+
+template <typename R, int W, int CH>
+__device__ __forceinline__ void reduced_line_strided(
+    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const RedRec<R>* __restrict__ rec,
+    Cx<double>* __restrict__ rtmp, const double* __restrict__ lo,
+    const double* __restrict__ up, int NS, int B, int t, Cx<double> (*sA)[2 * W + 1],
+    Cx<double> (*sB)[2 * W + 1]) {
+  // rho' of up to four blocks stays in registers; beyond, it goes through
+  // the (coalesced) scratch array
+  constexpr bool KEEP = CH <= 4;
+  constexpr int L = 64 * W;
+  const int lane = t & 63, wave = t >> 6;
+  auto rho = [&](int s) -> Cx<double> {
+    const int is = (s + 1) * B - 1;
+    const Cx<R> d = f[(size_t)s * 3 + 0], yl = f[(size_t)s * 3 + 1], yf = f[(size_t)(s + 1) * 3 + 2];
+    const double l = lo[is], u = up[is];
+    return Cx<double>{(double)d.x + l * (double)yl.x + u * (double)yf.x,
+                      (double)d.y + l * (double)yl.y + u * (double)yf.y};
+  };
+  const Cx<double> zero{0.0, 0.0};
+  const Cx<R> onef{R(1), R(0)}, zerof{R(0), R(0)};
+  // operands of block q + 1 are loaded while block q is scanned
+  auto fwd_ops = [&](int q, Cx<R>& a, Cx<double>& r) {
+    const int s = q * L + t;
+    a = s < NS ? rec[s].a : onef;
+    r = s < NS ? rho(s) : zero;
+  };
+  auto bwd_ops = [&](int q, Cx<R>& ap, Cx<R>& iv) {
+    const int s = q * L + t;
+    ap = s < NS ? rec[s].ap : onef;
+    iv = s < NS ? rec[s].inv : zerof;
+  };
+  Cx<double> rh[KEEP ? CH : 1];
+  Cx<R> an;
+  Cx<double> rn;
+  fwd_ops(0, an, rn);
+  int buf = 0;
+  Cx<double> carry = zero;
+#pragma unroll
+  for (int q = 0; q < CH; ++q) {
+    Cx<double> A = wide(an), Bv = rn, At, Bt;
+    if (q + 1 < CH) fwd_ops(q + 1, an, rn);
+    block_affine<true, W>(A, Bv, At, Bt, lane, wave, sA[buf], sB[buf]);
+    buf ^= 1;
+    const Cx<double> r = A * carry + Bv;  // rho'_s
+    if constexpr (KEEP) {
+      rh[q] = r;
+    } else {
+      const int s = q * L + t;
+      if (s < NS) rtmp[s] = r;
+    }
+    carry = At * carry + Bt;
+  }
+  Cx<R> apn, ivn;
+  bwd_ops(CH - 1, apn, ivn);
+  carry = zero;
+#pragma unroll
+  for (int q = CH - 1; q >= 0; --q) {
+    Cx<double> rq;
+    if constexpr (KEEP) {
+      rq = rh[q];
+    } else {
+      const int s = q * L + t;
+      rq = s < NS ? rtmp[s] : zero;
+    }
+    Cx<double> A = wide(apn), Bv = wide(ivn) * rq, At, Bt;
+    if (q > 0) bwd_ops(q - 1, apn, ivn);
+    block_affine<false, W>(A, Bv, At, Bt, lane, wave, sA[buf], sB[buf]);
+    buf ^= 1;
+    const Cx<double> S = A * carry + Bv;
+    carry = At * carry + Bt;
+    const int s = q * L + t;
+    if (s < NS) sep[s] = Cx<R>{(R)S.x, (R)S.y};
+  }
+}
+
+template <typename R, int W, int CH>
+__global__ __launch_bounds__(64 * W) void k_pc_reduced_strided(
+    const InstDesc* __restrict__ D, const int2* __restrict__ items, int nitems, int standalone) {
+  __shared__ Cx<double> sA[2][2 * W + 1], sB[2][2 * W + 1];
+  const int item = blockIdx.x;
+  if (item >= nitems) return;
+  const int2 wi = work_item(items, item);
+  const InstDesc& d = D[wi.x];
+  const PcPlan& pl = d.pl;
+  if (!standalone && d.st->sum.done) return;
+  const int j = wi.y;
+  const size_t row = (size_t)j * pl.NS;
+  reduced_line_strided<R, W, CH>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 3,
+                                 (Cx<R>*)pl.sep + row, (const RedRec<R>*)pl.red + row,
+                                 pl.red_tmp + row, pl.lo, pl.up, pl.NS, pl.B, threadIdx.x, sA,
+                                 sB);
 }
 
 template <typename R, int W, int CH>
@@ -193,8 +371,8 @@ __global__ __launch_bounds__(W == 1 ? K2_THREADS : 64 * W) void k_pc_reduced(
   const int j = wi.y;
   const size_t row = (size_t)j * pl.NS;
   reduced_line<R, W, CH>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 3, (Cx<R>*)pl.sep + row,
-                         pl.red_a + row, pl.red_ap + row, pl.red_inv + row, pl.red_tmp + row,
-                         pl.lo, pl.up, pl.NS, pl.B, t, sA, sB);
+                         (const RedRec<R>*)pl.red + row, pl.red_tmp + row, pl.lo, pl.up, pl.NS,
+                         pl.B, t, sA, sB);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,11 +445,11 @@ __device__ inline Cx<double> cdiv(Cx<double> a, Cx<double> b) {
   return Cx<double>{(a.x * b.x + a.y * b.y) * s, (a.y * b.x - a.x * b.y) * s};
 }
 
+template <typename R>
 __global__ void k_setup_reduced(const double* __restrict__ lo, const double* __restrict__ di,
                                 const double* __restrict__ up, const Cx<double>* __restrict__ mu,
                                 const Cx<double>* __restrict__ spk, int P, int NS, int B, int F,
-                                Cx<double>* __restrict__ ra, Cx<double>* __restrict__ rap,
-                                Cx<double>* __restrict__ rinv, int* __restrict__ err) {
+                                RedRec<R>* __restrict__ rec, int* __restrict__ err) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= F) return;
   const Cx<double> m = mu[j];
@@ -298,10 +476,9 @@ __global__ void k_setup_reduced(const double* __restrict__ lo, const double* __r
                        sqrt(Cm.x * Cm.x + Cm.y * Cm.y);
     if (!(mag > 1e-13 * scl) || !isfinite(mag)) bad = true;
     const Cx<double> inv = cdiv(Cx<double>{1.0, 0.0}, beta);
-    ra[row + s] = Cx<double>{-mlt.x, -mlt.y};
-    rinv[row + s] = inv;
     const Cx<double> capi = Cm * inv;
-    rap[row + s] = Cx<double>{-capi.x, -capi.y};
+    rec[row + s] = RedRec<R>{Cx<R>{(R)-mlt.x, (R)-mlt.y}, Cx<R>{(R)-capi.x, (R)-capi.y},
+                             Cx<R>{(R)inv.x, (R)inv.y}};
     beta_prev = beta;
     cm_prev = Cm;
   }
@@ -337,13 +514,20 @@ hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Item
 // Interface-solve variant for separator systems of up to `ns` unknowns:
 // 32 W + CH with W wavefronts per line and CH separators per lane held in
 // registers (CH = 0: streamed), the fewest wavefronts that keep the chunk in
-// registers without spilling (CH <= 8; <= 4 with 1024-thread workgroups).
-int k2_chunk_class(int ns) {
-  for (int w : {1, 4, 16}) {
+// registers without spilling: CH <= 8 (W = 1, 4, 8), CH <= 4 in 1024-thread
+// workgroups (W = 16).
+int k2_chunk_class(int ns, int prec) {
+  (void)prec;
+  for (int w : {1, 4, 8, 16}) {
     const int chunk = (ns + 64 * w - 1) / (64 * w);
-    for (int c = 1; c <= (w == 16 ? 4 : 8); c *= 2)
+    const int cmax = w == 16 ? 4 : 8;
+    for (int c = 1; c <= cmax; c *= 2)
       if (chunk <= c) return 32 * w + c;
   }
+  // strided blocks of 1024 separators (K2_STRIDED + CH), then streamed
+  const int blocks = (ns + 1023) / 1024;
+  for (int c = 4; c <= 16; c *= 2)
+    if (blocks <= c) return K2_STRIDED + c;
   return 32 * 16;
 }
 
@@ -366,6 +550,18 @@ hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int chunk_clas
     K2(1, 1) K2(1, 2) K2(1, 4) K2(1, 8)
     K2(4, 1) K2(4, 2) K2(4, 4) K2(4, 8)
     K2(16, 1) K2(16, 2) K2(16, 4) K2(16, 0)
+    K2(8, 1) K2(8, 2) K2(8, 4) K2(8, 8)
+#define K2S(CH)                                                                                \
+  case K2_STRIDED + CH:                                                                        \
+    if (prec)                                                                                  \
+      hipLaunchKernelGGL((k_pc_reduced_strided<float, 16, CH>), dim3(it.n), dim3(1024), 0, s, \
+                         L.D, it.it, it.n, standalone);                                        \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_pc_reduced_strided<double, 16, CH>), dim3(it.n), dim3(1024), 0,   \
+                         s, L.D, it.it, it.n, standalone);                                     \
+    break;
+    K2S(1) K2S(2) K2S(4) K2S(8) K2S(16)
+#undef K2S
 #undef K2
     default:
       return hipErrorInvalidValue;
@@ -390,8 +586,12 @@ hipError_t pc_setup(PcPlan& pl, Cx<double>* spk, int* err, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && pl.NS > 0) {
     const int t2 = 64, b2 = (pl.F + t2 - 1) / t2;
-    hipLaunchKernelGGL(k_setup_reduced, dim3(b2), dim3(t2), 0, s, pl.lo, pl.di, pl.up, pl.mu,
-                       spk, pl.P, pl.NS, pl.B, pl.F, pl.red_a, pl.red_ap, pl.red_inv, err);
+    if (pl.prec)
+      hipLaunchKernelGGL(k_setup_reduced<float>, dim3(b2), dim3(t2), 0, s, pl.lo, pl.di, pl.up,
+                         pl.mu, spk, pl.P, pl.NS, pl.B, pl.F, (RedRec<float>*)pl.red, err);
+    else
+      hipLaunchKernelGGL(k_setup_reduced<double>, dim3(b2), dim3(t2), 0, s, pl.lo, pl.di, pl.up,
+                         pl.mu, spk, pl.P, pl.NS, pl.B, pl.F, (RedRec<double>*)pl.red, err);
     e = hipGetLastError();
   }
   return e;

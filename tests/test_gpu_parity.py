@@ -400,14 +400,16 @@ def test_interface_solve_variants(nx, nt, tile, prec, monkeypatch):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_every_interface_solve_variant_matches_oracle(prec, monkeypatch):
-    """Each layout of the interface solve (1, 4 or 16 wavefronts per line;
-    2..8 separators per lane in registers, or streamed) forced on the same
+    """Each layout of the interface solve (1, 4, 8 or 16 wavefronts per line;
+    2..8 separators per lane in registers, or streamed; the strided layout
+    with block scans, rho' in registers or in scratch) forced on the same
     255-separator system, every element against the oracle."""
     monkeypatch.setenv("CN_PC_TILE", "16,256")
     inst = localvol(4095, 64)
     v = W.random_vector(inst.n, 23)
     ref = O.pc_apply(*oracle_args(inst), inst.alpha, v)
-    for cls in (36, 40, 129, 130, 132, 136, 513, 514, 516, 512):
+    for cls in (36, 40, 129, 130, 132, 136, 257, 258, 260, 264, 513, 514, 516, 512,
+                4097, 4098, 4100, 4104, 4112):
         monkeypatch.setenv("CN_K2_CLASS", str(cls))
         banner(f"interface variant {cls} {prec}")
         s = solver(inst, pc_prec=prec)
