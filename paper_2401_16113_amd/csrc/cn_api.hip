@@ -85,6 +85,8 @@ struct cn_aao {
   hipStream_t stream = nullptr;
   int device = 0;
   long long n = 0, npad = 0;
+  int ldx = 0;        // internal row pitch (N_x rounded up to 16)
+  long long nin = 0;  // N_t ldx
   PcPlan pl;
   double* dw = nullptr;   // time weights (device) or null
   double* V = nullptr;    // (m_max+1) x npad float64
@@ -139,8 +141,10 @@ static void fill_desc(cn_aao* h, InstDesc* d) {
   d->rows = matvec_rows(h->nx, h->nt);
   d->mv_cols = (h->nx + 255) / 256;
   d->mv_grid = d->mv_cols * ((h->nt + d->rows - 1) / d->rows);
-  d->st_grid = stream_grid(h->n);
+  d->st_grid = stream_grid(h->nin);
   d->n = h->n;
+  d->ldx = h->ldx;
+  d->nin = h->nin;
   d->vstride = h->npad;
   d->off = 0;
   d->V = h->V;
@@ -281,7 +285,9 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   h->prec = p->pc_prec == CN_PC_FP32 ? 1 : 0;
   h->stream = (hipStream_t)p->stream;
   h->n = n;
-  h->npad = (n + 63) / 64 * 64;
+  h->ldx = (p->nx + 15) / 16 * 16;
+  h->nin = (long long)p->nt * h->ldx;
+  h->npad = (h->nin + 63) / 64 * 64;
   auto bail = [&](cn_status s) {
     release(h);
     return s;
@@ -476,10 +482,13 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   TRY(dalloc(h, &h->V, (size_t)(h->m_max + 1) * h->npad * sizeof(double)));
   TRY(dalloc(h, &h->Z, (size_t)h->m_max * h->npad * rsz));
   TRY(dalloc(h, &h->w, (size_t)h->npad * sizeof(double)));
+  // the pad columns of V and w take part in the Gram-Schmidt passes as zeros
+  TRY(hipMemsetAsync(h->V, 0, (size_t)(h->m_max + 1) * h->npad * sizeof(double), h->stream));
+  TRY(hipMemsetAsync(h->w, 0, (size_t)h->npad * sizeof(double), h->stream));
   {
     const int rows = matvec_rows(nx, nt);
     const long long mgrid = (long long)((nx + 255) / 256) * ((nt + rows - 1) / rows);
-    const long long pgrid = std::max<long long>(mgrid, stream_grid(h->n));
+    const long long pgrid = std::max<long long>(mgrid, stream_grid(h->nin));
     TRY(dalloc(h, &h->partials, (size_t)pgrid * NVMAX * sizeof(double)));
   }
   TRY(dalloc(h, &h->st, sizeof(GState)));
@@ -556,10 +565,10 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
         e = setup(ci, &sing);
         if (e != hipSuccess || sing) continue;
         auto apply = [&]() -> hipError_t {
-          hipError_t r = pc_forward(pl.prec, pl.log2n, ci, h->L, h->wl.I_pc, 0, h->V, h->stream);
+          hipError_t r = pc_forward(pl.prec, pl.log2n, ci, h->L, h->wl.I_pc, 0, h->V, 0, h->stream);
           if (r == hipSuccess) r = pc_reduced(pl.prec, h->L, h->wl.I_k2, h->k2_thr, 0, 1, h->stream);
           if (r == hipSuccess)
-            r = pc_inverse(pl.prec, pl.log2n, ci, h->L, h->wl.I_pc, 0, h->Z, pl.prec, h->stream);
+            r = pc_inverse(pl.prec, pl.log2n, ci, h->L, h->wl.I_pc, 0, h->Z, pl.prec, 0, h->stream);
           return r;
         };
         e = apply();
@@ -663,11 +672,11 @@ static hipError_t enqueue_iteration(SolveCtx& c, int j, int stop_iter, double rt
                                     int seq) {
   hipError_t e = hipSuccess;
   for (const PcGroup& g : c.groups)
-    if (e == hipSuccess) e = pc_forward(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, c.s);
+    if (e == hipSuccess) e = pc_forward(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, 0, c.s);
   if (e == hipSuccess) e = pc_reduced(c.prec, c.L, c.k2, c.k2_thr, j, 0, c.s);
   for (const PcGroup& g : c.groups)
     if (e == hipSuccess)
-      e = pc_inverse(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, c.L.zf, c.s);
+      e = pc_inverse(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, c.L.zf, 0, c.s);
   if (e == hipSuccess) e = launch_arnoldi(c.L, c.mv, c.stv, j, stop_iter, rtol, slot, seq, c.s);
   return e;
 }
@@ -957,9 +966,9 @@ cn_status cn_matvec(cn_aao* h, const double* x, double* y) {
 cn_status cn_pc_apply(cn_aao* h, const double* v, double* z) {
   if (h == nullptr || v == nullptr || z == nullptr) return fail(CN_EINVAL, "NULL argument");
   const PcPlan& pl = h->pl;
-  HIP_TRY(pc_forward(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, v, h->stream));
+  HIP_TRY(pc_forward(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, v, h->nx, h->stream));
   HIP_TRY(pc_reduced(pl.prec, h->L, h->wl.I_k2, h->k2_thr, 0, 1, h->stream));
-  HIP_TRY(pc_inverse(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, z, 0, h->stream));
+  HIP_TRY(pc_inverse(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, z, 0, h->nx, h->stream));
   return CN_OK;
 }
 
@@ -1007,9 +1016,9 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
     hipError_t e = hipEventRecord(ev[0], s);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       switch (kk) {
-        case 0: e = pc_forward(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, j, nullptr, s); break;
+        case 0: e = pc_forward(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, j, nullptr, 0, s); break;
         case 1: e = pc_reduced(pl.prec, h->L, h->wl.I_k2, h->k2_thr, j, 0, s); break;
-        case 2: e = pc_inverse(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, j, nullptr, zf, s); break;
+        case 2: e = pc_inverse(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, j, nullptr, zf, 0, s); break;
         // the three streaming Krylov kernels alone (their one-workgroup
         // finishing reductions are left out, so each entry is one kernel)
         case 3: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 1, false); break;

@@ -72,7 +72,10 @@ struct InstDesc {
   int mv_cols;            // column blocks of the matvec
   int mv_grid;            // matvec workgroups (partials per dot)
   int st_grid;            // workgroups of the streaming passes
-  long long n;            // unknowns
+  long long n;            // unknowns (caller layout: row k of N_x values at k N_x)
+  int ldx;                // row pitch of the internal vectors (V, Z, w): N_x rounded
+                          // up to 16, so every row starts on a 128-byte line
+  long long nin;          // elements of an internal vector, N_t ldx (pads stay 0)
   long long vstride;      // elements between basis vectors
   long long off;          // offset of the instance in packed b / x arrays
   double* V;              // basis (m_max + 1 vectors)
@@ -104,16 +107,17 @@ __device__ __forceinline__ int2 work_item(const int2* __restrict__ items, int i)
 }
 
 // Launchers (cn_pc.hip, cn_pc_f64.hip, cn_pc_f32.hip).  `v`/`z` override the
-// basis vector V_j / Z_j of a single instance (standalone apply, no stop flag).
+// basis vector V_j / Z_j of a single instance (standalone apply, no stop flag);
+// `pitch` is their row pitch (0: the internal pitch ldx of V and Z).
 hipError_t pc_setup(PcPlan& pl, Cx<double>* spk, int* err_dev, hipStream_t s);
 hipError_t pc_forward(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
-                      const double* v, hipStream_t s);
+                      const double* v, int pitch, hipStream_t s);
 // chunk_class: k2_chunk_class(largest NS of the launch, precision)
 int k2_chunk_class(int ns, int prec);
 hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int chunk_class, int j,
                       int standalone, hipStream_t s);
 hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
-                      void* z, int zf, hipStream_t s);
+                      void* z, int zf, int pitch, hipStream_t s);
 // (B, T) of compiled candidate `ci`; false if that candidate is not compiled
 bool pc_candidate(int prec, int log2n, int ci, int* B, int* T);
 

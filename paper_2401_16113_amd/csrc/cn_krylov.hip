@@ -129,6 +129,9 @@ __global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
   }
   const int nv = j + 1;
   const int nx = d.nx;
+  // row pitches: caller vectors use N_x, internal ones (V, Z, w) ldx
+  const int px = MODE == 2 ? d.ldx : nx;   // x (and b)
+  const int py = MODE == 0 ? nx : d.ldx;   // y (and the basis V)
   const int blk = wi.y;
   const int cb = blk % d.mv_cols, rb = blk / d.mv_cols;
   const int i = cb * KT + threadIdx.x;
@@ -141,14 +144,14 @@ __global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
     const bool hl = i > 0, hr = i < nx - 1;
     double pm = 0.0, pc = 0.0, pp = 0.0;  // previous level at i-1, i, i+1
     if (k0 > 0 && x != nullptr) {
-      const TX* xr = x + (size_t)(k0 - 1) * nx;
+      const TX* xr = x + (size_t)(k0 - 1) * px;
       pc = (double)xr[i];
       if (hl) pm = (double)xr[i - 1];
       if (hr) pp = (double)xr[i + 1];
     }
     for (int k = k0; k < k1; ++k) {
       double cm = 0.0, cc = 0.0, cp = 0.0;
-      const size_t off = (size_t)k * nx;
+      const size_t off = (size_t)k * px, offy = (size_t)k * py;
       if (x != nullptr) {
         cc = (double)x[off + i];
         if (hl) cm = (double)x[off + i - 1];
@@ -165,11 +168,11 @@ __global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
         acc[0] += yv * yv;
         acc[1] += bv * bv;
       }
-      y[off + i] = yv;
+      y[offy + i] = yv;
       if (MODE == 2) {
 #pragma unroll
         for (int q = 0; q < NV; ++q)
-          if (q < nv) acc[q] += d.V[(size_t)q * d.vstride + off + i] * yv;
+          if (q < nv) acc[q] += d.V[(size_t)q * d.vstride + offy + i] * yv;
       }
       pm = cm;
       pc = cc;
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(KT) void k_cgs_pass1(const InstDesc* __restrict__ D
   const double* __restrict__ w = d.w;
   const double* __restrict__ V = d.V;
   const long long stride = (long long)d.st_grid * KT;
-  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.n; e += stride) {
+  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.nin; e += stride) {
     double vq[NV];
     double wv = w[e];
 #pragma unroll
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(KT) void k_cgs_pass2(const InstDesc* __restrict__ D
   const double* __restrict__ V = d.V;
   double* __restrict__ vout = d.V + (size_t)(j + 1) * d.vstride;
   const long long stride = (long long)d.st_grid * KT;
-  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.n; e += stride) {
+  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.nin; e += stride) {
     double wv = w[e];
 #pragma unroll
     for (int q = 0; q < NV; ++q)
@@ -349,10 +352,12 @@ __global__ __launch_bounds__(KT) void k_fallback(const InstDesc* __restrict__ D,
   const double* __restrict__ b = bb + d.off;
   double* __restrict__ x = xb + d.off;
   double* __restrict__ v = d.V;
-  const long long stride = (long long)d.st_grid * KT;
-  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.n; e += stride) {
-    v[e] = b[e];
-    x[e] = 0.0;
+  // rows of the caller layout (pitch N_x) into V_0 (pitch ldx)
+  for (int k = wi.y; k < d.nt; k += d.st_grid) {
+    for (int i = threadIdx.x; i < d.nx; i += KT) {
+      v[(size_t)k * d.ldx + i] = b[(size_t)k * d.nx + i];
+      x[(size_t)k * d.nx + i] = 0.0;
+    }
   }
 }
 
@@ -390,18 +395,21 @@ __global__ __launch_bounds__(KT) void k_update(const InstDesc* __restrict__ D,
   const TZ* __restrict__ Z = (const TZ*)d.Z;
   double* __restrict__ x = xb + d.off;
   const long long zstride = d.vstride;
-  const long long stride = (long long)d.st_grid * KT;
-  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.n; e += stride) {
-    double s = (x_zero & 1) ? 0.0 : x[e];
-    int q = 0;
-    for (; q + 4 <= k; q += 4) {
-      s += y[q] * (double)Z[(size_t)q * zstride + e] +
-           y[q + 1] * (double)Z[(size_t)(q + 1) * zstride + e] +
-           y[q + 2] * (double)Z[(size_t)(q + 2) * zstride + e] +
-           y[q + 3] * (double)Z[(size_t)(q + 3) * zstride + e];
+  // rows of the caller layout (pitch N_x); Z has the internal pitch ldx
+  for (int row = wi.y; row < d.nt; row += d.st_grid) {
+    for (int i = threadIdx.x; i < d.nx; i += KT) {
+      const size_t e = (size_t)row * d.nx + i, ez = (size_t)row * d.ldx + i;
+      double s = (x_zero & 1) ? 0.0 : x[e];
+      int q = 0;
+      for (; q + 4 <= k; q += 4) {
+        s += y[q] * (double)Z[(size_t)q * zstride + ez] +
+             y[q + 1] * (double)Z[(size_t)(q + 1) * zstride + ez] +
+             y[q + 2] * (double)Z[(size_t)(q + 2) * zstride + ez] +
+             y[q + 3] * (double)Z[(size_t)(q + 3) * zstride + ez];
+      }
+      for (; q < k; ++q) s += y[q] * (double)Z[(size_t)q * zstride + ez];
+      x[e] = s;
     }
-    for (; q < k; ++q) s += y[q] * (double)Z[(size_t)q * zstride + e];
-    x[e] = s;
   }
 }
 

@@ -488,10 +488,14 @@ __global__ void k_setup_reduced(const double* __restrict__ lo, const double* __r
 // ---------------------------------------------------------------------------
 // launchers: the transform kernels live in cn_pc_f64.hip / cn_pc_f32.hip
 // ---------------------------------------------------------------------------
-hipError_t pc_forward_f64(int, int, const Launch&, const Items&, int, const double*, hipStream_t);
-hipError_t pc_forward_f32(int, int, const Launch&, const Items&, int, const double*, hipStream_t);
-hipError_t pc_inverse_f64(int, int, const Launch&, const Items&, int, void*, int, hipStream_t);
-hipError_t pc_inverse_f32(int, int, const Launch&, const Items&, int, void*, int, hipStream_t);
+hipError_t pc_forward_f64(int, int, const Launch&, const Items&, int, const double*, int,
+                          hipStream_t);
+hipError_t pc_forward_f32(int, int, const Launch&, const Items&, int, const double*, int,
+                          hipStream_t);
+hipError_t pc_inverse_f64(int, int, const Launch&, const Items&, int, void*, int, int,
+                          hipStream_t);
+hipError_t pc_inverse_f32(int, int, const Launch&, const Items&, int, void*, int, int,
+                          hipStream_t);
 bool pc_candidate_f64(int log2n, int ci, int* B, int* T);
 bool pc_candidate_f32(int log2n, int ci, int* B, int* T);
 
@@ -500,15 +504,15 @@ bool pc_candidate(int prec, int log2n, int ci, int* B, int* T) {
 }
 
 hipError_t pc_forward(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
-                      const double* v, hipStream_t s) {
-  return prec ? pc_forward_f32(log2n, cand, L, it, j, v, s)
-              : pc_forward_f64(log2n, cand, L, it, j, v, s);
+                      const double* v, int pitch, hipStream_t s) {
+  return prec ? pc_forward_f32(log2n, cand, L, it, j, v, pitch, s)
+              : pc_forward_f64(log2n, cand, L, it, j, v, pitch, s);
 }
 
 hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
-                      void* z, int zf, hipStream_t s) {
-  return prec ? pc_inverse_f32(log2n, cand, L, it, j, z, zf, s)
-              : pc_inverse_f64(log2n, cand, L, it, j, z, zf, s);
+                      void* z, int zf, int pitch, hipStream_t s) {
+  return prec ? pc_inverse_f32(log2n, cand, L, it, j, z, zf, pitch, s)
+              : pc_inverse_f64(log2n, cand, L, it, j, z, zf, pitch, s);
 }
 
 // Interface-solve variant for separator systems of up to `ns` unknowns:

@@ -5,10 +5,10 @@ namespace cn {
 
 #define CN_FWD_CASE_f32(L) \
   case L:                 \
-    return fwd_cand<float, L>(cand, Lc, it, j, v, s);
+    return fwd_cand<float, L>(cand, Lc, it, j, v, pitch, s);
 #define CN_INV_CASE_f32(L) \
   case L:                 \
-    return inv_cand<float, L>(cand, Lc, it, j, z, zf, s);
+    return inv_cand<float, L>(cand, Lc, it, j, z, zf, pitch, s);
 #define CN_INFO_CASE_f32(L) \
   case L:                  \
     return cand_info<float, L>(ci, B, T);

@@ -5,10 +5,10 @@ namespace cn {
 
 #define CN_FWD_CASE_f64(L) \
   case L:                 \
-    return fwd_cand<double, L>(cand, Lc, it, j, v, s);
+    return fwd_cand<double, L>(cand, Lc, it, j, v, pitch, s);
 #define CN_INV_CASE_f64(L) \
   case L:                 \
-    return inv_cand<double, L>(cand, Lc, it, j, z, zf, s);
+    return inv_cand<double, L>(cand, Lc, it, j, z, zf, pitch, s);
 #define CN_INFO_CASE_f64(L) \
   case L:                  \
     return cand_info<double, L>(ci, B, T);

@@ -28,7 +28,7 @@ __device__ __forceinline__ void pc_forward_tile(
     const double* __restrict__ di, const double* __restrict__ up,
     const double* __restrict__ wfw, const Cx<R>* __restrict__ tw,
     const Cx<double>* __restrict__ mu, const Cx<double>* __restrict__ il2,
-    Cx<R>* __restrict__ spec, Cx<R>* __restrict__ iface, int nx, int P) {
+    Cx<R>* __restrict__ spec, Cx<R>* __restrict__ iface, int nx, int vp, int P) {
   using Cfg = PcCfg<R, LOG2N, BB, TT>;
   constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
   __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
@@ -48,7 +48,7 @@ __device__ __forceinline__ void pc_forward_tile(
     for (int q = 0; q < LPT; ++q) {
       const int e = tid + q * T;
       const int k = e / B, b = e % B;
-      xv[q] = ((N * B) % T == 0 || e < N * B) && b < ncols ? v[(size_t)k * nx + i0 + b] : 0.0;
+      xv[q] = ((N * B) % T == 0 || e < N * B) && b < ncols ? v[(size_t)k * vp + i0 + b] : 0.0;
     }
     TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
     if constexpr (Cfg::TWL) tws.fetch(tw);
@@ -147,11 +147,13 @@ __device__ __forceinline__ void pc_forward_tile(
   }
 }
 
+// v_ovr: input vector instead of V_j; pitch: its row pitch (0: the internal
+// pitch of V)
 template <typename R, int LOG2N, int BB, int TT>
 __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ D,
                                                    const int2* __restrict__ items, int nitems,
                                                    int nitems_pad, int jv,
-                                                   const double* __restrict__ v_ovr) {
+                                                   const double* __restrict__ v_ovr, int pitch) {
   const int itx = xcd_tile(blockIdx.x, nitems_pad);
   if (itx >= nitems) return;
   const int2 wi = work_item(items, itx);
@@ -163,7 +165,8 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
   const double sc = v_ovr != nullptr ? 1.0 : d.st->vscale[jv];
   const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
   pc_forward_tile<R, LOG2N, BB, TT>(wi.y, v, sc, pl.lo, pl.di, pl.up, pl.wfw, tw, pl.mu, pl.il2,
-                                    (Cx<R>*)pl.spec, (Cx<R>*)pl.iface, pl.nx, pl.P);
+                                    (Cx<R>*)pl.spec, (Cx<R>*)pl.iface, pl.nx,
+                                    pitch > 0 ? pitch : d.ldx, pl.P);
 }
 
 // ---------------------------------------------------------------------------
@@ -175,7 +178,7 @@ __device__ __forceinline__ void pc_inverse_tile(
     const double* __restrict__ lo, const double* __restrict__ di,
     const double* __restrict__ up, const double* __restrict__ winv,
     const Cx<R>* __restrict__ tw, const Cx<double>* __restrict__ mu, TZ* __restrict__ z, int nx,
-    int P, int NS) {
+    int zp, int P, int NS) {
   using Cfg = PcCfg<R, LOG2N, BB, TT>;
   constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
   __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
@@ -277,16 +280,19 @@ __device__ __forceinline__ void pc_inverse_tile(
       const int k = e / B, b = e % B;
       if (((N * B) % T == 0 || e < N * B) && b < ncols) {
         const double val = (double)ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] * winv[k];
-        z[(size_t)k * nx + i0 + b] = (TZ)val;
+        z[(size_t)k * zp + i0 + b] = (TZ)val;
       }
     }
   }
 }
 
+// z_ovr: output vector instead of Z_j; pitch: its row pitch (0: the internal
+// pitch of Z)
 template <typename R, int LOG2N, int BB, int TT, typename TZ>
 __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ D,
                                                    const int2* __restrict__ items, int nitems,
-                                                   int nitems_pad, int jv, TZ* __restrict__ z_ovr) {
+                                                   int nitems_pad, int jv, TZ* __restrict__ z_ovr,
+                                                   int pitch) {
   const int itx = xcd_tile(blockIdx.x, nitems_pad);
   if (itx >= nitems) return;
   const int2 wi = work_item(items, itx);
@@ -296,7 +302,8 @@ __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ 
   TZ* z = z_ovr != nullptr ? z_ovr : (TZ*)d.Z + (size_t)jv * d.vstride;
   const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
   pc_inverse_tile<R, LOG2N, BB, TT, TZ>(wi.y, (const Cx<R>*)pl.spec, (const Cx<R>*)pl.sep, pl.lo,
-                                        pl.di, pl.up, pl.winv, tw, pl.mu, z, pl.nx, pl.P, pl.NS);
+                                        pl.di, pl.up, pl.winv, tw, pl.mu, z, pl.nx,
+                                        pitch > 0 ? pitch : d.ldx, pl.P, pl.NS);
 }
 
 // ---------------------------------------------------------------------------
@@ -306,7 +313,7 @@ static inline int pad8(int v) { return (v + 7) / 8 * 8; }
 
 template <typename R, int L, int CI>
 static hipError_t launch_fwd_c(const Launch& Lc, const Items& it, int j, const double* v,
-                               hipStream_t s) {
+                               int pitch, hipStream_t s) {
   using C = PcCand<R, L, CI>;
   if constexpr (!C::ok) {
     return hipErrorInvalidValue;
@@ -314,14 +321,14 @@ static hipError_t launch_fwd_c(const Launch& Lc, const Items& it, int j, const d
     if (it.n <= 0) return hipSuccess;
     const int nwg = pad8(it.n);
     hipLaunchKernelGGL((k_pc_forward<R, L, C::B, C::T>), dim3(nwg), dim3(C::T), 0, s, Lc.D, it.it,
-                       it.n, nwg, j, v);
+                       it.n, nwg, j, v, pitch);
     return hipGetLastError();
   }
 }
 
 template <typename R, int L, int CI>
 static hipError_t launch_inv_c(const Launch& Lc, const Items& it, int j, void* z, int zf,
-                               hipStream_t s) {
+                               int pitch, hipStream_t s) {
   using C = PcCand<R, L, CI>;
   if constexpr (!C::ok) {
     return hipErrorInvalidValue;
@@ -330,33 +337,33 @@ static hipError_t launch_inv_c(const Launch& Lc, const Items& it, int j, void* z
     const int nwg = pad8(it.n);
     if (zf)
       hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, float>), dim3(nwg), dim3(C::T), 0, s,
-                         Lc.D, it.it, it.n, nwg, j, (float*)z);
+                         Lc.D, it.it, it.n, nwg, j, (float*)z, pitch);
     else
       hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, double>), dim3(nwg), dim3(C::T), 0, s,
-                         Lc.D, it.it, it.n, nwg, j, (double*)z);
+                         Lc.D, it.it, it.n, nwg, j, (double*)z, pitch);
     return hipGetLastError();
   }
 }
 
 template <typename R, int L, int CI = 0>
 static hipError_t fwd_cand(int ci, const Launch& Lc, const Items& it, int j, const double* v,
-                           hipStream_t s) {
+                           int pitch, hipStream_t s) {
   if constexpr (CI >= kNumCand) {
     return hipErrorInvalidValue;
   } else {
-    if (ci == CI) return launch_fwd_c<R, L, CI>(Lc, it, j, v, s);
-    return fwd_cand<R, L, CI + 1>(ci, Lc, it, j, v, s);
+    if (ci == CI) return launch_fwd_c<R, L, CI>(Lc, it, j, v, pitch, s);
+    return fwd_cand<R, L, CI + 1>(ci, Lc, it, j, v, pitch, s);
   }
 }
 
 template <typename R, int L, int CI = 0>
 static hipError_t inv_cand(int ci, const Launch& Lc, const Items& it, int j, void* z, int zf,
-                           hipStream_t s) {
+                           int pitch, hipStream_t s) {
   if constexpr (CI >= kNumCand) {
     return hipErrorInvalidValue;
   } else {
-    if (ci == CI) return launch_inv_c<R, L, CI>(Lc, it, j, z, zf, s);
-    return inv_cand<R, L, CI + 1>(ci, Lc, it, j, z, zf, s);
+    if (ci == CI) return launch_inv_c<R, L, CI>(Lc, it, j, z, zf, pitch, s);
+    return inv_cand<R, L, CI + 1>(ci, Lc, it, j, z, zf, pitch, s);
   }
 }
 
@@ -379,14 +386,14 @@ static bool cand_info(int ci, int* B, int* T) {
 
 #define CN_DEFINE_PC_PRECISION(R, SUF)                                                        \
   hipError_t pc_forward_##SUF(int log2n, int cand, const Launch& Lc, const Items& it, int j,  \
-                              const double* v, hipStream_t s) {                               \
+                              const double* v, int pitch, hipStream_t s) {                    \
     switch (log2n) {                                                                          \
       CN_LOG2N_CASES(CN_FWD_CASE_##SUF)                                                       \
     }                                                                                         \
     return hipErrorInvalidValue;                                                              \
   }                                                                                           \
   hipError_t pc_inverse_##SUF(int log2n, int cand, const Launch& Lc, const Items& it, int j,  \
-                              void* z, int zf, hipStream_t s) {                               \
+                              void* z, int zf, int pitch, hipStream_t s) {                    \
     switch (log2n) {                                                                          \
       CN_LOG2N_CASES(CN_INV_CASE_##SUF)                                                       \
     }                                                                                         \
