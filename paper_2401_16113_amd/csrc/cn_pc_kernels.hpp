@@ -24,7 +24,8 @@ namespace cn {
 // ---------------------------------------------------------------------------
 template <typename R, int LOG2N, int BB, int TT>
 __device__ __forceinline__ void pc_forward_tile(
-    int p, const double* __restrict__ v, double sc, const double* __restrict__ lo,
+    int p, const double* __restrict__ v, const double* scp, const int* stop,
+    const double* __restrict__ lo,
     const double* __restrict__ di, const double* __restrict__ up,
     const double* __restrict__ wfw, const Cx<R>* __restrict__ tw,
     const Cx<double>* __restrict__ mu, const Cx<double>* __restrict__ il2,
@@ -50,6 +51,10 @@ __device__ __forceinline__ void pc_forward_tile(
       const int k = e / B, b = e % B;
       xv[q] = ((N * B) % T == 0 || e < N * B) && b < ncols ? v[(size_t)k * vp + i0 + b] : 0.0;
     }
+    // the stop flag and the basis scale are read with the tile in flight
+    // (a stopped cycle's loads are simply dropped)
+    if (stop != nullptr && *stop) return;
+    const double sc = scp != nullptr ? *scp : 1.0;
     TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
     if constexpr (Cfg::TWL) tws.fetch(tw);
     if (tid < 3 * B) {
@@ -160,11 +165,12 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
   const InstDesc& d = D[wi.x];
   const PcPlan& pl = d.pl;
   // inside a solve: input V_j scaled by 1/||v_j||, skipped once the cycle stopped
-  if (v_ovr == nullptr && d.st->sum.done) return;
-  const double* v = v_ovr != nullptr ? v_ovr : d.V + (size_t)jv * d.vstride;
-  const double sc = v_ovr != nullptr ? 1.0 : d.st->vscale[jv];
+  const bool in_solve = v_ovr == nullptr;
+  const double* v = in_solve ? d.V + (size_t)jv * d.vstride : v_ovr;
   const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
-  pc_forward_tile<R, LOG2N, BB, TT>(wi.y, v, sc, pl.lo, pl.di, pl.up, pl.wfw, tw, pl.mu, pl.il2,
+  pc_forward_tile<R, LOG2N, BB, TT>(wi.y, v, in_solve ? d.st->vscale + jv : nullptr,
+                                    in_solve ? &d.st->sum.done : nullptr, pl.lo, pl.di, pl.up,
+                                    pl.wfw, tw, pl.mu, pl.il2,
                                     (Cx<R>*)pl.spec, (Cx<R>*)pl.iface, pl.nx,
                                     pitch > 0 ? pitch : d.ldx, pl.P);
 }
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
 // ---------------------------------------------------------------------------
 template <typename R, int LOG2N, int BB, int TT, typename TZ>
 __device__ __forceinline__ void pc_inverse_tile(
-    int p, const Cx<R>* __restrict__ spec, const Cx<R>* __restrict__ sep,
+    int p, const int* stop, const Cx<R>* __restrict__ spec, const Cx<R>* __restrict__ sep,
     const double* __restrict__ lo, const double* __restrict__ di,
     const double* __restrict__ up, const double* __restrict__ winv,
     const Cx<R>* __restrict__ tw, const Cx<double>* __restrict__ mu, TZ* __restrict__ z, int nx,
@@ -196,6 +202,7 @@ __device__ __forceinline__ void pc_inverse_tile(
       const int e = tid + q * T;
       if ((NSEQ * N) % T == 0 || e < NSEQ * N) iv[q] = img[e];
     }
+    if (stop != nullptr && *stop) return;  // read with the image in flight
     TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
     if constexpr (Cfg::TWL) tws.fetch(tw);
     if (tid < 3 * B) {
@@ -298,10 +305,10 @@ __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ 
   const int2 wi = work_item(items, itx);
   const InstDesc& d = D[wi.x];
   const PcPlan& pl = d.pl;
-  if (z_ovr == nullptr && d.st->sum.done) return;
   TZ* z = z_ovr != nullptr ? z_ovr : (TZ*)d.Z + (size_t)jv * d.vstride;
   const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
-  pc_inverse_tile<R, LOG2N, BB, TT, TZ>(wi.y, (const Cx<R>*)pl.spec, (const Cx<R>*)pl.sep, pl.lo,
+  pc_inverse_tile<R, LOG2N, BB, TT, TZ>(wi.y, z_ovr == nullptr ? &d.st->sum.done : nullptr,
+                                        (const Cx<R>*)pl.spec, (const Cx<R>*)pl.sep, pl.lo,
                                         pl.di, pl.up, pl.winv, tw, pl.mu, z, pl.nx,
                                         pitch > 0 ? pitch : d.ldx, pl.P, pl.NS);
 }
