@@ -302,11 +302,23 @@ def cpu_baseline(inst, x_gpu):
     u = O.sequential_cn(*args, inst.u0, inst.f)
     scale = np.max(np.abs(u))
     errs = {k: float(np.max(np.abs(v - u)) / scale) for k, v in x_gpu.items()}
+    # the plain definition (CN time stepping with banded solves) for context
+    t0 = time.perf_counter()
+    O.sequential_cn_banded(*args, inst.u0, f=inst.f)
+    sec_cn = time.perf_counter() - t0
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": inst.n / sec, "unit": "unknowns/s", "cores": int(cores), "kind": "oracle",
         "sample": (f"whole solve of the same {inst.nx}x{inst.nt} workload by the FP64 oracle "
                    f"(right-preconditioned GMRES({M}), direct O(N_t^2) DFT sums), median of 3 "
                    f"runs, {sec:.2f} s each, {r.iters} iterations"),
+        "cpu_model": cpu, "host_cores": len(os.sched_getaffinity(0)),
+        "sequential_cn_unknowns_per_s": inst.n / sec_cn,
         "gpu_err_vs_exact_cn": errs,
     }
 

@@ -99,6 +99,16 @@ cn_status cn_ws_interpolate(const float *coarse, int32_t count, int32_t nx, int3
                             const double *u0, const double *gl, const double *gr,
                             const double *scale, double *x0, void *stream);
 
+/* The initial guess in one call: the network's forward pass on `count`
+ * feature rows (device, count x n_in, run in chunks of max_batch), the
+ * de-standardised coarse prediction into `coarse` (device workspace,
+ * count x 8192 floats, left holding the prediction), then cn_ws_interpolate
+ * into x0 -- all on the network's stream.  The network must have
+ * n_out = 8192. */
+cn_status cn_ws_predict(cn_mlp *net, const float *features, int32_t count, int32_t nx,
+                        int32_t nt, const double *u0, const double *gl, const double *gr,
+                        const double *scale, float *coarse, double *x0);
+
 const char *cn_ws_last_error(void);
 
 #ifdef __cplusplus

@@ -101,6 +101,7 @@ def load():
                                             ctypes.c_float]),
         "cn_ws_restrict": (ctypes.c_int, [vp, i32, i32, i32, vp, vp, vp]),
         "cn_ws_interpolate": (ctypes.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "cn_ws_predict": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "cn_ws_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -359,6 +360,13 @@ class Mlp:
 
     def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
         _check(self._lib.cn_mlp_adam_step(self._h, lr, beta1, beta2, eps), "cn_mlp_adam_step")
+
+    def predict(self, features, nx: int, nt: int, u0, gl, gr, scale, coarse, x0):
+        """Forward pass + interpolation to the fine grid (cn_ws_predict)."""
+        _check(self._lib.cn_ws_predict(self._h, _f32(features), int(features.shape[0]), nx, nt,
+                                       _ptr(u0), _ptr(gl), _ptr(gr), _ptr(scale), _f32(coarse),
+                                       _ptr(x0)), "cn_ws_predict")
+        return x0
 
 
 def ws_restrict(x, count: int, nx: int, nt: int, inv_scale, coarse, stream=None):

@@ -15,6 +15,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -554,6 +555,22 @@ cn_status cn_ws_interpolate(const float* coarse, int32_t count, int32_t nx, int3
                      (hipStream_t)stream, coarse, count, nx, nt, u0, gl, gr, scale, x0);
   WS_TRY(hipGetLastError());
   return CN_OK;
+}
+
+cn_status cn_ws_predict(cn_mlp* n, const float* features, int32_t count, int32_t nx, int32_t nt,
+                        const double* u0, const double* gl, const double* gr,
+                        const double* scale, float* coarse, double* x0) {
+  if (n == nullptr || features == nullptr || coarse == nullptr || x0 == nullptr)
+    return ws_fail(CN_EINVAL, "NULL argument");
+  if (n->n_out != CX * CT) return ws_fail(CN_EINVAL, "the network must predict 128 x 64 values");
+  if (count < 1) return ws_fail(CN_EINVAL, "count must be >= 1");
+  for (int c0 = 0; c0 < count; c0 += n->max_batch) {
+    const int B = std::min(n->max_batch, count - c0);
+    const cn_status st = cn_mlp_forward(n, features + (size_t)c0 * n->n_in, B,
+                                        coarse + (size_t)c0 * n->n_out);
+    if (st != CN_OK) return st;
+  }
+  return cn_ws_interpolate(coarse, count, nx, nt, u0, gl, gr, scale, x0, n->s);
 }
 
 }  // extern "C"

@@ -175,15 +175,12 @@ def train(X: torch.Tensor, Y: torch.Tensor, epochs: int = 200, batch: int = 256,
 def initial_guess(net: B.Mlp, fb: FamilyBatch, coarse: Optional[torch.Tensor] = None,
                   x0: Optional[torch.Tensor] = None):
     """x0 for every instance of the family batch: network forward pass on the
-    features, then interpolation to the fine grid (both in the library)."""
+    features, then interpolation to the fine grid (one library call)."""
     dev = fb.u0.device
     if coarse is None:
         coarse = torch.empty((fb.count, N_OUT), dtype=torch.float32, device=dev)
     if x0 is None:
         x0 = torch.empty(fb.count * fb.nx * fb.nt, dtype=torch.float64, device=dev)
-    for c0 in range(0, fb.count, net.max_batch):
-        c1 = min(fb.count, c0 + net.max_batch)
-        net.forward(fb.features[c0:c1], coarse[c0:c1])
     scale = torch.ones(fb.count, dtype=torch.float64, device=dev)
-    B.ws_interpolate(coarse, fb.count, fb.nx, fb.nt, fb.u0, fb.gl, fb.gr, scale, x0)
+    net.predict(fb.features, fb.nx, fb.nt, fb.u0, fb.gl, fb.gr, scale, coarse, x0)
     return x0, coarse

@@ -324,3 +324,31 @@ def test_learned_warm_start_gains_over_zero_start():
         err = rel_inf(xs[q * n:(q + 1) * n], u)
         assert err <= max(1e-7, 50 * pw[q].relres_true), (q, err, pw[q])
     net.close()
+
+
+def test_predict_equals_forward_then_interpolate():
+    """cn_ws_predict (chunked forward pass + interpolation in one call) gives
+    bit for bit what the two separate calls give."""
+    banner("ws predict")
+    rng = np.random.default_rng(30)
+    count, nx, nt = 5, 255, 64
+    net = B.Mlp(67, 64, 8192, 2)   # max_batch 2: three chunks
+    net.set_params(torch.as_tensor(WS.init_params(3, 67, 64, 8192), device=dev()))
+    X = f32(rng.standard_normal((count, 67)))
+    u0 = T(rng.standard_normal(count * nx))
+    gl = T(rng.standard_normal(count * nt))
+    gr = T(rng.standard_normal(count * nt))
+    scale = T(rng.uniform(0.5, 2.0, count))
+    coarse = torch.empty((count, 8192), dtype=torch.float32, device=dev())
+    x0 = torch.empty(count * nx * nt, dtype=torch.float64, device=dev())
+    net.predict(X, nx, nt, u0, gl, gr, scale, coarse, x0)
+    c2 = torch.empty_like(coarse)
+    for c0 in range(0, count, 2):
+        net.forward(X[c0:c0 + 2], c2[c0:c0 + 2])
+    x2 = torch.empty_like(x0)
+    B.ws_interpolate(c2, count, nx, nt, u0, gl, gr, scale, x2)
+    torch.cuda.synchronize()
+    assert torch.equal(coarse, c2) and torch.equal(x0, x2)
+    with pytest.raises(B.CnError, match="128 x 64"):
+        B.Mlp(67, 64, 100, 2).predict(X, nx, nt, u0, gl, gr, scale, coarse, x0)
+    net.close()
