@@ -367,7 +367,7 @@ def main():
             "avg_launch_us": round(prof[dom]["ms"] * 1e3, 2),
             "algorithmic_bytes": prof[dom]["bytes"]}
     out = {
-        "metric": "space-time unknowns/s to rel.res 1e-8",
+        "metric": "space-time unknowns/s to rel.res 1e-8: plain vs batched+FP32-PC+warm-start",
         "value": prim["unknowns_per_s"],
         "unit": "unknowns/s",
         "n_gpus": 1,
@@ -381,7 +381,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"local-vol Black-Scholes put, N_x={inst.nx}, N_t={inst.nt}, "
                                f"alpha={inst.alpha}, flexible GMRES({M}), rtol {RTOL}",
-                   "unknowns": inst.n, "form": "fp32_pc"},
+                   "unknowns": inst.n, "form": "fp32_pc",
+                   "plain_form": "plain_fp64 (variants)",
+                   "batched_warm_forms": "forms.warm_start (held-out 2047x512 local-vol puts: "
+                                         "plain_fp64 vs batched_fp32 vs batched_fp32_warm)"},
         "variants": variants,
         "roofline": roof,
     }
