@@ -86,6 +86,7 @@ struct cn_aao {
   int device = 0;
   long long n = 0, npad = 0;
   int ldx = 0;        // internal row pitch (N_x rounded up to 16)
+  long long pgrid = 0;  // partial sums per dot (largest grid of a reducing kernel)
   long long nin = 0;  // N_t ldx
   PcPlan pl;
   double* dw = nullptr;   // time weights (device) or null
@@ -139,7 +140,7 @@ static void fill_desc(cn_aao* h, InstDesc* d) {
   d->nx = h->nx;
   d->nt = h->nt;
   d->rows = matvec_rows(h->nx, h->nt);
-  d->mv_cols = (h->nx + 255) / 256;
+  d->mv_cols = (h->nx + MVT - 1) / MVT;
   d->mv_grid = d->mv_cols * ((h->nt + d->rows - 1) / d->rows);
   d->st_grid = stream_grid(h->nin);
   d->n = h->n;
@@ -151,6 +152,7 @@ static void fill_desc(cn_aao* h, InstDesc* d) {
   d->Z = h->Z;
   d->w = h->w;
   d->partials = h->partials;
+  d->partials2 = h->partials + h->pgrid * NVMAX;
   d->st = h->st;
   d->host = h->hsum_dev;
   d->zf = h->prec;
@@ -487,9 +489,9 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   TRY(hipMemsetAsync(h->w, 0, (size_t)h->npad * sizeof(double), h->stream));
   {
     const int rows = matvec_rows(nx, nt);
-    const long long mgrid = (long long)((nx + 255) / 256) * ((nt + rows - 1) / rows);
-    const long long pgrid = std::max<long long>(mgrid, stream_grid(h->nin));
-    TRY(dalloc(h, &h->partials, (size_t)pgrid * NVMAX * sizeof(double)));
+    const long long mgrid = (long long)((nx + MVT - 1) / MVT) * ((nt + rows - 1) / rows);
+    h->pgrid = std::max<long long>(mgrid, stream_grid(h->nin));
+    TRY(dalloc(h, &h->partials, (size_t)2 * h->pgrid * NVMAX * sizeof(double)));
   }
   TRY(dalloc(h, &h->st, sizeof(GState)));
   TRY(hipMemsetAsync(h->st, 0, sizeof(GState), h->stream));

@@ -81,7 +81,9 @@ struct InstDesc {
   double* V;              // basis (m_max + 1 vectors)
   void* Z;                // preconditioned vectors (float64 or float32)
   double* w;              // matvec output
-  double* partials;       // per-workgroup partial sums [q][block]
+  double* partials;       // per-workgroup partial sums [q][block]: matvec, pass 2
+  double* partials2;      // second buffer: pass 1 (read by pass 2 while pass 1's
+                          // inputs in the first buffer are still needed)
   GState* st;             // solver state
   GSummary* host;         // the instance's summary slot in pinned host memory
   int zf;                 // Z stored in float32
@@ -122,7 +124,11 @@ hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Item
 bool pc_candidate(int prec, int log2n, int ci, int* B, int* T);
 
 // Krylov launchers (cn_krylov.hip)
-constexpr int KGRID = 2048;  // target number of workgroups of a streaming pass
+constexpr int KT = 512;     // threads per workgroup of the streaming Krylov kernels
+constexpr int KGRID = 512;  // most workgroups of a streaming pass (= partial sums
+                            // per dot, which every consumer workgroup re-reduces)
+constexpr int MVT = 256;       // threads per workgroup of the matvec (one column each)
+constexpr int MV_KGRID = 2048; // target workgroups of the matvec (marching depth)
 int matvec_rows(int nx, int nt);
 int stream_grid(long long n);
 // y = M x for one instance (standalone matvec)

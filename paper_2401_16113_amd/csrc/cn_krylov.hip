@@ -20,7 +20,6 @@
 
 namespace cn {
 
-constexpr int KT = 256;  // threads per workgroup of the streaming kernels
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -29,7 +28,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Block-reduce NV accumulators into partials[q*nblk + blk] (fixed order).
-template <int NV>
+template <int NV, int THREADS = KT>
 __device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, double* red,
                                                double* partials, int blk, int nblk) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -44,20 +43,22 @@ __device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, 
   if (tid < nv) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < KT / 64; ++w) s += red[w * NV + tid];
+    for (int w = 0; w < THREADS / 64; ++w) s += red[w * NV + tid];
     partials[(size_t)tid * nblk + blk] = s;
   }
 }
 
 // Sum partials[q*nblk + b] over b for q < nv into out[q]: wave w handles
-// q = w, w + 16, ...; lane l adds b = l, l + 64, ... then the wave adds its
-// lanes.  The order is fixed, so the result is bitwise reproducible.
+// q = w, w + W, ... (W wavefronts); lane l adds b = l, l + 64, ... then the
+// wave adds its lanes.  The order is fixed, so the result is bitwise
+// reproducible -- and identical in every workgroup that computes it.
 constexpr int FT = 1024;    // threads of a finishing kernel
 constexpr int FCHUNK = 32;  // partials per lane loaded back to back
+template <int THREADS = FT>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int nblk,
                                                 int nv, double* out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int q = wv; q < nv; q += FT / 64) {
+  for (int q = wv; q < nv; q += THREADS / 64) {
     const double* p = partials + (size_t)q * nblk;
     double s = 0.0;
     for (int base = 0; base < nblk; base += 64 * FCHUNK) {
@@ -101,13 +102,13 @@ __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int 
 // Each thread marches down the time levels of one spatial column.
 // ---------------------------------------------------------------------------
 template <typename TX, int MODE, int NV>
-__global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
+__global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
                                                const int2* __restrict__ items, int j,
                                                const TX* __restrict__ xo,
                                                const double* __restrict__ bo,
                                                double* __restrict__ yo, int x_zero) {
   constexpr int NA = NV > 2 ? NV : 2;
-  __shared__ double red[(KT / 64) * NA];
+  __shared__ double red[(MVT / 64) * NA];
   const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
   if (MODE == 2 && d.st->sum.done) return;
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
   const int py = MODE == 0 ? nx : d.ldx;   // y (and the basis V)
   const int blk = wi.y;
   const int cb = blk % d.mv_cols, rb = blk / d.mv_cols;
-  const int i = cb * KT + threadIdx.x;
+  const int i = cb * MVT + threadIdx.x;
   const int k0 = rb * d.rows, k1 = min(d.nt, k0 + d.rows);
   double acc[NA];
 #pragma unroll
@@ -180,25 +181,50 @@ __global__ __launch_bounds__(KT) void k_matvec(const InstDesc* __restrict__ D,
     }
   }
   if (MODE == 0) return;
-  block_partials<NA>(acc, MODE == 1 ? 2 : nv, red, d.partials, blk, d.mv_grid);
+  block_partials<NA, MVT>(acc, MODE == 1 ? 2 : nv, red, d.partials, blk, d.mv_grid);
 }
 
 // ---------------------------------------------------------------------------
 // CGS2 second pass: h2 = V^T (w - V c1), w - V c1 is never stored
 // ---------------------------------------------------------------------------
+// The coefficients of a Gram-Schmidt pass from the producer's partial dots:
+// every workgroup reduces them itself (same order, same values), so no
+// finishing kernel sits between the passes.  h_q = <v_q, w> with the stored
+// (unnormalised) basis, c_q = h_q / ||v_q||^2; block 0 of each instance keeps
+// (h, c) in the solver state for the Hessenberg column.
+__device__ __forceinline__ void pass_coeffs(const double* __restrict__ partials, int nblk,
+                                            int nv, const double* __restrict__ vscale,
+                                            double* h_st, double* c_st, bool keep, double* sh,
+                                            double* sc) {
+  reduce_partials<KT>(partials, nblk, nv, sh);
+  if (threadIdx.x < nv) {
+    const int q = threadIdx.x;
+    const double h = sh[q] * vscale[q];
+    sh[q] = h;
+    sc[q] = h * vscale[q];
+    if (keep) {
+      h_st[q] = h;
+      c_st[q] = h * vscale[q];
+    }
+  }
+  __syncthreads();
+}
+
 template <int NV>
 __global__ __launch_bounds__(KT) void k_cgs_pass1(const InstDesc* __restrict__ D,
                                                   const int2* __restrict__ items, int j) {
   __shared__ double red[(KT / 64) * NV];
+  __shared__ double sh[NVMAX], sc[NVMAX];
   const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
-  const GState* st = d.st;
+  GState* st = d.st;
   if (st->sum.done) return;
   const int nv = j + 1;
+  pass_coeffs(d.partials, d.mv_grid, nv, st->vscale, st->h1, st->c1, wi.y == 0, sh, sc);
   double c[NV], acc[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    c[q] = q < nv ? st->c1[q] : 0.0;
+    c[q] = q < nv ? sc[q] : 0.0;
     acc[q] = 0.0;
   }
   const double* __restrict__ w = d.w;
@@ -215,7 +241,7 @@ __global__ __launch_bounds__(KT) void k_cgs_pass1(const InstDesc* __restrict__ D
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] += vq[q] * wv;
   }
-  block_partials<NV>(acc, nv, red, d.partials, wi.y, d.st_grid);
+  block_partials<NV>(acc, nv, red, d.partials2, wi.y, d.st_grid);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,14 +251,16 @@ template <int NV>
 __global__ __launch_bounds__(KT) void k_cgs_pass2(const InstDesc* __restrict__ D,
                                                   const int2* __restrict__ items, int j) {
   __shared__ double red[(KT / 64) * 2];
+  __shared__ double sh[NVMAX], sc[NVMAX];
   const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
-  const GState* st = d.st;
+  GState* st = d.st;
   if (st->sum.done) return;
   const int nv = j + 1;
+  pass_coeffs(d.partials2, d.st_grid, nv, st->vscale, st->h2, st->c2, wi.y == 0, sh, sc);
   double c[NV];
 #pragma unroll
-  for (int q = 0; q < NV; ++q) c[q] = q < nv ? st->c1[q] + st->c2[q] : 0.0;
+  for (int q = 0; q < NV; ++q) c[q] = q < nv ? st->c1[q] + sc[q] : 0.0;
   double acc[2] = {0.0, 0.0};
   const double* __restrict__ w = d.w;
   const double* __restrict__ V = d.V;
@@ -254,9 +282,9 @@ __global__ __launch_bounds__(KT) void k_cgs_pass2(const InstDesc* __restrict__ D
 // FIN 1: residual r = b - M x -> ||b||, beta, v_0 scale, g, relres, stop flag;
 //        j = start mode: 0 restart, 1 first residual, 2 first residual with
 //        fallback to x = 0 when ||r|| >= ||b|| (then beta = ||b||)
-// FIN 2: first Gram-Schmidt dots -> h1, c1
-// FIN 3: second Gram-Schmidt dots -> h2, c2
 // FIN 4: ||v_{j+1}|| -> Hessenberg column, Givens rotation, residual estimate
+// (the Gram-Schmidt coefficients in between are reduced by the passes that
+// consume them)
 // FIN 1 and FIN 4 publish the summary to host slot `slot` of the instance.
 // ---------------------------------------------------------------------------
 template <int FIN>
@@ -273,9 +301,9 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
     if (FIN == 4 && threadIdx.x == 0) publish(host, st->sum, seq);
     return;
   }
-  const int nv = j + 1;
-  const int nq = FIN == 1 ? 2 : (FIN == 4 ? 1 : nv);
-  const int nblk = (FIN == 1 || FIN == 2) ? d.mv_grid : d.st_grid;
+  static_assert(FIN == 1 || FIN == 4, "finishing kernels: cycle start and Givens step");
+  const int nq = FIN == 1 ? 2 : 1;
+  const int nblk = FIN == 1 ? d.mv_grid : d.st_grid;
   reduce_partials(d.partials, nblk, nq, out);
   if (threadIdx.x != 0) return;
   GSummary& sm = st->sum;
@@ -297,14 +325,6 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
     sm.k = 0;
     sm.done = (sm.relres <= rtol || beta == 0.0) ? 1 : 0;
     publish(host, sm, seq);
-  } else if (FIN == 2 || FIN == 3) {
-    double* hh = FIN == 2 ? st->h1 : st->h2;
-    double* cc = FIN == 2 ? st->c1 : st->c2;
-    for (int q = 0; q < nv; ++q) {
-      const double h = out[q] * st->vscale[q];
-      hh[q] = h;
-      cc[q] = h * st->vscale[q];
-    }
   } else {
     const double hn = sqrt(out[0]);
     double col[MMAX + 1];
@@ -480,8 +500,8 @@ static int nv_bucket(int nv) {
 }
 
 int matvec_rows(int nx, int nt) {
-  const int cb = (nx + KT - 1) / KT;
-  int rb = KGRID / cb;
+  const int cb = (nx + MVT - 1) / MVT;
+  int rb = MV_KGRID / cb;
   if (rb < 1) rb = 1;
   if (rb > nt) rb = nt;
   return (nt + rb - 1) / rb;
@@ -496,7 +516,7 @@ int stream_grid(long long n) {
 
 hipError_t launch_matvec_plain(const Launch& L, const Items& mv, const double* x, double* y,
                                hipStream_t s) {
-  hipLaunchKernelGGL((k_matvec<double, 0, 2>), dim3(mv.n), dim3(KT), 0, s, L.D, mv.it, 0, x,
+  hipLaunchKernelGGL((k_matvec<double, 0, 2>), dim3(mv.n), dim3(MVT), 0, s, L.D, mv.it, 0, x,
                      nullptr, y, 0);
   return hipGetLastError();
 }
@@ -504,7 +524,7 @@ hipError_t launch_matvec_plain(const Launch& L, const Items& mv, const double* x
 hipError_t launch_residual(const Launch& L, const Items& mv, const Items& stv,
                            const double* b_base, double* x_base, int x_zero, double rtol,
                            int slot, int seq, hipStream_t s, int start, bool guard) {
-  hipLaunchKernelGGL((k_matvec<double, 1, 2>), dim3(mv.n), dim3(KT), 0, s, L.D, mv.it, 0,
+  hipLaunchKernelGGL((k_matvec<double, 1, 2>), dim3(mv.n), dim3(MVT), 0, s, L.D, mv.it, 0,
                      (const double*)x_base, b_base, nullptr, (x_zero ? 1 : 0) | (guard ? 2 : 0));
   hipLaunchKernelGGL((k_finish<1>), dim3(L.ninst), dim3(FT), 0, s, L.D, start, guard ? 1 : 0,
                      rtol, slot, seq);
@@ -522,20 +542,14 @@ hipError_t launch_arnoldi(const Launch& L, const Items& mv, const Items& stv, in
   case NVB:                                                                                   \
     if (passes & 1) {                                                                         \
       if (L.zf)                                                                               \
-        hipLaunchKernelGGL((k_matvec<float, 2, NVB>), dim3(mv.n), dim3(KT), 0, s, L.D, mv.it, \
+        hipLaunchKernelGGL((k_matvec<float, 2, NVB>), dim3(mv.n), dim3(MVT), 0, s, L.D, mv.it,\
                            j, (const float*)nullptr, nullptr, nullptr, 0);                    \
       else                                                                                    \
-        hipLaunchKernelGGL((k_matvec<double, 2, NVB>), dim3(mv.n), dim3(KT), 0, s, L.D,       \
+        hipLaunchKernelGGL((k_matvec<double, 2, NVB>), dim3(mv.n), dim3(MVT), 0, s, L.D,      \
                            mv.it, j, (const double*)nullptr, nullptr, nullptr, 0);            \
-      if (finish)                                                                             \
-        hipLaunchKernelGGL((k_finish<2>), dim3(L.ninst), dim3(FT), 0, s, L.D, j, stop_iter,  \
-                           rtol, slot, seq);                                                  \
     }                                                                                         \
     if (passes & 2) {                                                                         \
       hipLaunchKernelGGL((k_cgs_pass1<NVB>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, j);    \
-      if (finish)                                                                             \
-        hipLaunchKernelGGL((k_finish<3>), dim3(L.ninst), dim3(FT), 0, s, L.D, j, stop_iter,  \
-                           rtol, slot, seq);                                                  \
     }                                                                                         \
     if (passes & 4) {                                                                         \
       hipLaunchKernelGGL((k_cgs_pass2<NVB>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, j);    \
