@@ -195,10 +195,10 @@ cn_status cn_batch_solve(cn_batch *b, const double *bp, double *xp, const cn_gmr
  * (reads + writes of its inputs and outputs, each touched once).  Kernel
  * order: 0 pc_forward (steps (a) + local (b)), 1 pc_reduced (interface
  * systems of (b)), 2 pc_inverse (correction + step (c)), 3 matvec fused with
- * the first Gram-Schmidt dots, 4 second Gram-Schmidt dots, 5 basis update +
- * norm (each Krylov entry is the streaming kernel alone, without the
- * one-workgroup kernel that finishes its reduction).  ms and bytes: host
- * arrays of 6 doubles.  Synchronises. */
+ * the first Gram-Schmidt dots, 4 second Gram-Schmidt dots (with the
+ * reduction of the first), 5 basis update + norm (with the reduction of the
+ * second); the one-workgroup Givens kernel is not included.  ms and bytes:
+ * host arrays of 6 doubles.  Synchronises. */
 #define CN_PROFILE_KERNELS 6
 cn_status cn_profile_step(cn_aao *h, int32_t j, int32_t reps, double *ms, double *bytes);
 
