@@ -148,6 +148,19 @@ cn_status cn_gmres_solve(cn_aao *h, const double *b, double *x,
 cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
                        int32_t *threads);
 
+/* Form of the preconditioner apply chosen at create time (autotuned, like
+ * the tile shape): *single_launch = 1 when steps (a)-(c) run as one kernel
+ * whose workgroups (one per tile, all resident on the device at once) meet
+ * at two grid-wide barriers around the interface systems, so the tile image
+ * stays in on-chip memory; 0 for the three launches K1, K2, K3.  Only a
+ * stand-alone handle whose tiles all fit on the device at once is eligible.
+ * The environment variable CN_PC_FUSED=0 or =1 at create time restricts the
+ * choice to the three-launch or (where eligible) the single-launch form.  A
+ * barrier that times out (never expected: eligibility is checked against
+ * the device's occupancy) makes the next call on the handle return CN_EHIP
+ * and switches the handle to three launches. */
+cn_status cn_aao_pc_mode(const cn_aao *h, int32_t *single_launch);
+
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems of uneven sizes solved together.  Every
  * step of the method (each transform, interface solve, matvec, Gram-Schmidt
@@ -189,7 +202,7 @@ cn_status cn_batch_solve(cn_batch *b, const double *bp, double *xp, const cn_gmr
 /* Kernel timing of one inner iteration, for benchmarking.  Must follow a
  * cn_gmres_solve on the same handle that ran at least j+1 inner iterations
  * (its basis is reused; the solution is not touched).  Launches each of the
- * six kernels of iteration j `reps` times back to back on the handle's
+ * kernels of iteration j `reps` times back to back on the handle's
  * stream, timed with HIP events, and returns per kernel the average launch
  * duration in milliseconds and the algorithmic bytes one launch must move
  * (reads + writes of its inputs and outputs, each touched once).  Kernel
@@ -197,9 +210,13 @@ cn_status cn_batch_solve(cn_batch *b, const double *bp, double *xp, const cn_gmr
  * systems of (b)), 2 pc_inverse (correction + step (c)), 3 matvec fused with
  * the first Gram-Schmidt dots, 4 second Gram-Schmidt dots (with the
  * reduction of the first), 5 basis update + norm (with the reduction of the
- * second); the one-workgroup Givens kernel is not included.  ms and bytes:
- * host arrays of 6 doubles.  Synchronises. */
-#define CN_PROFILE_KERNELS 6
+ * second); the one-workgroup Givens kernel is not included; 6 the
+ * single-launch apply (steps (a)-(c) in one kernel, see cn_aao_pc_mode).
+ * Only the apply form the handle's solves use is timed: ms is 0 for kernels
+ * 0-2 of a single-launch handle, and ms and bytes are 0 for kernel 6 of a
+ * three-launch handle.  ms and bytes: host arrays of CN_PROFILE_KERNELS
+ * doubles.  Synchronises. */
+#define CN_PROFILE_KERNELS 7
 cn_status cn_profile_step(cn_aao *h, int32_t j, int32_t reps, double *ms, double *bytes);
 
 const char *cn_status_string(cn_status s);

@@ -71,6 +71,7 @@ def load():
         "cn_aao_destroy": (ctypes.c_int, [vp]),
         "cn_aao_query": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                         ctypes.POINTER(i32)]),
+        "cn_aao_pc_mode": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
         "cn_rhs": (ctypes.c_int, [vp, vp, vp, vp]),
         "cn_matvec": (ctypes.c_int, [vp, vp, vp]),
         "cn_pc_apply": (ctypes.c_int, [vp, vp, vp]),
@@ -194,7 +195,10 @@ class Solver:
         b, p, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(self._lib.cn_aao_query(self._h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(t)),
                "cn_aao_query")
-        return {"tile_cols": b.value, "tiles": p.value, "threads": t.value}
+        f = ctypes.c_int32()
+        _check(self._lib.cn_aao_pc_mode(self._h, ctypes.byref(f)), "cn_aao_pc_mode")
+        return {"tile_cols": b.value, "tiles": p.value, "threads": t.value,
+                "single_launch": bool(f.value)}
 
     def rhs(self, u0, f, out):
         _check(self._lib.cn_rhs(self._h, _ptr(u0), _ptr(f), _ptr(out)), "cn_rhs")
@@ -209,15 +213,19 @@ class Solver:
         return out
 
     KERNELS = ("pc_forward", "pc_reduced", "pc_inverse", "matvec_dots", "cgs_pass1",
-               "cgs_pass2")
+               "cgs_pass2", "pc_fused")
 
     def profile_step(self, j: int, reps: int = 20):
-        """Average launch time (ms) and algorithmic bytes of the six kernels of
-        inner iteration j (after a solve with more than j iterations)."""
-        ms = (ctypes.c_double * 6)()
-        by = (ctypes.c_double * 6)()
+        """Average launch time (ms) and algorithmic bytes of the kernels of
+        inner iteration j (after a solve with more than j iterations): the
+        preconditioner apply in the form the handle uses (pc_forward,
+        pc_reduced, pc_inverse, or the single-launch pc_fused) and the three
+        streaming Krylov kernels."""
+        n = len(self.KERNELS)
+        ms = (ctypes.c_double * n)()
+        by = (ctypes.c_double * n)()
         _check(self._lib.cn_profile_step(self._h, int(j), int(reps), ms, by), "cn_profile_step")
-        return {k: {"ms": ms[i], "bytes": by[i]} for i, k in enumerate(self.KERNELS)}
+        return {k: {"ms": ms[i], "bytes": by[i]} for i, k in enumerate(self.KERNELS) if ms[i] > 0}
 
     def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
               use_x0: bool = False, allow_not_converged: bool = True) -> SolveResult:

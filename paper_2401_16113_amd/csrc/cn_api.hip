@@ -30,7 +30,7 @@ static thread_local std::string g_err;
 // Process-wide cache of the autotuned transform variant per
 // (precision, log2 N_t, N_x): later handles of the same shape skip tuning.
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int>, int> g_tune;
+static std::map<std::tuple<int, int, int, int>, int> g_tune;
 
 static cn_status fail(cn_status s, const std::string& msg) {
   g_err = msg;
@@ -104,6 +104,13 @@ struct cn_aao {
   WorkLists wl;
   Launch L{};
   int k2_thr = 32 * 16;  // interface-solve variant (k2_chunk_class)
+  // single-launch apply (one instance, all tiles resident): chosen by the
+  // autotuner; its grid-barrier words and host-visible time-out flag
+  int fused = 0;
+  unsigned long long* bar = nullptr;  // grid-barrier arrival counter
+  int* ferr = nullptr;      // pinned coherent host memory
+  int* ferr_dev = nullptr;
+  unsigned polls = 1u << 22;  // bound of a barrier wait (CN_PC_BARRIER_POLLS)
   std::vector<void*> dev_allocs;
 };
 
@@ -113,6 +120,7 @@ static void release(cn_aao* h) {
   h->wl.release();
   for (void* p : h->dev_allocs) (void)hipFree(p);
   if (h->hsum != nullptr) (void)hipHostFree(h->hsum);
+  if (h->ferr != nullptr) (void)hipHostFree(h->ferr);
   delete h;
 }
 
@@ -257,7 +265,9 @@ const char* cn_last_error(void) { return g_err.c_str(); }
 }  // extern "C"
 
 // Create a handle; force_cand >= 0 skips autotuning and uses that variant.
-static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out) {
+// single: a stand-alone handle (may use the single-launch apply), not a
+// batch member.
+static cn_status create_handle(const cn_problem* p, int force_cand, bool single, cn_aao** out) {
   if (out == nullptr) return fail(CN_EINVAL, "out is NULL");
   *out = nullptr;
   if (p == nullptr) return fail(CN_EINVAL, "problem is NULL");
@@ -500,6 +510,14 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   memset(h->hsum, 0, 4 * sizeof(GSummary));
   TRY(hipHostGetDevicePointer((void**)&h->hsum_dev, h->hsum, 0));
   TRY(dalloc(h, &h->d_desc, sizeof(InstDesc)));
+  if (single) {
+    TRY(dalloc(h, &h->bar, sizeof(unsigned long long)));
+    TRY(hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream));
+    TRY(hipHostMalloc((void**)&h->ferr, sizeof(int), hipHostMallocCoherent | hipHostMallocMapped));
+    *h->ferr = 0;
+    TRY(hipHostGetDevicePointer((void**)&h->ferr_dev, h->ferr, 0));
+    if (const char* bp = getenv("CN_PC_BARRIER_POLLS")) h->polls = (unsigned)strtoul(bp, nullptr, 10);
+  }
 
   // -- preconditioner workspace, interface factorisation, variant choice -------------
   TRY(dalloc(h, &pl.spec, spec_elems * rsz));
@@ -539,15 +557,23 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
       *singular = herr != 0;
       return e;
     };
-    int best = -1;
-    const auto key = std::make_tuple(pl.prec, pl.log2n, nx);
+    // CN_PC_FUSED=0 / 1 restricts a stand-alone handle to the three-launch /
+    // single-launch apply (the latter where eligible)
+    int fused_mode = single ? 2 : 0;
+    if (const char* fz = getenv("CN_PC_FUSED"); fz != nullptr && single)
+      fused_mode = fz[0] == '0' ? 0 : 1;
+    int best = -1, best_fused = 0;
+    const auto key = std::make_tuple(pl.prec, pl.log2n, nx, fused_mode);
     if (force_cand < 0) {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune.find(key);
-      if (it != g_tune.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
-        best = it->second;
+      if (it != g_tune.end() &&
+          std::find(cands.begin(), cands.end(), it->second / 2) != cands.end()) {
+        best = it->second / 2;
+        best_fused = it->second % 2;
+      }
     }
-    if (best < 0 && cands.size() == 1) best = cands[0];
+    if (best < 0 && cands.size() == 1 && fused_mode == 0) best = cands[0];
     hipError_t e = hipSuccess;
     if (best < 0) {
       // time every candidate on this problem's shape as it runs inside a
@@ -561,6 +587,14 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
                                             (size_t)1 << 30);
       if (e == hipSuccess) e = hipMemsetAsync(h->V, 0, flush, h->stream);
       float best_ms = 1e30f;
+      auto fusable = [&](int ci) {
+        int B = 0, T = 0;
+        pc_candidate(pl.prec, pl.log2n, ci, &B, &T);
+        const int P = (nx + B - 1) / B;
+        return pc_fused_ok(pl.prec, pl.log2n, ci, P, P - 1);
+      };
+      bool any_fuse = false;
+      for (int ci : cands) any_fuse = any_fuse || (fused_mode != 0 && fusable(ci));
       for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
         const int ci = cands[c];
         int sing = 0;
@@ -573,32 +607,75 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
             r = pc_inverse(pl.prec, pl.log2n, ci, h->L, h->wl.I_pc, 0, h->Z, pl.prec, 0, h->stream);
           return r;
         };
-        e = apply();
-        float cand_ms = 1e30f;
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-          e = hipMemsetAsync(h->V, 0, flush, h->stream);
-          if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-          if (e == hipSuccess) e = apply();
-          if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-          if (e == hipSuccess) e = hipEventSynchronize(e1);
-          float ms = 0.f;
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-          if (e == hipSuccess) cand_ms = std::min(cand_ms, ms);
+        auto apply1 = [&]() -> hipError_t {
+          return pc_fused(pl.prec, pl.log2n, ci, h->L, pl.P, 0, h->V, 0, h->Z, pl.prec, 0,
+                          h->bar, h->polls, h->ferr_dev, h->stream);
+        };
+        auto time_of = [&](auto&& fn) -> float {
+          float best_t = 1e30f;
+          e = fn();
+          for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipMemsetAsync(h->V, 0, flush, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+            if (e == hipSuccess) e = fn();
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) best_t = std::min(best_t, ms);
+          }
+          return best_t;
+        };
+        const bool can_fuse = fused_mode != 0 && fusable(ci);
+        // CN_PC_FUSED=1: three launches only where no candidate can fuse
+        if (fused_mode != 1 || !any_fuse) {
+          const float t3 = time_of(apply);
+          if (e == hipSuccess && t3 < best_ms) {
+            best_ms = t3;
+            best = ci;
+            best_fused = 0;
+          }
         }
-        if (e == hipSuccess && cand_ms < best_ms) {
-          best_ms = cand_ms;
-          best = ci;
+        if (e == hipSuccess && can_fuse) {
+          // the arrival counter restarts for this candidate's grid size
+          e = hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream);
+          const float t1 = e == hipSuccess ? time_of(apply1) : 0.f;
+          bool timed_out = false;
+          if (e == hipSuccess && *(volatile int*)h->ferr != 0) {
+            // a barrier wait ran out: clear its words, keep three launches
+            e = hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+            *(volatile int*)h->ferr = 0;
+            timed_out = true;
+            if (fused_mode == 1 && any_fuse) {
+              // the three-launch form was not timed for this candidate
+              const float t3 = time_of(apply);
+              if (e == hipSuccess && t3 < best_ms) {
+                best_ms = t3;
+                best = ci;
+                best_fused = 0;
+              }
+            }
+          }
+          if (e == hipSuccess && !timed_out && t1 < best_ms) {
+            best_ms = t1;
+            best = ci;
+            best_fused = 1;
+          }
         }
       }
       if (e0 != nullptr) (void)hipEventDestroy(e0);
       if (e1 != nullptr) (void)hipEventDestroy(e1);
       if (e == hipSuccess && best >= 0 && force_cand < 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[key] = best;
+        g_tune[key] = 2 * best + best_fused;
       }
     }
     int sing = 1;
     if (e == hipSuccess && best >= 0) e = setup(best, &sing);
+    if (e == hipSuccess && h->bar != nullptr)
+      e = hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream);
+    h->fused = best_fused && pc_fused_ok(pl.prec, pl.log2n, best, pl.P, pl.NS) ? 1 : 0;
     free_tmp();
     if (e != hipSuccess) {
       fail(CN_EHIP, std::string("preconditioner set-up: ") + hipGetErrorString(e));
@@ -644,6 +721,11 @@ struct SolveCtx {
   std::vector<long long> off, len;   // packed offsets and lengths
   // batch: captured inner iterations (null: launch kernel by kernel)
   struct GraphCache* graphs = nullptr;
+  // one instance: single-launch apply on P tiles (fused = 0: three launches)
+  int fused = 0, P = 0;
+  unsigned long long* bar = nullptr;
+  unsigned polls = 0;
+  int* ferr_dev = nullptr;
 };
 
 // One captured graph per inner-iteration index j of a batch: the transform
@@ -673,12 +755,18 @@ struct GraphCache {
 static hipError_t enqueue_iteration(SolveCtx& c, int j, int stop_iter, double rtol, int slot,
                                     int seq) {
   hipError_t e = hipSuccess;
-  for (const PcGroup& g : c.groups)
-    if (e == hipSuccess) e = pc_forward(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, 0, c.s);
-  if (e == hipSuccess) e = pc_reduced(c.prec, c.L, c.k2, c.k2_thr, j, 0, c.s);
-  for (const PcGroup& g : c.groups)
-    if (e == hipSuccess)
-      e = pc_inverse(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, c.L.zf, 0, c.s);
+  if (c.fused) {
+    const PcGroup& g = c.groups[0];
+    e = pc_fused(g.prec, g.log2n, g.cand, c.L, c.P, j, nullptr, 0, nullptr, c.L.zf, 0, c.bar,
+                 c.polls, c.ferr_dev, c.s);
+  } else {
+    for (const PcGroup& g : c.groups)
+      if (e == hipSuccess) e = pc_forward(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, 0, c.s);
+    if (e == hipSuccess) e = pc_reduced(c.prec, c.L, c.k2, c.k2_thr, j, 0, c.s);
+    for (const PcGroup& g : c.groups)
+      if (e == hipSuccess)
+        e = pc_inverse(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, c.L.zf, 0, c.s);
+  }
   if (e == hipSuccess) e = launch_arnoldi(c.L, c.mv, c.stv, j, stop_iter, rtol, slot, seq, c.s);
   return e;
 }
@@ -891,6 +979,11 @@ static SolveCtx handle_ctx(cn_aao* h) {
   c.batched = false;
   c.hs = h->hsum;
   c.seqc = &h->seqc;
+  c.fused = h->fused;
+  c.P = h->pl.P;
+  c.bar = h->bar;
+  c.polls = h->polls;
+  c.ferr_dev = h->ferr_dev;
   c.off.assign(1, 0);
   c.len.assign(1, h->n);
   return c;
@@ -930,9 +1023,23 @@ static void batch_release(cn_batch* b) {
   delete b;
 }
 
+// A grid barrier of the single-launch apply that timed out (its workgroups
+// were not all resident) leaves its counter undefined: clear it, fall back to
+// the three-launch apply for the rest of the handle's life, and report.
+static cn_status check_fused(cn_aao* h) {
+  if (h->ferr == nullptr || *(volatile int*)h->ferr == 0) return CN_OK;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  *(volatile int*)h->ferr = 0;
+  h->fused = 0;
+  return fail(CN_EHIP, "single-launch preconditioner: grid barrier timed out (three-launch "
+                       "apply from now on)");
+}
+
 extern "C" {
 
-cn_status cn_aao_create(const cn_problem* p, cn_aao** out) { return create_handle(p, -1, out); }
+cn_status cn_aao_create(const cn_problem* p, cn_aao** out) { return create_handle(p, -1, true, out); }
 
 cn_status cn_aao_destroy(cn_aao* h) {
   if (h == nullptr) return fail(CN_EINVAL, "handle is NULL");
@@ -945,6 +1052,12 @@ cn_status cn_aao_query(const cn_aao* h, int32_t* tile_cols, int32_t* tiles, int3
   if (tile_cols != nullptr) *tile_cols = h->pl.B;
   if (tiles != nullptr) *tiles = h->pl.P;
   if (threads != nullptr) *threads = h->pl.T;
+  return CN_OK;
+}
+
+cn_status cn_aao_pc_mode(const cn_aao* h, int32_t* single_launch) {
+  if (h == nullptr || single_launch == nullptr) return fail(CN_EINVAL, "NULL argument");
+  *single_launch = h->fused;
   return CN_OK;
 }
 
@@ -967,7 +1080,13 @@ cn_status cn_matvec(cn_aao* h, const double* x, double* y) {
 
 cn_status cn_pc_apply(cn_aao* h, const double* v, double* z) {
   if (h == nullptr || v == nullptr || z == nullptr) return fail(CN_EINVAL, "NULL argument");
+  CN_TRY(check_fused(h));
   const PcPlan& pl = h->pl;
+  if (h->fused) {
+    HIP_TRY(pc_fused(pl.prec, pl.log2n, pl.cand, h->L, pl.P, 0, v, h->nx, z, 0, h->nx, h->bar,
+                     h->polls, h->ferr_dev, h->stream));
+    return CN_OK;
+  }
   HIP_TRY(pc_forward(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, v, h->nx, h->stream));
   HIP_TRY(pc_reduced(pl.prec, h->L, h->wl.I_k2, h->k2_thr, 0, 1, h->stream));
   HIP_TRY(pc_inverse(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, z, 0, h->nx, h->stream));
@@ -985,8 +1104,11 @@ cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_o
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
   if (overlaps(b, x, h->n * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
+  CN_TRY(check_fused(h));
   SolveCtx c = handle_ctx(h);
-  return run_solve(c, b, x, opts, info, nullptr);
+  const cn_status st = run_solve(c, b, x, opts, info, nullptr);
+  CN_TRY(check_fused(h));
+  return st;
 }
 
 cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double* bytes) {
@@ -1013,8 +1135,16 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   bytes[3] = n * zes + n * 8 + (double)(j + 1) * n * 8;
   bytes[4] = (double)(j + 2) * n * 8;
   bytes[5] = (double)(j + 3) * n * 8;
+  // the single-launch apply: no tile image through memory
+  bytes[6] = h->fused ? n * 8 + (double)pl.F * pl.P * 10 * rsz + nsep * 14 * rsz + n * zes : 0.0;
+  ms[6] = 0.0;
   cn_status rc = CN_OK;
   for (int kk = 0; kk < CN_PROFILE_KERNELS && rc == CN_OK; ++kk) {
+    // the apply the handle's solves run: three launches or the single launch
+    if ((kk == 6 && !h->fused) || (kk <= 2 && h->fused)) {
+      ms[kk] = 0.0;
+      continue;
+    }
     hipError_t e = hipEventRecord(ev[0], s);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       switch (kk) {
@@ -1026,6 +1156,10 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
         case 3: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 1, false); break;
         case 4: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 2, false); break;
         case 5: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 4, false); break;
+        case 6:
+          e = pc_fused(pl.prec, pl.log2n, pl.cand, h->L, pl.P, j, nullptr, 0, nullptr, zf, 0, h->bar,
+                       h->polls, h->ferr_dev, s);
+          break;
       }
     }
     if (e == hipSuccess) e = hipEventRecord(ev[1], s);
@@ -1040,7 +1174,7 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
-  (void)zes;
+  if (rc == CN_OK) rc = check_fused(h);
   return rc;
 }
 
@@ -1072,7 +1206,7 @@ cn_status cn_batch_create(const cn_problem* probs, int32_t count, cn_batch** out
     while ((1 << l2) < probs[i].nt && l2 < 31) ++l2;
     auto it = group_cand.find(l2);
     cn_aao* h = nullptr;
-    const cn_status st = create_handle(&probs[i], it == group_cand.end() ? -1 : it->second, &h);
+    const cn_status st = create_handle(&probs[i], it == group_cand.end() ? -1 : it->second, false, &h);
     if (st != CN_OK) {
       g_err = "problem " + std::to_string(i) + ": " + g_err;
       batch_release(b);

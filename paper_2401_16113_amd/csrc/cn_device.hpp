@@ -35,6 +35,41 @@ __device__ __forceinline__ Cx<R> mul_mi(Cx<R> a) {
   return INV ? Cx<R>{-a.y, a.x} : Cx<R>{a.y, -a.x};
 }
 
+// Device-coherent (agent-scope) stores and loads of complex values, for data
+// that workgroups of one launch exchange across a grid barrier: they write
+// through to, and read from, the level where the XCDs' caches agree, so the
+// barrier itself needs no cache write-back or invalidation.
+__device__ __forceinline__ void st_dev(Cx<float>* p, Cx<float> v) {
+  unsigned long long u;
+  __builtin_memcpy(&u, &v, sizeof(u));
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), u, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(Cx<double>* p, Cx<double> v) {
+  __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ Cx<float> ld_dev(const Cx<float>* p) {
+  const unsigned long long u = __hip_atomic_load(
+      reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  Cx<float> v;
+  __builtin_memcpy(&v, &u, sizeof(v));
+  return v;
+}
+__device__ __forceinline__ Cx<double> ld_dev(const Cx<double>* p) {
+  return Cx<double>{__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                    __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+}
+// plain (COH = false) or device-coherent (COH = true) access
+template <bool COH, typename R>
+__device__ __forceinline__ void st_x(Cx<R>* p, Cx<R> v) {
+  if constexpr (COH) st_dev(p, v); else *p = v;
+}
+template <bool COH, typename R>
+__device__ __forceinline__ Cx<R> ld_x(const Cx<R>* p) {
+  if constexpr (COH) return ld_dev(p); else return *p;
+}
+
 // Reciprocals.  float64: hardware estimate refined by two Newton steps
 // (error ~1 ulp); float32: hardware estimate (1 ulp).
 __device__ __forceinline__ double rcp(double a) {
@@ -171,6 +206,18 @@ struct PcCand {
                   Cfg::ELEMS >= T && (T < 1024 || B * (int)sizeof(R) <= 64));
 };
 
+// threadIdx.x through an empty asm: index arithmetic derived from it cannot be
+// hoisted above the call or shared with an earlier phase, so a long kernel
+// recomputes its (cheap) per-phase indices instead of keeping them live in
+// registers across the whole launch.
+template <int T>
+__device__ __forceinline__ int phase_tid() {
+  static_assert((T & (T - 1)) == 0, "workgroup size must be a power of two");
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t & (T - 1);  // the known range keeps the index arithmetic narrow
+}
+
 template <int N>
 __device__ __forceinline__ int lidx(int s, int e) {
   return s * (N + N / 16 + 1) + e + (e >> 4);
@@ -180,12 +227,11 @@ __device__ __forceinline__ int lidx(int s, int e) {
 // p is the product of the radices of earlier passes.  All inputs of the pass
 // are read to registers before a barrier, so the pass runs in place.
 template <typename R, int N, int NSEQ, int T, bool INV, int LR, int P, typename TW>
-__device__ __forceinline__ void fft_pass(Cx<R>* lds, const TW& tw) {
+__device__ __forceinline__ void fft_pass(Cx<R>* lds, const TW& tw, int tid) {
   constexpr int RAD = 1 << LR;
   constexpr int NQ = N / RAD;             // butterflies per sequence
   constexpr int NB = NSEQ * NQ;           // butterflies in the pass
   constexpr int PER = (NB + T - 1) / T;   // per thread
-  const int tid = threadIdx.x;
   Cx<R> u[PER][RAD];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -261,24 +307,27 @@ struct TwTab {
 };
 
 template <typename R, int LOG2N, int NSEQ, int T, bool INV, int MAXLOG, int DONE, typename TW>
-__device__ __forceinline__ void fft_run(Cx<R>* lds, const TW& tw) {
+__device__ __forceinline__ void fft_run(Cx<R>* lds, const TW& tw, int tid) {
   if constexpr (DONE < LOG2N) {
     constexpr int LR = (DONE == 0 && (LOG2N % MAXLOG) != 0) ? (LOG2N % MAXLOG) : MAXLOG;
-    fft_pass<R, (1 << LOG2N), NSEQ, T, INV, LR, (1 << DONE)>(lds, tw);
-    fft_run<R, LOG2N, NSEQ, T, INV, MAXLOG, DONE + LR>(lds, tw);
+    fft_pass<R, (1 << LOG2N), NSEQ, T, INV, LR, (1 << DONE)>(lds, tw, tid);
+    fft_run<R, LOG2N, NSEQ, T, INV, MAXLOG, DONE + LR>(lds, tw, tid);
   }
 }
 
 // FFT with the twiddles from LDS (staged as Cfg says) or from global memory.
 template <typename Cfg, typename R, int LOG2N, bool INV>
-__device__ __forceinline__ void fft_tile(Cx<R>* lds, const Cx<R>* ltw, const Cx<R>* __restrict__ tw) {
+// tid: the thread index the passes derive their element indices from (one
+// opaque value per transform, see phase_tid)
+__device__ __forceinline__ void fft_tile(Cx<R>* lds, const Cx<R>* ltw, const Cx<R>* __restrict__ tw,
+                                         int tid) {
   constexpr int N = 1 << LOG2N;
   if constexpr (Cfg::TWMODE == 2) {
-    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, false>{ltw});
+    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, false>{ltw}, tid);
   } else if constexpr (Cfg::TWMODE == 1) {
-    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, true>{ltw});
+    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, true>{ltw}, tid);
   } else {
-    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, false>{tw});
+    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, false>{tw}, tid);
   }
 }
 
