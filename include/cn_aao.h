@@ -208,14 +208,15 @@ cn_status cn_batch_solve(cn_batch *b, const double *bp, double *xp, const cn_gmr
  * (reads + writes of its inputs and outputs, each touched once).  Kernel
  * order: 0 pc_forward (steps (a) + local (b)), 1 pc_reduced (interface
  * systems of (b)), 2 pc_inverse (correction + step (c)), 3 matvec fused with
- * the first Gram-Schmidt dots, 4 second Gram-Schmidt dots (with the
- * reduction of the first), 5 basis update + norm (with the reduction of the
- * second); the one-workgroup Givens kernel is not included; 6 the
- * single-launch apply (steps (a)-(c) in one kernel, see cn_aao_pc_mode).
- * Only the apply form the handle's solves use is timed: ms is 0 for kernels
- * 0-2 of a single-launch handle, and ms and bytes are 0 for kernel 6 of a
- * three-launch handle.  ms and bytes: host arrays of CN_PROFILE_KERNELS
- * doubles.  Synchronises. */
+ * the dots against the basis, 4 unused (ms and bytes 0: the second CGS2
+ * projection takes its coefficients from the basis' Gram matrix and has no
+ * pass of its own), 5 CGS2 update (both projections, with the reduction of
+ * the matvec's dots) + norm + Gram row of the new vector; the one-workgroup
+ * Givens kernel is not included; 6 the single-launch apply (steps (a)-(c) in
+ * one kernel, see cn_aao_pc_mode).  Only the apply form the handle's solves
+ * use is timed: ms is 0 for kernels 0-2 of a single-launch handle, and ms and
+ * bytes are 0 for kernel 6 of a three-launch handle.  ms and bytes: host
+ * arrays of CN_PROFILE_KERNELS doubles.  Synchronises. */
 #define CN_PROFILE_KERNELS 7
 cn_status cn_profile_step(cn_aao *h, int32_t j, int32_t reps, double *ms, double *bytes);
 

@@ -212,15 +212,16 @@ class Solver:
         _check(self._lib.cn_pc_apply(self._h, _ptr(v), _ptr(out)), "cn_pc_apply")
         return out
 
-    KERNELS = ("pc_forward", "pc_reduced", "pc_inverse", "matvec_dots", "cgs_pass1",
-               "cgs_pass2", "pc_fused")
+    # entry 4 is retired (no second dot pass); entries with ms = 0 are dropped
+    KERNELS = ("pc_forward", "pc_reduced", "pc_inverse", "matvec_dots", "retired",
+               "cgs_update", "pc_fused")
 
     def profile_step(self, j: int, reps: int = 20):
         """Average launch time (ms) and algorithmic bytes of the kernels of
         inner iteration j (after a solve with more than j iterations): the
         preconditioner apply in the form the handle uses (pc_forward,
-        pc_reduced, pc_inverse, or the single-launch pc_fused) and the three
-        streaming Krylov kernels."""
+        pc_reduced, pc_inverse, or the single-launch pc_fused) and the two
+        streaming Krylov kernels (matvec with the basis dots, CGS2 update)."""
         n = len(self.KERNELS)
         ms = (ctypes.c_double * n)()
         by = (ctypes.c_double * n)()

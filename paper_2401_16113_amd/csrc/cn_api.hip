@@ -1140,9 +1140,11 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   ms[6] = 0.0;
   cn_status rc = CN_OK;
   for (int kk = 0; kk < CN_PROFILE_KERNELS && rc == CN_OK; ++kk) {
-    // the apply the handle's solves run: three launches or the single launch
-    if ((kk == 6 && !h->fused) || (kk <= 2 && h->fused)) {
+    // the apply the handle's solves run: three launches or the single launch;
+    // kernel 4 no longer exists (the second projection has no pass of its own)
+    if ((kk == 6 && !h->fused) || (kk <= 2 && h->fused) || kk == 4) {
       ms[kk] = 0.0;
+      if (kk == 4) bytes[kk] = 0.0;
       continue;
     }
     hipError_t e = hipEventRecord(ev[0], s);

@@ -56,9 +56,12 @@ struct GState {
   double g[MMAX + 1];
   double cs[MMAX], sn[MMAX];
   double vscale[NVMAX];         // 1/||v_q|| of the stored (unnormalised) basis
-  double h1[NVMAX], c1[NVMAX];  // first Gram-Schmidt pass: coefficients
-  double h2[NVMAX], c2[NVMAX];  // second pass
+  double h1[NVMAX], c1[NVMAX];  // first Gram-Schmidt projection: coefficients
+  double h2[NVMAX], c2[NVMAX];  // second projection
   double y[MMAX];
+  // Gram matrix of the normalised basis, gram[p*NVMAX + q] = <v_p, v_q> /
+  // (||v_p|| ||v_q||) (unit diagonal), rows 0..k of the current cycle
+  double gram[NVMAX * NVMAX];
 };
 
 // Everything a kernel needs to know about one instance.  Kernels receive an
@@ -81,9 +84,9 @@ struct InstDesc {
   double* V;              // basis (m_max + 1 vectors)
   void* Z;                // preconditioned vectors (float64 or float32)
   double* w;              // matvec output
-  double* partials;       // per-workgroup partial sums [q][block]: matvec, pass 2
-  double* partials2;      // second buffer: pass 1 (read by pass 2 while pass 1's
-                          // inputs in the first buffer are still needed)
+  double* partials;       // per-workgroup partial sums [q][block]: matvec
+  double* partials2;      // second buffer: the update pass (written while its
+                          // workgroups still read the matvec's partials)
   GState* st;             // solver state
   GSummary* host;         // the instance's summary slot in pinned host memory
   int zf;                 // Z stored in float32
@@ -155,10 +158,11 @@ hipError_t launch_matvec_plain(const Launch& L, const Items& mv, const double* x
 hipError_t launch_residual(const Launch& L, const Items& mv, const Items& stv,
                            const double* b_base, double* x_base, int x_zero, double rtol,
                            int slot, int seq, hipStream_t s, int start = 0, bool guard = false);
-// one inner iteration's Krylov part: w = M z_j with the first dots, the two
-// CGS2 passes and the Givens update (`finish` = false leaves out the
-// finishing kernels, for timing the streaming kernels alone)
-// passes: bit 0 matvec + first dots, bit 1 second dots, bit 2 update + norm
+// one inner iteration's Krylov part: w = M z_j with the dots against the
+// basis, the update pass (both CGS2 projections, the new vector's norm and
+// Gram row) and the Givens update (`finish` = false leaves out the finishing
+// kernel, for timing the streaming kernels alone)
+// passes: bit 0 matvec + dots, bit 2 update + norm + Gram row (bit 1 unused)
 hipError_t launch_arnoldi(const Launch& L, const Items& mv, const Items& stv, int j, int stop_iter,
                           double rtol, int slot, int seq, hipStream_t s, int passes = 7,
                           bool finish = true);

@@ -1,9 +1,12 @@
 // Krylov kernels of the right-preconditioned GMRES(m) solve on gfx950:
 //   * the all-at-once CN matvec (block form of Sec. 3.2), plain, as a
 //     residual b - M x, and fused with the first Gram-Schmidt dot pass;
-//   * the two remaining CGS2 passes (dots against the stored basis, update,
-//     norm) -- the basis is stored unnormalised with a float64 scale per
-//     vector, so normalisation never costs a pass;
+//   * the CGS2 update pass: both projections in one update of w, the second
+//     one's coefficients from the Gram matrix of the basis (kept up to date
+//     by this pass itself: while it writes v_{j+1} it also forms the dots of
+//     v_{j+1} with the basis), so the second projection needs no pass over
+//     the basis of its own; the basis is stored unnormalised with a float64
+//     scale per vector, so normalisation never costs a pass either;
 //   * the Givens / least-squares update (one workgroup per instance);
 //   * x += Z y and the right-hand side b = xi + tau f (eq. (2.2)).
 // Every kernel serves a list of instances: work items (instance, block) index
@@ -98,7 +101,8 @@ __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int 
 //         r = b - M x into V_0 with ||r||^2, ||b||^2 (MODE 1: x = xo + off,
 //         unread when bit 0 of x_zero is set; bit 1: only for instances whose
 //         cycle has stopped; b = bo + off),
-//         w = M z_j with dots against V_0..V_j (MODE 2, first CGS pass)
+//         w = M z_j with dots against V_0..V_j (MODE 2, the coefficients of
+//         the first CGS2 projection)
 // Each thread marches down the time levels of one spatial column.
 // ---------------------------------------------------------------------------
 template <typename TX, int MODE, int NV>
@@ -185,50 +189,65 @@ __global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
 }
 
 // ---------------------------------------------------------------------------
-// CGS2 second pass: h2 = V^T (w - V c1), w - V c1 is never stored
+// CGS2 update: v_{j+1} = w - V (c1 + c2), its norm and its Gram row
 // ---------------------------------------------------------------------------
-// The coefficients of a Gram-Schmidt pass from the producer's partial dots:
-// every workgroup reduces them itself (same order, same values), so no
-// finishing kernel sits between the passes.  h_q = <v_q, w> with the stored
-// (unnormalised) basis, c_q = h_q / ||v_q||^2; block 0 of each instance keeps
-// (h, c) in the solver state for the Hessenberg column.
-__device__ __forceinline__ void pass_coeffs(const double* __restrict__ partials, int nblk,
-                                            int nv, const double* __restrict__ vscale,
-                                            double* h_st, double* c_st, bool keep, double* sh,
-                                            double* sc) {
+// Coefficients of both projections.  The first, h1_q = <q_q, w> for the
+// normalised basis q_q = v_q / ||v_q||, from the matvec's partial dots: every
+// workgroup reduces them itself (same order, same values), so no finishing
+// kernel sits between the matvec and this pass.  The second projection of
+// CGS2, h2 = Q^T (w - Q h1) = (I - Q^T Q) h1 in exact arithmetic, from the
+// Gram matrix G = Q^T Q of the basis (unit diagonal, so h2_p = -sum_{q != p}
+// G_pq h1_q).  The update forms v_{j+1} from w in one pass either way, so the
+// dots against the once-projected vector would only add that vector's own
+// rounding; the Gram matrix carries what the second pass corrects, the
+// basis' loss of orthogonality.  c = (h1 + h2) / ||v_q|| are the coefficients
+// of the stored (unnormalised) basis; block 0 of each instance keeps h1, h2
+// for the Hessenberg column.
+__device__ __forceinline__ void update_coeffs(const double* __restrict__ partials, int nblk,
+                                              int nv, GState* st, bool keep, double* sh,
+                                              double* sc) {
   reduce_partials<KT>(partials, nblk, nv, sh);
+  if (threadIdx.x < nv) sh[threadIdx.x] *= st->vscale[threadIdx.x];
+  __syncthreads();
   if (threadIdx.x < nv) {
-    const int q = threadIdx.x;
-    const double h = sh[q] * vscale[q];
-    sh[q] = h;
-    sc[q] = h * vscale[q];
+    const int p = threadIdx.x;
+    const double* g = st->gram + (size_t)p * NVMAX;
+    double h2 = 0.0;
+    for (int q = 0; q < nv; ++q)
+      if (q != p) h2 -= g[q] * sh[q];
+    const double h1 = sh[p], s = st->vscale[p];
+    sc[p] = (h1 + h2) * s;
     if (keep) {
-      h_st[q] = h;
-      c_st[q] = h * vscale[q];
+      st->h1[p] = h1;
+      st->h2[p] = h2;
+      st->c1[p] = h1 * s;
+      st->c2[p] = h2 * s;
     }
   }
   __syncthreads();
 }
 
+// partials2 rows: 0 = ||v_{j+1}||^2, 1 + q = <v_q, v_{j+1}> (q <= j)
 template <int NV>
-__global__ __launch_bounds__(KT) void k_cgs_pass1(const InstDesc* __restrict__ D,
-                                                  const int2* __restrict__ items, int j) {
-  __shared__ double red[(KT / 64) * NV];
+__global__ __launch_bounds__(KT) void k_cgs_update(const InstDesc* __restrict__ D,
+                                                   const int2* __restrict__ items, int j) {
+  constexpr int NA = NV + 1;
+  __shared__ double red[(KT / 64) * NA];
   __shared__ double sh[NVMAX], sc[NVMAX];
   const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
   GState* st = d.st;
   if (st->sum.done) return;
   const int nv = j + 1;
-  pass_coeffs(d.partials, d.mv_grid, nv, st->vscale, st->h1, st->c1, wi.y == 0, sh, sc);
-  double c[NV], acc[NV];
+  update_coeffs(d.partials, d.mv_grid, nv, st, wi.y == 0, sh, sc);
+  double c[NV], acc[NA];
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    c[q] = q < nv ? sc[q] : 0.0;
-    acc[q] = 0.0;
-  }
+  for (int q = 0; q < NV; ++q) c[q] = q < nv ? sc[q] : 0.0;
+#pragma unroll
+  for (int q = 0; q < NA; ++q) acc[q] = 0.0;
   const double* __restrict__ w = d.w;
   const double* __restrict__ V = d.V;
+  double* __restrict__ vout = d.V + (size_t)(j + 1) * d.vstride;
   const long long stride = (long long)d.st_grid * KT;
   for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.nin; e += stride) {
     double vq[NV];
@@ -238,43 +257,12 @@ __global__ __launch_bounds__(KT) void k_cgs_pass1(const InstDesc* __restrict__ D
       vq[q] = q < nv ? V[(size_t)q * d.vstride + e] : 0.0;
       wv -= c[q] * vq[q];
     }
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] += vq[q] * wv;
-  }
-  block_partials<NV>(acc, nv, red, d.partials2, wi.y, d.st_grid);
-}
-
-// ---------------------------------------------------------------------------
-// CGS2 update: v_{j+1} = w - V (c1 + c2) and its norm
-// ---------------------------------------------------------------------------
-template <int NV>
-__global__ __launch_bounds__(KT) void k_cgs_pass2(const InstDesc* __restrict__ D,
-                                                  const int2* __restrict__ items, int j) {
-  __shared__ double red[(KT / 64) * 2];
-  __shared__ double sh[NVMAX], sc[NVMAX];
-  const int2 wi = work_item(items, blockIdx.x);
-  const InstDesc& d = D[wi.x];
-  GState* st = d.st;
-  if (st->sum.done) return;
-  const int nv = j + 1;
-  pass_coeffs(d.partials2, d.st_grid, nv, st->vscale, st->h2, st->c2, wi.y == 0, sh, sc);
-  double c[NV];
-#pragma unroll
-  for (int q = 0; q < NV; ++q) c[q] = q < nv ? st->c1[q] + sc[q] : 0.0;
-  double acc[2] = {0.0, 0.0};
-  const double* __restrict__ w = d.w;
-  const double* __restrict__ V = d.V;
-  double* __restrict__ vout = d.V + (size_t)(j + 1) * d.vstride;
-  const long long stride = (long long)d.st_grid * KT;
-  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.nin; e += stride) {
-    double wv = w[e];
-#pragma unroll
-    for (int q = 0; q < NV; ++q)
-      if (q < nv) wv -= c[q] * V[(size_t)q * d.vstride + e];
     vout[e] = wv;
     acc[0] += wv * wv;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[1 + q] += vq[q] * wv;
   }
-  block_partials<2>(acc, 1, red, d.partials, wi.y, d.st_grid);
+  block_partials<NA>(acc, nv + 1, red, d.partials2, wi.y, d.st_grid);
 }
 
 // ---------------------------------------------------------------------------
@@ -282,9 +270,10 @@ __global__ __launch_bounds__(KT) void k_cgs_pass2(const InstDesc* __restrict__ D
 // FIN 1: residual r = b - M x -> ||b||, beta, v_0 scale, g, relres, stop flag;
 //        j = start mode: 0 restart, 1 first residual, 2 first residual with
 //        fallback to x = 0 when ||r|| >= ||b|| (then beta = ||b||)
-// FIN 4: ||v_{j+1}|| -> Hessenberg column, Givens rotation, residual estimate
-// (the Gram-Schmidt coefficients in between are reduced by the passes that
-// consume them)
+// FIN 4: ||v_{j+1}|| -> Hessenberg column, Givens rotation, residual estimate,
+//        and the Gram row of v_{j+1}
+// (the Gram-Schmidt coefficients in between are reduced by the pass that
+// consumes them)
 // FIN 1 and FIN 4 publish the summary to host slot `slot` of the instance.
 // ---------------------------------------------------------------------------
 template <int FIN>
@@ -302,9 +291,9 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
     return;
   }
   static_assert(FIN == 1 || FIN == 4, "finishing kernels: cycle start and Givens step");
-  const int nq = FIN == 1 ? 2 : 1;
+  const int nq = FIN == 1 ? 2 : j + 2;
   const int nblk = FIN == 1 ? d.mv_grid : d.st_grid;
-  reduce_partials(d.partials, nblk, nq, out);
+  reduce_partials(FIN == 1 ? d.partials : d.partials2, nblk, nq, out);
   if (threadIdx.x != 0) return;
   GSummary& sm = st->sum;
   if (FIN == 1) {
@@ -318,6 +307,7 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
     }
     sm.beta = beta;
     st->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+    st->gram[0] = 1.0;
     st->g[0] = beta;
     for (int q = 1; q <= MMAX; ++q) st->g[q] = 0.0;
     sm.relres = sm.bnorm > 0.0 ? beta / sm.bnorm : 0.0;
@@ -351,7 +341,15 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
     st->g[j + 1] = -sn * gj;
     const double est = fabs(st->g[j + 1]);
     sm.est = sm.bnorm > 0.0 ? est / sm.bnorm : 0.0;
-    st->vscale[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    const double sn1 = hn > 0.0 ? 1.0 / hn : 0.0;
+    st->vscale[j + 1] = sn1;
+    double* grow = st->gram + (size_t)(j + 1) * NVMAX;
+    for (int q = 0; q <= j; ++q) {
+      const double gq = out[1 + q] * st->vscale[q] * sn1;
+      grow[q] = gq;
+      st->gram[(size_t)q * NVMAX + j + 1] = gq;
+    }
+    grow[j + 1] = 1.0;
     sm.k = j + 1;
     const bool brk = !(hn > 1e-300 * (sm.beta > 0.0 ? sm.beta : 1.0));
     sm.breakdown = brk ? 1 : 0;
@@ -548,11 +546,8 @@ hipError_t launch_arnoldi(const Launch& L, const Items& mv, const Items& stv, in
         hipLaunchKernelGGL((k_matvec<double, 2, NVB>), dim3(mv.n), dim3(MVT), 0, s, L.D,      \
                            mv.it, j, (const double*)nullptr, nullptr, nullptr, 0);            \
     }                                                                                         \
-    if (passes & 2) {                                                                         \
-      hipLaunchKernelGGL((k_cgs_pass1<NVB>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, j);    \
-    }                                                                                         \
     if (passes & 4) {                                                                         \
-      hipLaunchKernelGGL((k_cgs_pass2<NVB>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, j);    \
+      hipLaunchKernelGGL((k_cgs_update<NVB>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, j);   \
       if (finish)                                                                             \
         hipLaunchKernelGGL((k_finish<4>), dim3(L.ninst), dim3(FT), 0, s, L.D, j, stop_iter,  \
                            rtol, slot, seq);                                                  \
