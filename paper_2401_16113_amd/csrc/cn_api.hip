@@ -831,9 +831,11 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
     // speculative cycle end queued behind the iteration the host waits for
     bool spec = false, spec_taken = false;
     int spec_fin = 0, spec_res = 0;
+    int enq = 0;  // inner iterations queued in this cycle
     for (int j = 0; j < m_eff; ++j) {
       spec = false;
       seqs[j] = c.batched ? 0 : ++(*c.seqc);
+      enq = j + 1;
       if (c.graphs != nullptr) {
         CN_TRY(launch_iteration_graph(c, j, m_eff, rtol));
         seqs[j] = ++(*c.bseq);
@@ -868,9 +870,14 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
           // so a converged solve goes on without a host round trip
           if (!c.batched) {
             spec_fin = ++(*c.seqc);
-            HIP_TRY(launch_cycle_end(c.L, c.stv, x, x_zero ? 1 : 0, 3, spec_fin, c.s, true));
             spec_res = ++(*c.seqc);
-            HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, spec_res, c.s, 0, true));
+            if (x_zero) {
+              HIP_TRY(launch_cycle_end_zero(c.L, c.mv, enq, b, x, rtol, 3, spec_fin, 2, spec_res,
+                                            c.s, true));
+            } else {
+              HIP_TRY(launch_cycle_end(c.L, c.stv, x, 0, 3, spec_fin, c.s, true));
+              HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, spec_res, c.s, 0, true));
+            }
             spec = true;
           }
           CN_TRY(wait_slot(c.s, slots + (j & 1), seqs[j], &it));
@@ -884,15 +891,20 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
       }
     }
     // y from the triangular factors (cycle summaries -> slot 3), x += Z y,
-    // then the true residuals (-> slot 2), unless already queued
+    // then the true residuals (-> slot 2), unless already queued; a cycle
+    // from x = 0 does the update and the residual in one pass
     int seq_fin = spec_fin;
     if (spec_taken) {
       seq_res = spec_res;
     } else {
       seq_fin = c.batched ? 0 : ++(*c.seqc);
-      HIP_TRY(launch_cycle_end(c.L, c.stv, x, x_zero ? 1 : 0, 3, seq_fin, c.s));
       seq_res = c.batched ? 0 : ++(*c.seqc);
-      HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, seq_res, c.s, 0));
+      if (x_zero) {
+        HIP_TRY(launch_cycle_end_zero(c.L, c.mv, enq, b, x, rtol, 3, seq_fin, 2, seq_res, c.s));
+      } else {
+        HIP_TRY(launch_cycle_end(c.L, c.stv, x, 0, 3, seq_fin, c.s));
+        HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, seq_res, c.s, 0));
+      }
     }
     x_zero = false;
     if (c.batched) {

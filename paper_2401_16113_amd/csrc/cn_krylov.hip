@@ -175,9 +175,10 @@ __global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
       }
       y[offy + i] = yv;
       if (MODE == 2) {
+        // q >= nv re-reads v_{nv-1} (cache hits); those dots are never written
 #pragma unroll
         for (int q = 0; q < NV; ++q)
-          if (q < nv) acc[q] += d.V[(size_t)q * d.vstride + offy + i] * yv;
+          acc[q] += d.V[(size_t)(q < nv ? q : nv - 1) * d.vstride + offy + i] * yv;
       }
       pm = cm;
       pc = cc;
@@ -249,14 +250,18 @@ __global__ __launch_bounds__(KT) void k_cgs_update(const InstDesc* __restrict__ 
   const double* __restrict__ V = d.V;
   double* __restrict__ vout = d.V + (size_t)(j + 1) * d.vstride;
   const long long stride = (long long)d.st_grid * KT;
+  // vectors q >= nv re-read v_{nv-1} (cache hits) with coefficient 0 and their
+  // dots are never written: no branch between the loads
+  size_t vo[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) vo[q] = (size_t)(q < nv ? q : nv - 1) * d.vstride;
   for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.nin; e += stride) {
     double vq[NV];
     double wv = w[e];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      vq[q] = q < nv ? V[(size_t)q * d.vstride + e] : 0.0;
-      wv -= c[q] * vq[q];
-    }
+    for (int q = 0; q < NV; ++q) vq[q] = V[vo[q] + e];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) wv -= c[q] * vq[q];
     vout[e] = wv;
     acc[0] += wv * wv;
 #pragma unroll
@@ -353,7 +358,16 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
     sm.k = j + 1;
     const bool brk = !(hn > 1e-300 * (sm.beta > 0.0 ? sm.beta : 1.0));
     sm.breakdown = brk ? 1 : 0;
-    if (est <= rtol * sm.bnorm || brk || j + 1 >= stop_iter) sm.done = 1;
+    if (est <= rtol * sm.bnorm || brk || j + 1 >= stop_iter) {
+      sm.done = 1;
+      // the cycle stops here: y = R^{-1} g for the cycle end
+      for (int q = j; q >= 0; --q) {
+        double s = st->g[q];
+        for (int r = q + 1; r <= j; ++r) s -= st->H[r * (MMAX + 1) + q] * st->y[r];
+        const double dd = st->H[q * (MMAX + 1) + q];
+        st->y[q] = dd != 0.0 ? s / dd : 0.0;
+      }
+    }
     publish(host, sm, seq);
   }
 }
@@ -396,6 +410,146 @@ __global__ void k_cycle_finish(const InstDesc* __restrict__ D, int ninst, int sl
     const double dd = st->H[q * (MMAX + 1) + q];
     st->y[q] = dd != 0.0 ? s / dd : 0.0;
   }
+}
+
+// End of a cycle that started from x = 0, in one pass (y = R^{-1} g was formed
+// by the Givens kernel that stopped the cycle; block 0 publishes the cycle
+// summary to host slot `slot`): x = Z y,
+// and the true residual r = b - M x into V_0 with the partial sums of ||r||^2
+// and ||b||^2 for FIN 1.  The matvec's blocks (MVT columns x `rows` levels),
+// walked UR_R levels at a time: every thread forms x at its column for the
+// UR_R levels with all loads in flight, the values go through LDS so that
+// each residual sees its neighbours' x, and a fifth wavefront forms the two
+// halo columns of the block; the level above the block is formed again from
+// Z.  Nothing is read from the x being written, which is why a cycle that
+// started from a nonzero x takes k_update and the residual matvec instead.
+// guard: speculative launch, returns unless the cycle has stopped.
+constexpr int UR_T = MVT + 64;  // MVT columns + one wavefront for the 2 halo columns
+constexpr int UR_R = 8;         // time levels per step
+
+template <typename TZ, int KB>
+__global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __restrict__ D,
+                                                          const int2* __restrict__ items,
+                                                          const double* __restrict__ bo,
+                                                          double* __restrict__ xo, int guard,
+                                                          int slot, int seq) {
+  __shared__ double red[(UR_T / 64) * 2];
+  __shared__ double ys[KB];
+  __shared__ double xs[UR_R + 1][MVT + 2];  // level above the step + its UR_R levels
+  const int2 wi = work_item(items, blockIdx.x);
+  const InstDesc& d = D[wi.x];
+  const GState* st = d.st;
+  if (guard && !st->sum.done) return;
+  const int kk = st->sum.k;
+  if (threadIdx.x == 0 && wi.y == 0)
+    publish(d.host != nullptr ? d.host + slot : nullptr, st->sum, seq);
+  if (threadIdx.x < KB) ys[threadIdx.x] = (int)threadIdx.x < kk ? st->y[threadIdx.x] : 0.0;
+  __syncthreads();
+  const TZ* __restrict__ Z = (const TZ*)d.Z;
+  const long long zs = d.vstride;
+  const double* __restrict__ b = bo + d.off;
+  double* __restrict__ x = xo + d.off;
+  double* __restrict__ v0 = d.V;
+  const int nx = d.nx, ldx = d.ldx;
+  const int blk = wi.y;
+  const int cb = blk % d.mv_cols, rb = blk / d.mv_cols;
+  const int k0 = rb * d.rows, k1 = min(d.nt, k0 + d.rows);
+  const int t = threadIdx.x, i0 = cb * MVT;
+  // this thread's column and LDS slot: MVT own columns, then the halo columns
+  // i0 - 1 and i0 + MVT; the rest of the last wavefront idles
+  int col = -1, sl = -1;
+  if (t < MVT) {
+    col = i0 + t;
+    sl = t + 1;
+  } else if (t == MVT) {
+    col = i0 - 1;
+    sl = 0;
+  } else if (t == MVT + 1) {
+    col = i0 + MVT;
+    sl = MVT + 1;
+  }
+  const bool valid = col >= 0 && col < nx;
+  const bool own = t < MVT && col < nx;
+  double lo = 0.0, di = 0.0, up = 0.0;
+  if (own) {
+    lo = d.pl.lo[col];
+    di = d.pl.di[col];
+    up = d.pl.up[col];
+  }
+  // x at levels kc .. kc + nr - 1 of this thread's column, loads in flight together
+  // (vectors q >= kk re-read vector kk - 1 -- cache hits -- with weight 0, and
+  // levels past the block re-read its last level: no branch between the
+  // loads, so they are all in flight together)
+  auto form = [&](int kc, int nr, double (&xr)[UR_R]) {
+#pragma unroll
+    for (int r = 0; r < UR_R; ++r) xr[r] = 0.0;
+    if (!valid || kk == 0 || nr == 0) return;
+    constexpr int QG = KB < 8 ? KB : 8;  // vectors per batch of loads
+#pragma unroll 1
+    for (int q0 = 0; q0 < KB; q0 += QG) {
+      if (q0 < kk) {
+        TZ zv[QG][UR_R];
+#pragma unroll
+        for (int g = 0; g < QG; ++g) {
+          const int q = q0 + g;
+          const size_t zq = (size_t)(q < kk ? q : kk - 1) * zs + col;
+#pragma unroll
+          for (int r = 0; r < UR_R; ++r)
+            zv[g][r] = Z[zq + (size_t)(kc + (r < nr ? r : nr - 1)) * ldx];
+        }
+#pragma unroll
+        for (int g = 0; g < QG; ++g)
+#pragma unroll
+          for (int r = 0; r < UR_R; ++r) xr[r] += ys[q0 + g] * (double)zv[g][r];
+      }
+    }
+  };
+  if (sl >= 0) {
+    double xr[UR_R];
+    form(k0 - 1, k0 > 0 ? 1 : 0, xr);
+    xs[0][sl] = xr[0];
+  }
+  double acc[2] = {0.0, 0.0};
+  for (int kc = k0; kc < k1; kc += UR_R) {
+    const int nr = min(UR_R, k1 - kc);
+    double xr[UR_R], bv[UR_R];
+    form(kc, nr, xr);
+    if (own) {
+#pragma unroll
+      for (int r = 0; r < UR_R; ++r) bv[r] = b[(size_t)(kc + (r < nr ? r : nr - 1)) * nx + col];
+    }
+    if (sl >= 0) {
+#pragma unroll
+      for (int r = 0; r < UR_R; ++r)
+        if (r < nr) xs[1 + r][sl] = xr[r];
+    }
+    if (own) {
+#pragma unroll
+      for (int r = 0; r < UR_R; ++r)
+        if (r < nr) x[(size_t)(kc + r) * nx + col] = xr[r];
+    }
+    __syncthreads();
+    if (own) {
+#pragma unroll
+      for (int r = 0; r < UR_R; ++r) {
+        if (r < nr) {
+          const int k = kc + r;
+          const double pm = xs[r][sl - 1], pc = xs[r][sl], pp = xs[r][sl + 1];
+          const double cm = xs[r + 1][sl - 1], cc = xs[r + 1][sl], cp = xs[r + 1][sl + 1];
+          const double w = d.dw != nullptr ? d.dw[k] : 1.0;
+          const double ax = lo * (cm + pm) + di * (cc + pc) + up * (cp + pp);
+          const double rv = bv[r] - ((cc - pc) - 0.5 * w * ax);
+          v0[(size_t)k * ldx + col] = rv;
+          acc[0] += rv * rv;
+          acc[1] += bv[r] * bv[r];
+        }
+      }
+    }
+    __syncthreads();
+    // the last level of this step is the level above the next one
+    if (sl >= 0) xs[0][sl] = xs[nr][sl];
+  }
+  block_partials<2, UR_T>(acc, 2, red, d.partials, blk, d.mv_grid);
 }
 
 // x += sum_q y_q z_q (x = sum_q y_q z_q when the initial guess was zero)
@@ -572,6 +726,31 @@ hipError_t launch_cycle_end(const Launch& L, const Items& stv, double* x_base, i
   else
     hipLaunchKernelGGL((k_update<double>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, x_base,
                        x_zero);
+  return hipGetLastError();
+}
+
+hipError_t launch_cycle_end_zero(const Launch& L, const Items& mv, int kmax,
+                                 const double* b_base, double* x_base, double rtol, int slot_fin,
+                                 int seq_fin, int slot_res, int seq_res, hipStream_t s,
+                                 bool guard) {
+  const int bk = nv_bucket(kmax < 1 ? 1 : kmax);
+  switch (bk) {
+#define UR(KB)                                                                                \
+  case KB:                                                                                    \
+    if (L.zf)                                                                                 \
+      hipLaunchKernelGGL((k_update_residual<float, KB>), dim3(mv.n), dim3(UR_T), 0, s, L.D,   \
+                         mv.it, b_base, x_base, guard ? 1 : 0, slot_fin, seq_fin);            \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_update_residual<double, KB>), dim3(mv.n), dim3(UR_T), 0, s, L.D,  \
+                         mv.it, b_base, x_base, guard ? 1 : 0, slot_fin, seq_fin);            \
+    break;
+    UR(1) UR(2) UR(4) UR(8) UR(16) UR(32) UR(64)
+#undef UR
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL((k_finish<1>), dim3(L.ninst), dim3(FT), 0, s, L.D, 0, guard ? 1 : 0, rtol,
+                     slot_res, seq_res);
   return hipGetLastError();
 }
 
