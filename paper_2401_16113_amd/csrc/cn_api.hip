@@ -1245,6 +1245,13 @@ cn_status cn_batch_create(const cn_problem* probs, int32_t count, cn_batch** out
   for (int i = 0; i < count; ++i) {
     desc[i] = b->inst[i]->desc;
     desc[i].off = b->off[i];
+    // the batch has parallelism across instances: matvec blocks of at least
+    // MV_BATCH_ROWS time levels keep per-workgroup latency chains and partial
+    // sums few (a lone small instance keeps its finer blocks)
+    if (desc[i].rows < MV_BATCH_ROWS) {
+      desc[i].rows = std::min(MV_BATCH_ROWS, desc[i].nt);
+      desc[i].mv_grid = desc[i].mv_cols * ((desc[i].nt + desc[i].rows - 1) / desc[i].rows);
+    }
     append_items(desc[i], i, &pcs[b->inst[i]->pl.log2n], &k2, &mv, &stv);
     max_ns = std::max(max_ns, desc[i].pl.NS);
   }

@@ -143,6 +143,7 @@ constexpr int KGRID = 512;  // most workgroups of a streaming pass (= partial su
                             // per dot, which every consumer workgroup re-reduces)
 constexpr int MVT = 256;       // threads per workgroup of the matvec (one column each)
 constexpr int MV_KGRID = 2048; // target workgroups of the matvec (marching depth)
+constexpr int MV_BATCH_ROWS = 8;  // least time levels per matvec block in a batch
 int matvec_rows(int nx, int nt);
 int stream_grid(long long n);
 // y = M x for one instance (standalone matvec)

@@ -477,14 +477,14 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
     up = d.pl.up[col];
   }
   // x at levels kc .. kc + nr - 1 of this thread's column, loads in flight together
-  // (vectors q >= kk re-read vector kk - 1 -- cache hits -- with weight 0, and
-  // levels past the block re-read its last level: no branch between the
-  // loads, so they are all in flight together)
-  auto form = [&](int kc, int nr, double (&xr)[UR_R]) {
+  // (vectors q >= kk re-read vector kk - 1 -- cache hits -- with weight 0: no
+  // branch between the loads of a batch)
+  constexpr int QG = KB < 8 ? KB : 8;  // vectors per batch of loads
+  // x at UR_R levels from kc, every load of a batch in flight together
+  auto form = [&](int kc, double (&xr)[UR_R]) {
 #pragma unroll
     for (int r = 0; r < UR_R; ++r) xr[r] = 0.0;
-    if (!valid || kk == 0 || nr == 0) return;
-    constexpr int QG = KB < 8 ? KB : 8;  // vectors per batch of loads
+    if (!valid || kk == 0) return;
 #pragma unroll 1
     for (int q0 = 0; q0 < KB; q0 += QG) {
       if (q0 < kk) {
@@ -492,10 +492,9 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
 #pragma unroll
         for (int g = 0; g < QG; ++g) {
           const int q = q0 + g;
-          const size_t zq = (size_t)(q < kk ? q : kk - 1) * zs + col;
+          const size_t zq = (size_t)(q < kk ? q : kk - 1) * zs + col + (size_t)kc * ldx;
 #pragma unroll
-          for (int r = 0; r < UR_R; ++r)
-            zv[g][r] = Z[zq + (size_t)(kc + (r < nr ? r : nr - 1)) * ldx];
+          for (int r = 0; r < UR_R; ++r) zv[g][r] = Z[zq + (size_t)r * ldx];
         }
 #pragma unroll
         for (int g = 0; g < QG; ++g)
@@ -504,45 +503,71 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
       }
     }
   };
-  if (sl >= 0) {
-    double xr[UR_R];
-    form(k0 - 1, k0 > 0 ? 1 : 0, xr);
-    xs[0][sl] = xr[0];
-  }
+  // x at one level (short steps: the last of a block, or the blocks of one
+  // or a few levels that small instances have)
+  auto form1 = [&](int k) -> double {
+    double xv = 0.0;
+    if (!valid || kk == 0) return xv;
+    const size_t zk = (size_t)k * ldx + col;
+#pragma unroll 1
+    for (int q0 = 0; q0 < KB; q0 += QG) {
+      if (q0 < kk) {
+        TZ zv[QG];
+#pragma unroll
+        for (int g = 0; g < QG; ++g) {
+          const int q = q0 + g;
+          zv[g] = Z[(size_t)(q < kk ? q : kk - 1) * zs + zk];
+        }
+#pragma unroll
+        for (int g = 0; g < QG; ++g) xv += ys[q0 + g] * (double)zv[g];
+      }
+    }
+    return xv;
+  };
+  // residual at level k from the x of levels k-1 (LDS row ra) and k (row ra+1)
+  auto resid = [&](int k, int ra, double bv, double (&acc)[2]) {
+    const double pm = xs[ra][sl - 1], pc = xs[ra][sl], pp = xs[ra][sl + 1];
+    const double cm = xs[ra + 1][sl - 1], cc = xs[ra + 1][sl], cp = xs[ra + 1][sl + 1];
+    const double w = d.dw != nullptr ? d.dw[k] : 1.0;
+    const double ax = lo * (cm + pm) + di * (cc + pc) + up * (cp + pp);
+    const double rv = bv - ((cc - pc) - 0.5 * w * ax);
+    v0[(size_t)k * ldx + col] = rv;
+    acc[0] += rv * rv;
+    acc[1] += bv * bv;
+  };
+  if (sl >= 0) xs[0][sl] = k0 > 0 ? form1(k0 - 1) : 0.0;
   double acc[2] = {0.0, 0.0};
   for (int kc = k0; kc < k1; kc += UR_R) {
     const int nr = min(UR_R, k1 - kc);
-    double xr[UR_R], bv[UR_R];
-    form(kc, nr, xr);
-    if (own) {
+    if (nr == UR_R) {
+      double xr[UR_R], bv[UR_R];
+      form(kc, xr);
+      if (own) {
 #pragma unroll
-      for (int r = 0; r < UR_R; ++r) bv[r] = b[(size_t)(kc + (r < nr ? r : nr - 1)) * nx + col];
-    }
-    if (sl >= 0) {
+        for (int r = 0; r < UR_R; ++r) bv[r] = b[(size_t)(kc + r) * nx + col];
+      }
+      if (sl >= 0) {
 #pragma unroll
-      for (int r = 0; r < UR_R; ++r)
-        if (r < nr) xs[1 + r][sl] = xr[r];
-    }
-    if (own) {
+        for (int r = 0; r < UR_R; ++r) xs[1 + r][sl] = xr[r];
+      }
+      if (own) {
 #pragma unroll
-      for (int r = 0; r < UR_R; ++r)
-        if (r < nr) x[(size_t)(kc + r) * nx + col] = xr[r];
-    }
-    __syncthreads();
-    if (own) {
+        for (int r = 0; r < UR_R; ++r) x[(size_t)(kc + r) * nx + col] = xr[r];
+      }
+      __syncthreads();
+      if (own) {
 #pragma unroll
-      for (int r = 0; r < UR_R; ++r) {
-        if (r < nr) {
-          const int k = kc + r;
-          const double pm = xs[r][sl - 1], pc = xs[r][sl], pp = xs[r][sl + 1];
-          const double cm = xs[r + 1][sl - 1], cc = xs[r + 1][sl], cp = xs[r + 1][sl + 1];
-          const double w = d.dw != nullptr ? d.dw[k] : 1.0;
-          const double ax = lo * (cm + pm) + di * (cc + pc) + up * (cp + pp);
-          const double rv = bv[r] - ((cc - pc) - 0.5 * w * ax);
-          v0[(size_t)k * ldx + col] = rv;
-          acc[0] += rv * rv;
-          acc[1] += bv[r] * bv[r];
-        }
+        for (int r = 0; r < UR_R; ++r) resid(kc + r, r, bv[r], acc);
+      }
+    } else {
+      for (int r = 0; r < nr; ++r) {
+        const double xv = form1(kc + r);
+        if (sl >= 0) xs[1 + r][sl] = xv;
+        if (own) x[(size_t)(kc + r) * nx + col] = xv;
+      }
+      __syncthreads();
+      if (own) {
+        for (int r = 0; r < nr; ++r) resid(kc + r, r, b[(size_t)(kc + r) * nx + col], acc);
       }
     }
     __syncthreads();
