@@ -7,6 +7,16 @@
 
 namespace cn {
 
+// Global-memory pointers.  Pointers read from an instance descriptor are
+// generic to the compiler, which then emits flat memory instructions (they
+// also count against the LDS counter, so an LDS wait waits for memory too);
+// the hot loops take their vectors as global-qualified pointers instead.
+#define CN_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ CN_G T* gp(T* p) {
+  return (CN_G T*)p;
+}
+
 // ---------------------------------------------------------------------------
 // complex numbers
 // ---------------------------------------------------------------------------
@@ -14,6 +24,37 @@ template <typename R>
 struct Cx {
   R x, y;
 };
+
+// Complex values through global-qualified pointers, as one 8- or 16-byte access
+// (a struct copy through such a pointer would need an address-space-aware
+// assignment operator).
+typedef float cn_f2 __attribute__((ext_vector_type(2)));
+typedef double cn_d2 __attribute__((ext_vector_type(2)));
+template <typename R>
+struct CxVec;
+template <>
+struct CxVec<float> {
+  using T = cn_f2;
+};
+template <>
+struct CxVec<double> {
+  using T = cn_d2;
+};
+template <typename R>
+__device__ __forceinline__ Cx<R> gld(const CN_G Cx<R>* p) {
+  const typename CxVec<R>::T v = *(const CN_G typename CxVec<R>::T*)p;
+  return Cx<R>{v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void gst(CN_G Cx<R>* p, Cx<R> c) {
+  typename CxVec<R>::T v;
+  v.x = c.x;
+  v.y = c.y;
+  *(CN_G typename CxVec<R>::T*)p = v;
+}
+// generic pointers keep plain accesses
+template <typename R>
+__device__ __forceinline__ Cx<R> gld(const Cx<R>* p) { return *p; }
 
 template <typename R>
 __device__ __forceinline__ Cx<R> mk(R a, R b) { return Cx<R>{a, b}; }
@@ -274,11 +315,12 @@ __device__ __forceinline__ void fft_pass(Cx<R>* lds, const TW& tw, int tid) {
 template <typename R, int TWN, int T, int TWPT>
 struct TwStage {
   Cx<R> v[TWPT];
-  __device__ __forceinline__ void fetch(const Cx<R>* __restrict__ tw) {
+  template <typename PTR>
+  __device__ __forceinline__ void fetch(PTR tw) {
 #pragma unroll
     for (int q = 0; q < TWPT; ++q) {
       const int m = threadIdx.x + q * T;
-      if (TWN % T == 0 || m < TWN) v[q] = tw[m];
+      if (TWN % T == 0 || m < TWN) v[q] = gld(tw + m);
     }
   }
   __device__ __forceinline__ void store(Cx<R>* ltw) {

@@ -47,7 +47,7 @@ __device__ __forceinline__ void block_partials(const double (&acc)[NV], int nv, 
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < THREADS / 64; ++w) s += red[w * NV + tid];
-    partials[(size_t)tid * nblk + blk] = s;
+    gp(partials)[(size_t)tid * nblk + blk] = s;
   }
 }
 
@@ -62,7 +62,7 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ parti
                                                 int nv, double* out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int q = wv; q < nv; q += THREADS / 64) {
-    const double* p = partials + (size_t)q * nblk;
+    const CN_G double* p = gp(partials + (size_t)q * nblk);
     double s = 0.0;
     for (int base = 0; base < nblk; base += 64 * FCHUNK) {
       double v[FCHUNK];
@@ -105,6 +105,65 @@ __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int 
 //         the first CGS2 projection)
 // Each thread marches down the time levels of one spatial column.
 // ---------------------------------------------------------------------------
+// One thread's column of the matvec, levels k0 .. k1-1 (see k_matvec).  The
+// vectors are parameters so that __restrict__ holds (y is never one of the
+// vectors read), which lets the loads of later levels be issued before the
+// store of the current one.
+template <typename TX, int MODE, int NV, int NA>
+__device__ __forceinline__ void matvec_column(const CN_G TX* __restrict__ x,
+                                              const CN_G double* __restrict__ b,
+                                              CN_G double* __restrict__ y,
+                                              const CN_G double* __restrict__ V,
+                                              const CN_G double* __restrict__ plo,
+                                              const CN_G double* __restrict__ pdi,
+                                              const CN_G double* __restrict__ pup,
+                                              const CN_G double* __restrict__ dw, long long vstride,
+                                              int px, int py, int nx, int nv, int i, int k0,
+                                              int k1, double (&acc)[NA]) {
+  const double lo = plo[i], di = pdi[i], up = pup[i];
+  const bool hl = i > 0, hr = i < nx - 1;
+  double pm = 0.0, pc = 0.0, pp = 0.0;  // previous level at i-1, i, i+1
+  if (k0 > 0 && x != nullptr) {
+    const CN_G TX* xr = x + (size_t)(k0 - 1) * px;
+    pc = (double)xr[i];
+    if (hl) pm = (double)xr[i - 1];
+    if (hr) pp = (double)xr[i + 1];
+  }
+  size_t vo[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) vo[q] = (size_t)(q < nv ? q : nv - 1) * vstride;
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
+    double cm = 0.0, cc = 0.0, cp = 0.0;
+    const size_t off = (size_t)k * px, offy = (size_t)k * py;
+    if (x != nullptr) {
+      cc = (double)x[off + i];
+      if (hl) cm = (double)x[off + i - 1];
+      if (hr) cp = (double)x[off + i + 1];
+    }
+    const double w = dw != nullptr ? dw[k] : 1.0;
+    // (M x)^k = (x^k - x^{k-1}) - (w/2) A~ (x^k + x^{k-1})
+    const double sm = cm + pm, s0 = cc + pc, sp = cp + pp;
+    const double ax = lo * sm + di * s0 + up * sp;
+    double yv = (cc - pc) - 0.5 * w * ax;
+    if (MODE == 1) {
+      const double bv = b[off + i];
+      yv = bv - yv;
+      acc[0] += yv * yv;
+      acc[1] += bv * bv;
+    }
+    y[offy + i] = yv;
+    if (MODE == 2) {
+      // q >= nv re-reads v_{nv-1} (cache hits); those dots are never written
+#pragma unroll
+      for (int q = 0; q < NV; ++q) acc[q] += V[vo[q] + offy + i] * yv;
+    }
+    pm = cm;
+    pc = cc;
+    pp = cp;
+  }
+}
+
 template <typename TX, int MODE, int NV>
 __global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
                                                const int2* __restrict__ items, int j,
@@ -144,47 +203,10 @@ __global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
   double acc[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = 0.0;
-  if (i < nx) {
-    const double lo = d.pl.lo[i], di = d.pl.di[i], up = d.pl.up[i];
-    const bool hl = i > 0, hr = i < nx - 1;
-    double pm = 0.0, pc = 0.0, pp = 0.0;  // previous level at i-1, i, i+1
-    if (k0 > 0 && x != nullptr) {
-      const TX* xr = x + (size_t)(k0 - 1) * px;
-      pc = (double)xr[i];
-      if (hl) pm = (double)xr[i - 1];
-      if (hr) pp = (double)xr[i + 1];
-    }
-    for (int k = k0; k < k1; ++k) {
-      double cm = 0.0, cc = 0.0, cp = 0.0;
-      const size_t off = (size_t)k * px, offy = (size_t)k * py;
-      if (x != nullptr) {
-        cc = (double)x[off + i];
-        if (hl) cm = (double)x[off + i - 1];
-        if (hr) cp = (double)x[off + i + 1];
-      }
-      const double w = d.dw != nullptr ? d.dw[k] : 1.0;
-      // (M x)^k = (x^k - x^{k-1}) - (w/2) A~ (x^k + x^{k-1})
-      const double sm = cm + pm, s0 = cc + pc, sp = cp + pp;
-      const double ax = lo * sm + di * s0 + up * sp;
-      double yv = (cc - pc) - 0.5 * w * ax;
-      if (MODE == 1) {
-        const double bv = b[off + i];
-        yv = bv - yv;
-        acc[0] += yv * yv;
-        acc[1] += bv * bv;
-      }
-      y[offy + i] = yv;
-      if (MODE == 2) {
-        // q >= nv re-reads v_{nv-1} (cache hits); those dots are never written
-#pragma unroll
-        for (int q = 0; q < NV; ++q)
-          acc[q] += d.V[(size_t)(q < nv ? q : nv - 1) * d.vstride + offy + i] * yv;
-      }
-      pm = cm;
-      pc = cc;
-      pp = cp;
-    }
-  }
+  if (i < nx)
+    matvec_column<TX, MODE, NV, NA>(gp(x), gp(b), gp(y), gp(d.V), gp(d.pl.lo), gp(d.pl.di),
+                                    gp(d.pl.up), gp(d.dw), d.vstride, px, py, nx, nv, i, k0, k1,
+                                    acc);
   if (MODE == 0) return;
   block_partials<NA, MVT>(acc, MODE == 1 ? 2 : nv, red, d.partials, blk, d.mv_grid);
 }
@@ -228,6 +250,37 @@ __device__ __forceinline__ void update_coeffs(const double* __restrict__ partial
   __syncthreads();
 }
 
+// The update's sweep: v_{j+1} = w - V c over elements e0, e0 + stride, ...,
+// with ||v_{j+1}||^2 into acc[0] and <v_q, v_{j+1}> into acc[1 + q].  The
+// pointers are parameters so that __restrict__ holds (v_{j+1} is the basis
+// buffer's next vector, disjoint from the vectors read): loads of the next
+// elements may then be issued before the current store.  Vectors q >= nv
+// re-read v_{nv-1} (cache hits) with coefficient 0; their dots are never
+// written: no branch between the loads.
+template <int NV>
+__device__ __forceinline__ void update_sweep(const CN_G double* __restrict__ w,
+                                             const CN_G double* __restrict__ V,
+                                             CN_G double* __restrict__ vout, long long vstride,
+                                             int nv, long long n, long long e0, long long stride,
+                                             const double (&c)[NV], double (&acc)[NV + 1]) {
+  size_t vo[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) vo[q] = (size_t)(q < nv ? q : nv - 1) * vstride;
+#pragma unroll 2
+  for (long long e = e0; e < n; e += stride) {
+    double vq[NV];
+    double wv = w[e];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) vq[q] = V[vo[q] + e];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) wv -= c[q] * vq[q];
+    vout[e] = wv;
+    acc[0] += wv * wv;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[1 + q] += vq[q] * wv;
+  }
+}
+
 // partials2 rows: 0 = ||v_{j+1}||^2, 1 + q = <v_q, v_{j+1}> (q <= j)
 template <int NV>
 __global__ __launch_bounds__(KT) void k_cgs_update(const InstDesc* __restrict__ D,
@@ -246,27 +299,8 @@ __global__ __launch_bounds__(KT) void k_cgs_update(const InstDesc* __restrict__ 
   for (int q = 0; q < NV; ++q) c[q] = q < nv ? sc[q] : 0.0;
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = 0.0;
-  const double* __restrict__ w = d.w;
-  const double* __restrict__ V = d.V;
-  double* __restrict__ vout = d.V + (size_t)(j + 1) * d.vstride;
-  const long long stride = (long long)d.st_grid * KT;
-  // vectors q >= nv re-read v_{nv-1} (cache hits) with coefficient 0 and their
-  // dots are never written: no branch between the loads
-  size_t vo[NV];
-#pragma unroll
-  for (int q = 0; q < NV; ++q) vo[q] = (size_t)(q < nv ? q : nv - 1) * d.vstride;
-  for (long long e = (long long)wi.y * KT + threadIdx.x; e < d.nin; e += stride) {
-    double vq[NV];
-    double wv = w[e];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) vq[q] = V[vo[q] + e];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) wv -= c[q] * vq[q];
-    vout[e] = wv;
-    acc[0] += wv * wv;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[1 + q] += vq[q] * wv;
-  }
+  update_sweep<NV>(gp(d.w), gp(d.V), gp(d.V + (size_t)(j + 1) * d.vstride), d.vstride, nv, d.nin,
+                   (long long)wi.y * KT + threadIdx.x, (long long)d.st_grid * KT, c, acc);
   block_partials<NA>(acc, nv + 1, red, d.partials2, wi.y, d.st_grid);
 }
 
@@ -445,11 +479,11 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
     publish(d.host != nullptr ? d.host + slot : nullptr, st->sum, seq);
   if (threadIdx.x < KB) ys[threadIdx.x] = (int)threadIdx.x < kk ? st->y[threadIdx.x] : 0.0;
   __syncthreads();
-  const TZ* __restrict__ Z = (const TZ*)d.Z;
+  const CN_G TZ* __restrict__ Z = gp((const TZ*)d.Z);
   const long long zs = d.vstride;
-  const double* __restrict__ b = bo + d.off;
-  double* __restrict__ x = xo + d.off;
-  double* __restrict__ v0 = d.V;
+  const CN_G double* __restrict__ b = gp(bo + d.off);
+  CN_G double* __restrict__ x = gp(xo + d.off);
+  CN_G double* __restrict__ v0 = gp(d.V);
   const int nx = d.nx, ldx = d.ldx;
   const int blk = wi.y;
   const int cb = blk % d.mv_cols, rb = blk / d.mv_cols;
@@ -472,9 +506,9 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
   const bool own = t < MVT && col < nx;
   double lo = 0.0, di = 0.0, up = 0.0;
   if (own) {
-    lo = d.pl.lo[col];
-    di = d.pl.di[col];
-    up = d.pl.up[col];
+    lo = gp(d.pl.lo)[col];
+    di = gp(d.pl.di)[col];
+    up = gp(d.pl.up)[col];
   }
   // x at levels kc .. kc + nr - 1 of this thread's column, loads in flight together
   // (vectors q >= kk re-read vector kk - 1 -- cache hits -- with weight 0: no
@@ -528,7 +562,7 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
   auto resid = [&](int k, int ra, double bv, double (&acc)[2]) {
     const double pm = xs[ra][sl - 1], pc = xs[ra][sl], pp = xs[ra][sl + 1];
     const double cm = xs[ra + 1][sl - 1], cc = xs[ra + 1][sl], cp = xs[ra + 1][sl + 1];
-    const double w = d.dw != nullptr ? d.dw[k] : 1.0;
+    const double w = d.dw != nullptr ? gp(d.dw)[k] : 1.0;
     const double ax = lo * (cm + pm) + di * (cc + pc) + up * (cp + pp);
     const double rv = bv - ((cc - pc) - 0.5 * w * ax);
     v0[(size_t)k * ldx + col] = rv;

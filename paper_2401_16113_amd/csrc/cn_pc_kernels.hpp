@@ -29,12 +29,12 @@ namespace cn {
 // ---------------------------------------------------------------------------
 template <typename R, int LOG2N, int BB, int TT>
 __device__ __forceinline__ void pc_forward_tile(
-    int p, const double* __restrict__ v, const double* scp, const int* stop,
-    const double* __restrict__ lo,
-    const double* __restrict__ di, const double* __restrict__ up,
-    const double* __restrict__ wfw, const Cx<R>* __restrict__ tw,
-    const Cx<double>* __restrict__ mu, const Cx<double>* __restrict__ il2,
-    Cx<R>* __restrict__ spec, Cx<R>* __restrict__ iface, int nx, int vp, int P) {
+    int p, const CN_G double* __restrict__ v, const double* scp, const int* stop,
+    const CN_G double* __restrict__ lo,
+    const CN_G double* __restrict__ di, const CN_G double* __restrict__ up,
+    const CN_G double* __restrict__ wfw, const Cx<R>* __restrict__ tw,
+    const CN_G Cx<double>* __restrict__ mu, const CN_G Cx<double>* __restrict__ il2,
+    CN_G Cx<R>* __restrict__ spec, CN_G Cx<R>* __restrict__ iface, int nx, int vp, int P) {
   using Cfg = PcCfg<R, LOG2N, BB, TT>;
   constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
   __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
@@ -61,7 +61,7 @@ __device__ __forceinline__ void pc_forward_tile(
     if (stop != nullptr && *stop) return;
     const double sc = scp != nullptr ? *scp : 1.0;
     TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
-    if constexpr (Cfg::TWL) tws.fetch(tw);
+    if constexpr (Cfg::TWL) tws.fetch(gp(tw));
     if (tid < 3 * B) {
       const int b = tid / 3, c = tid % 3;
       R val = R(0);
@@ -84,7 +84,7 @@ __device__ __forceinline__ void pc_forward_tile(
   // step (b), tile-local part
   const bool has_sep = p < P - 1;
   const int nb = has_sep ? B - 1 : ncols;
-  Cx<R>* ifc = iface + (size_t)p * 3;
+  CN_G Cx<R>* ifc = iface + (size_t)p * 3;
   for (int t = tid; t < Cfg::TASKS; t += T) {
     if (t == 0) {
       // j = 0 and j = N/2: real modes, real shifts
@@ -109,14 +109,14 @@ __device__ __forceinline__ void pc_forward_tile(
           if (b == nb - 1) ylast = d[b];
 #pragma unroll
         for (int c = 0; c < NSEQ; ++c) lds[lidx<N>(c, j)] = Cx<R>{d[2 * c], d[2 * c + 1]};
-        Cx<R>* f = ifc + (size_t)j * P * 3;
-        f[0] = Cx<R>{has_sep ? sepv : R(0), R(0)};
-        f[1] = Cx<R>{ylast, R(0)};
-        f[2] = Cx<R>{d[0], R(0)};
+        CN_G Cx<R>* f = ifc + (size_t)j * P * 3;
+        gst(f, Cx<R>{has_sep ? sepv : R(0), R(0)});
+        gst(f + 1, Cx<R>{ylast, R(0)});
+        gst(f + 2, Cx<R>{d[0], R(0)});
       }
     } else {
       const int j = t;
-      const Cx<double> md = mu[j], sd = il2[j];
+      const Cx<double> md = gld(mu + j), sd = gld(il2 + j);
       const Cx<R> m{(R)md.x, (R)md.y}, s2{(R)sd.x, (R)sd.y};
       Cx<R> d[B];
 #pragma unroll
@@ -139,20 +139,20 @@ __device__ __forceinline__ void pc_forward_tile(
         lds[lidx<N>(c, j)] = d[2 * c];
         lds[lidx<N>(c, N - j)] = d[2 * c + 1];
       }
-      Cx<R>* f = ifc + (size_t)j * P * 3;
-      f[0] = has_sep ? sepv : Cx<R>{R(0), R(0)};
-      f[1] = ylast;
-      f[2] = d[0];
+      CN_G Cx<R>* f = ifc + (size_t)j * P * 3;
+      gst(f, has_sep ? sepv : Cx<R>{R(0), R(0)});
+      gst(f + 1, ylast);
+      gst(f + 2, d[0]);
     }
   }
   __syncthreads();
-  Cx<R>* img = spec + (size_t)p * NSEQ * N;
+  CN_G Cx<R>* img = spec + (size_t)p * NSEQ * N;
   {
     constexpr int SPT = (NSEQ * N + T - 1) / T;
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int e = tid + q * T;
-      if ((NSEQ * N) % T == 0 || e < NSEQ * N) img[e] = lds[lidx<N>(e / N, e % N)];
+      if ((NSEQ * N) % T == 0 || e < NSEQ * N) gst(img + e, lds[lidx<N>(e / N, e % N)]);
     }
   }
 }
@@ -173,11 +173,11 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
   const bool in_solve = v_ovr == nullptr;
   const double* v = in_solve ? d.V + (size_t)jv * d.vstride : v_ovr;
   const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
-  pc_forward_tile<R, LOG2N, BB, TT>(wi.y, v, in_solve ? d.st->vscale + jv : nullptr,
-                                    in_solve ? &d.st->sum.done : nullptr, pl.lo, pl.di, pl.up,
-                                    pl.wfw, tw, pl.mu, pl.il2,
-                                    (Cx<R>*)pl.spec, (Cx<R>*)pl.iface, pl.nx,
-                                    pitch > 0 ? pitch : d.ldx, pl.P);
+  pc_forward_tile<R, LOG2N, BB, TT>(wi.y, gp(v), in_solve ? d.st->vscale + jv : nullptr,
+                                    in_solve ? &d.st->sum.done : nullptr, gp(pl.lo), gp(pl.di),
+                                    gp(pl.up), gp(pl.wfw), tw, gp((const Cx<double>*)pl.mu),
+                                    gp((const Cx<double>*)pl.il2), gp((Cx<R>*)pl.spec),
+                                    gp((Cx<R>*)pl.iface), pl.nx, pitch > 0 ? pitch : d.ldx, pl.P);
 }
 
 // ---------------------------------------------------------------------------
@@ -185,11 +185,12 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
 // ---------------------------------------------------------------------------
 template <typename R, int LOG2N, int BB, int TT, typename TZ>
 __device__ __forceinline__ void pc_inverse_tile(
-    int p, const int* stop, const Cx<R>* __restrict__ spec, const Cx<R>* __restrict__ sep,
-    const double* __restrict__ lo, const double* __restrict__ di,
-    const double* __restrict__ up, const double* __restrict__ winv,
-    const Cx<R>* __restrict__ tw, const Cx<double>* __restrict__ mu, TZ* __restrict__ z, int nx,
-    int zp, int P, int NS) {
+    int p, const int* stop, const CN_G Cx<R>* __restrict__ spec,
+    const CN_G Cx<R>* __restrict__ sep, const CN_G double* __restrict__ lo,
+    const CN_G double* __restrict__ di, const CN_G double* __restrict__ up,
+    const CN_G double* __restrict__ winv, const Cx<R>* __restrict__ tw,
+    const CN_G Cx<double>* __restrict__ mu, CN_G TZ* __restrict__ z, int nx, int zp, int P,
+    int NS) {
   using Cfg = PcCfg<R, LOG2N, BB, TT>;
   constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
   __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
@@ -198,18 +199,18 @@ __device__ __forceinline__ void pc_inverse_tile(
   const int tid = threadIdx.x;
   const int i0 = p * B;
   const int ncols = min(B, nx - i0);
-  const Cx<R>* img = spec + (size_t)p * NSEQ * N;
+  const CN_G Cx<R>* img = spec + (size_t)p * NSEQ * N;
   {
     constexpr int SPT = (NSEQ * N + T - 1) / T;
     Cx<R> iv[SPT];
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int e = tid + q * T;
-      if ((NSEQ * N) % T == 0 || e < NSEQ * N) iv[q] = img[e];
+      if ((NSEQ * N) % T == 0 || e < NSEQ * N) iv[q] = gld(img + e);
     }
     if (stop != nullptr && *stop) return;  // read with the image in flight
     TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
-    if constexpr (Cfg::TWL) tws.fetch(tw);
+    if constexpr (Cfg::TWL) tws.fetch(gp(tw));
     if (tid < 3 * B) {
       const int b = tid / 3, c = tid % 3;
       R val = R(0);
@@ -256,11 +257,11 @@ __device__ __forceinline__ void pc_inverse_tile(
       }
     } else {
       const int j = t;
-      const Cx<double> md = mu[j];
+      const Cx<double> md = gld(mu + j);
       const Cx<R> m{(R)md.x, (R)md.y};
       const Cx<R> zero{R(0), R(0)};
-      const Cx<R> sl = has_left ? sep[(size_t)j * NS + p - 1] : zero;
-      const Cx<R> sr = has_sep ? sep[(size_t)j * NS + p] : zero;
+      const Cx<R> sl = has_left ? gld(sep + (size_t)j * NS + p - 1) : zero;
+      const Cx<R> sr = has_sep ? gld(sep + (size_t)j * NS + p) : zero;
       Cx<R> d[B];
 #pragma unroll
       for (int b = 0; b < B; ++b) d[b] = zero;
@@ -313,8 +314,9 @@ __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ 
   TZ* z = z_ovr != nullptr ? z_ovr : (TZ*)d.Z + (size_t)jv * d.vstride;
   const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
   pc_inverse_tile<R, LOG2N, BB, TT, TZ>(wi.y, z_ovr == nullptr ? &d.st->sum.done : nullptr,
-                                        (const Cx<R>*)pl.spec, (const Cx<R>*)pl.sep, pl.lo,
-                                        pl.di, pl.up, pl.winv, tw, pl.mu, z, pl.nx,
+                                        gp((const Cx<R>*)pl.spec), gp((const Cx<R>*)pl.sep),
+                                        gp(pl.lo), gp(pl.di), gp(pl.up), gp(pl.winv), tw,
+                                        gp((const Cx<double>*)pl.mu), gp(z), pl.nx,
                                         pitch > 0 ? pitch : d.ldx, pl.P, pl.NS);
 }
 
@@ -355,7 +357,7 @@ __device__ __forceinline__ bool fwd_load(int p, const double* __restrict__ v, co
   if (stop != nullptr && *stop) return false;
   const double sc = scp != nullptr ? *scp : 1.0;
   TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
-  if constexpr (Cfg::TWL) tws.fetch(tw);
+  if constexpr (Cfg::TWL) tws.fetch(gp(tw));
   if (tid < 3 * B) {
     const int b = tid / 3, c = tid % 3;
     R val = R(0);
