@@ -45,7 +45,9 @@ RTOL = 1e-8
 M = 30
 # sources whose change invalidates stored hardware-counter traffic figures
 KERNEL_SOURCES = ["paper_2401_16113_amd/csrc/cn_device.hpp",
+                  "paper_2401_16113_amd/csrc/cn_internal.hpp",
                   "paper_2401_16113_amd/csrc/cn_pc_kernels.hpp",
+                  "paper_2401_16113_amd/csrc/cn_pc_reduced.hpp",
                   "paper_2401_16113_amd/csrc/cn_pc.hip",
                   "paper_2401_16113_amd/csrc/cn_krylov.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_localvol_4095x1024_fp32pc.txt")
