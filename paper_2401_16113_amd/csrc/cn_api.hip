@@ -1144,9 +1144,9 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   bytes[0] = n * 8 + nimg * rsz + (double)pl.F * pl.P * 6 * rsz;
   bytes[1] = nsep * (6 * rsz + 6 * rsz + 2 * rsz);  // interface values, factor records, S
   bytes[2] = nimg * rsz + (double)pl.F * pl.P * 4 * rsz + n * zes;
-  bytes[3] = n * zes + n * 8 + (double)(j + 1) * n * 8;
+  bytes[3] = n * zes + (double)(j + 1) * n * 8;  // z_j and the basis (w is not stored)
   bytes[4] = (double)(j + 2) * n * 8;
-  bytes[5] = (double)(j + 3) * n * 8;
+  bytes[5] = n * zes + (double)(j + 2) * n * 8;  // z_j, the basis, v_{j+1}
   // the single-launch apply: no tile image through memory
   bytes[6] = h->fused ? n * 8 + (double)pl.F * pl.P * 10 * rsz + nsep * 14 * rsz + n * zes : 0.0;
   ms[6] = 0.0;

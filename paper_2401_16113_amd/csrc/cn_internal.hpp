@@ -141,8 +141,8 @@ bool pc_fused_ok(int prec, int log2n, int cand, int P, int NS);
 constexpr int KT = 512;     // threads per workgroup of the streaming Krylov kernels
 constexpr int KGRID = 512;  // most workgroups of a streaming pass (= partial sums
                             // per dot, which every consumer workgroup re-reduces)
-constexpr int MVT = 256;       // threads per workgroup of the matvec (one column each)
-constexpr int MV_KGRID = 2048; // target workgroups of the matvec (marching depth)
+constexpr int MVT = 512;       // threads per workgroup of the matvec (one column each)
+constexpr int MV_KGRID = 512;  // target workgroups of the matvec (marching depth)
 constexpr int MV_BATCH_ROWS = 8;  // least time levels per matvec block in a batch
 int matvec_rows(int nx, int nt);
 int stream_grid(long long n);

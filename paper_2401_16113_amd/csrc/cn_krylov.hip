@@ -1,7 +1,8 @@
 // Krylov kernels of the right-preconditioned GMRES(m) solve on gfx950:
 //   * the all-at-once CN matvec (block form of Sec. 3.2), plain, as a
 //     residual b - M x, and fused with the first Gram-Schmidt dot pass;
-//   * the CGS2 update pass: both projections in one update of w, the second
+//   * the CGS2 update pass: both projections in one update of w (formed
+//     again from z_j rather than stored by the matvec), the second
 //     one's coefficients from the Gram matrix of the basis (kept up to date
 //     by this pass itself: while it writes v_{j+1} it also forms the dots of
 //     v_{j+1} with the basis), so the second projection needs no pass over
@@ -101,8 +102,9 @@ __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int 
 //         r = b - M x into V_0 with ||r||^2, ||b||^2 (MODE 1: x = xo + off,
 //         unread when bit 0 of x_zero is set; bit 1: only for instances whose
 //         cycle has stopped; b = bo + off),
-//         w = M z_j with dots against V_0..V_j (MODE 2, the coefficients of
-//         the first CGS2 projection)
+//         the dots of w = M z_j with V_0..V_j (MODE 2, the coefficients of the
+//         first CGS2 projection; w itself is not stored: the update forms it
+//         again from z_j, which moves fewer bytes than storing and re-reading it)
 // Each thread marches down the time levels of one spatial column.
 // ---------------------------------------------------------------------------
 // One thread's column of the matvec, levels k0 .. k1-1 (see k_matvec).  The
@@ -132,7 +134,8 @@ __device__ __forceinline__ void matvec_column(const CN_G TX* __restrict__ x,
   size_t vo[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) vo[q] = (size_t)(q < nv ? q : nv - 1) * vstride;
-#pragma unroll 4
+  constexpr int UNR = NV <= 4 ? 4 : (NV <= 8 ? 2 : 1);
+#pragma unroll UNR
   for (int k = k0; k < k1; ++k) {
     double cm = 0.0, cc = 0.0, cp = 0.0;
     const size_t off = (size_t)k * px, offy = (size_t)k * py;
@@ -152,11 +155,12 @@ __device__ __forceinline__ void matvec_column(const CN_G TX* __restrict__ x,
       acc[0] += yv * yv;
       acc[1] += bv * bv;
     }
-    y[offy + i] = yv;
     if (MODE == 2) {
       // q >= nv re-reads v_{nv-1} (cache hits); those dots are never written
 #pragma unroll
       for (int q = 0; q < NV; ++q) acc[q] += V[vo[q] + offy + i] * yv;
+    } else {
+      y[offy + i] = yv;
     }
     pm = cm;
     pc = cc;
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
     y = d.V;
   } else {
     x = (const TX*)d.Z + (size_t)j * d.vstride;
-    y = d.w;
+    y = nullptr;
   }
   const int nv = j + 1;
   const int nx = d.nx;
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
 __device__ __forceinline__ void update_coeffs(const double* __restrict__ partials, int nblk,
                                               int nv, GState* st, bool keep, double* sh,
                                               double* sc) {
-  reduce_partials<KT>(partials, nblk, nv, sh);
+  reduce_partials<MVT>(partials, nblk, nv, sh);
   if (threadIdx.x < nv) sh[threadIdx.x] *= st->vscale[threadIdx.x];
   __syncthreads();
   if (threadIdx.x < nv) {
@@ -250,43 +254,78 @@ __device__ __forceinline__ void update_coeffs(const double* __restrict__ partial
   __syncthreads();
 }
 
-// The update's sweep: v_{j+1} = w - V c over elements e0, e0 + stride, ...,
-// with ||v_{j+1}||^2 into acc[0] and <v_q, v_{j+1}> into acc[1 + q].  The
-// pointers are parameters so that __restrict__ holds (v_{j+1} is the basis
-// buffer's next vector, disjoint from the vectors read): loads of the next
-// elements may then be issued before the current store.  Vectors q >= nv
-// re-read v_{nv-1} (cache hits) with coefficient 0; their dots are never
-// written: no branch between the loads.
-template <int NV>
-__device__ __forceinline__ void update_sweep(const CN_G double* __restrict__ w,
-                                             const CN_G double* __restrict__ V,
-                                             CN_G double* __restrict__ vout, long long vstride,
-                                             int nv, long long n, long long e0, long long stride,
-                                             const double (&c)[NV], double (&acc)[NV + 1]) {
-  size_t vo[NV];
+// The update's column: at levels k0 .. k1-1 of column i, w = (M z_j) formed
+// again from z_j as the matvec forms it (same expression, same bits),
+// v_{j+1} = w - V c, with ||v_{j+1}||^2 into acc[0] and <v_q, v_{j+1}> into
+// acc[1 + q].  The vectors are parameters so that __restrict__ holds
+// (v_{j+1} is the basis buffer's next vector, disjoint from the vectors read).
+// Vectors q >= nv re-read v_{nv-1} (cache hits) with coefficient 0; their
+// dots are never written: no branch between the loads.
+template <typename TX, int NV>
+__device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
+                                              const CN_G double* __restrict__ V,
+                                              CN_G double* __restrict__ vout,
+                                              const CN_G double* __restrict__ plo,
+                                              const CN_G double* __restrict__ pdi,
+                                              const CN_G double* __restrict__ pup,
+                                              const CN_G double* __restrict__ dw,
+                                              long long vstride, int ldx, int nx, int nv, int i,
+                                              int k0, int k1, const double* c,
+                                              double (&acc)[NV + 1]) {
+  const double lo = plo[i], di = pdi[i], up = pup[i];
+  const bool hl = i > 0, hr = i < nx - 1;
+  double pm = 0.0, pc = 0.0, pp = 0.0;  // z at the previous level, i-1, i, i+1
+  if (k0 > 0) {
+    const CN_G TX* zr = z + (size_t)(k0 - 1) * ldx;
+    pc = (double)zr[i];
+    if (hl) pm = (double)zr[i - 1];
+    if (hr) pp = (double)zr[i + 1];
+  }
+  // basis offsets in registers for short bases, formed per load for long ones
+  constexpr int NVO = NV <= 8 ? NV : 1;
+  size_t vo[NVO];
 #pragma unroll
-  for (int q = 0; q < NV; ++q) vo[q] = (size_t)(q < nv ? q : nv - 1) * vstride;
-#pragma unroll 2
-  for (long long e = e0; e < n; e += stride) {
+  for (int q = 0; q < NVO; ++q) vo[q] = (size_t)(q < nv ? q : nv - 1) * vstride;
+  auto voff = [&](int q) -> size_t {
+    if constexpr (NV <= 8) return vo[q];
+    else return (size_t)(q < nv ? q : nv - 1) * vstride;
+  };
+  // levels in flight together: fewer for long bases (registers)
+  constexpr int UNR = NV <= 4 ? 4 : (NV <= 8 ? 2 : 1);
+#pragma unroll UNR
+  for (int k = k0; k < k1; ++k) {
+    const size_t off = (size_t)k * ldx;
+    const double cc = (double)z[off + i];
+    const double cm = hl ? (double)z[off + i - 1] : 0.0;
+    const double cp = hr ? (double)z[off + i + 1] : 0.0;
     double vq[NV];
-    double wv = w[e];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) vq[q] = V[vo[q] + e];
+    for (int q = 0; q < NV; ++q) vq[q] = V[voff(q) + off + i];
+    const double w = dw != nullptr ? dw[k] : 1.0;
+    // (M z)^k = (z^k - z^{k-1}) - (w/2) A~ (z^k + z^{k-1})
+    const double sm = cm + pm, s0 = cc + pc, sp = cp + pp;
+    const double ax = lo * sm + di * s0 + up * sp;
+    double v = (cc - pc) - 0.5 * w * ax;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) wv -= c[q] * vq[q];
-    vout[e] = wv;
-    acc[0] += wv * wv;
+    for (int q = 0; q < NV; ++q) v -= c[q] * vq[q];
+    vout[off + i] = v;
+    acc[0] += v * v;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) acc[1 + q] += vq[q] * wv;
+    for (int q = 0; q < NV; ++q) acc[1 + q] += vq[q] * v;
+    pm = cm;
+    pc = cc;
+    pp = cp;
   }
 }
 
-// partials2 rows: 0 = ||v_{j+1}||^2, 1 + q = <v_q, v_{j+1}> (q <= j)
-template <int NV>
-__global__ __launch_bounds__(KT) void k_cgs_update(const InstDesc* __restrict__ D,
-                                                   const int2* __restrict__ items, int j) {
+// CGS2 update over the matvec's blocks (z_j in TX).  partials2 rows:
+// 0 = ||v_{j+1}||^2, 1 + q = <v_q, v_{j+1}> (q <= j).  The pad columns of
+// v_{j+1} (N_x <= i < ldx) are never written and stay zero.
+template <typename TX, int NV>
+__global__ __launch_bounds__(MVT) void k_cgs_update(const InstDesc* __restrict__ D,
+                                                    const int2* __restrict__ items, int j) {
   constexpr int NA = NV + 1;
-  __shared__ double red[(KT / 64) * NA];
+  __shared__ double red[(MVT / 64) * NA];
   __shared__ double sh[NVMAX], sc[NVMAX];
   const int2 wi = work_item(items, blockIdx.x);
   const InstDesc& d = D[wi.x];
@@ -294,14 +333,21 @@ __global__ __launch_bounds__(KT) void k_cgs_update(const InstDesc* __restrict__ 
   if (st->sum.done) return;
   const int nv = j + 1;
   update_coeffs(d.partials, d.mv_grid, nv, st, wi.y == 0, sh, sc);
-  double c[NV], acc[NA];
-#pragma unroll
-  for (int q = 0; q < NV; ++q) c[q] = q < nv ? sc[q] : 0.0;
+  // coefficients of vectors past the live count are zero
+  if (threadIdx.x >= nv && threadIdx.x < NV) sc[threadIdx.x] = 0.0;
+  __syncthreads();
+  double acc[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = 0.0;
-  update_sweep<NV>(gp(d.w), gp(d.V), gp(d.V + (size_t)(j + 1) * d.vstride), d.vstride, nv, d.nin,
-                   (long long)wi.y * KT + threadIdx.x, (long long)d.st_grid * KT, c, acc);
-  block_partials<NA>(acc, nv + 1, red, d.partials2, wi.y, d.st_grid);
+  const int blk = wi.y;
+  const int cb = blk % d.mv_cols, rb = blk / d.mv_cols;
+  const int i = cb * MVT + threadIdx.x;
+  const int k0 = rb * d.rows, k1 = min(d.nt, k0 + d.rows);
+  if (i < d.nx)
+    update_column<TX, NV>(gp((const TX*)d.Z + (size_t)j * d.vstride), gp(d.V),
+                          gp(d.V + (size_t)(j + 1) * d.vstride), gp(d.pl.lo), gp(d.pl.di),
+                          gp(d.pl.up), gp(d.dw), d.vstride, d.ldx, d.nx, nv, i, k0, k1, sc, acc);
+  block_partials<NA, MVT>(acc, nv + 1, red, d.partials2, blk, d.mv_grid);
 }
 
 // ---------------------------------------------------------------------------
@@ -331,7 +377,7 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
   }
   static_assert(FIN == 1 || FIN == 4, "finishing kernels: cycle start and Givens step");
   const int nq = FIN == 1 ? 2 : j + 2;
-  const int nblk = FIN == 1 ? d.mv_grid : d.st_grid;
+  const int nblk = d.mv_grid;
   reduce_partials(FIN == 1 ? d.partials : d.partials2, nblk, nq, out);
   if (threadIdx.x != 0) return;
   GSummary& sm = st->sum;
@@ -760,7 +806,12 @@ hipError_t launch_arnoldi(const Launch& L, const Items& mv, const Items& stv, in
                            mv.it, j, (const double*)nullptr, nullptr, nullptr, 0);            \
     }                                                                                         \
     if (passes & 4) {                                                                         \
-      hipLaunchKernelGGL((k_cgs_update<NVB>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, j);   \
+      if (L.zf)                                                                               \
+        hipLaunchKernelGGL((k_cgs_update<float, NVB>), dim3(mv.n), dim3(MVT), 0, s, L.D,      \
+                           mv.it, j);                                                         \
+      else                                                                                    \
+        hipLaunchKernelGGL((k_cgs_update<double, NVB>), dim3(mv.n), dim3(MVT), 0, s, L.D,     \
+                           mv.it, j);                                                         \
       if (finish)                                                                             \
         hipLaunchKernelGGL((k_finish<4>), dim3(L.ninst), dim3(FT), 0, s, L.D, j, stop_iter,  \
                            rtol, slot, seq);                                                  \
