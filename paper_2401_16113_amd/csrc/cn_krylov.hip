@@ -499,7 +499,7 @@ __global__ void k_cycle_finish(const InstDesc* __restrict__ D, int ninst, int sl
 // and ||b||^2 for FIN 1.  The matvec's blocks (MVT columns x `rows` levels),
 // walked UR_R levels at a time: every thread forms x at its column for the
 // UR_R levels with all loads in flight, the values go through LDS so that
-// each residual sees its neighbours' x, and a fifth wavefront forms the two
+// each residual sees its neighbours' x, and an extra wavefront forms the two
 // halo columns of the block; the level above the block is formed again from
 // Z.  Nothing is read from the x being written, which is why a cycle that
 // started from a nonzero x takes k_update and the residual matvec instead.
