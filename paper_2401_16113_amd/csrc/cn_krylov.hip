@@ -361,95 +361,160 @@ __global__ __launch_bounds__(MVT) void k_cgs_update(const InstDesc* __restrict__
 // consumes them)
 // FIN 1 and FIN 4 publish the summary to host slot `slot` of the instance.
 // ---------------------------------------------------------------------------
+// FIN 4, the Givens step of inner iteration j.  Everything the serial part
+// reads from the solver state (the Gram-Schmidt coefficients, the rotations
+// so far, g, the basis scales, the columns of R for the back substitution,
+// the summary) is loaded by the workgroup's threads together, with the
+// partial sums in flight, and handed over through LDS: the one thread that
+// then forms the column, the rotation and (when the cycle stops) y = R^{-1} g
+// waits for no memory (a dependent chain of state loads and a column held in
+// private memory had made this kernel several memory latencies long).
+__device__ __forceinline__ void givens_step(const InstDesc& d, GState* st, GSummary* host, int j,
+                                            int stop_iter, double rtol, int seq, double* out) {
+  constexpr int LDH = MMAX + 1;              // column pitch of R
+  constexpr int HPT = (MMAX * LDH + FT - 1) / FT;
+  __shared__ double s_h1[NVMAX], s_h2[NVMAX], s_vs[NVMAX], s_g[MMAX + 1];
+  __shared__ double s_cs[MMAX], s_sn[MMAX], s_col[NVMAX], s_y[MMAX];
+  __shared__ double s_R[MMAX * LDH];
+  const int t = threadIdx.x;
+  double r_h1 = 0.0, r_h2 = 0.0, r_vs = 0.0, r_g = 0.0, r_cs = 0.0, r_sn = 0.0, r_R[HPT];
+  if (t <= j) {
+    r_h1 = st->h1[t];
+    r_h2 = st->h2[t];
+    r_vs = st->vscale[t];
+    r_g = st->g[t];
+  }
+  if (t < j) {
+    r_cs = st->cs[t];
+    r_sn = st->sn[t];
+  }
+  const int nR = j * LDH;  // columns 0 .. j-1 of R
+#pragma unroll
+  for (int c = 0; c < HPT; ++c) {
+    const int e = t + c * FT;
+    r_R[c] = e < nR ? st->H[e] : 0.0;
+  }
+  const GSummary sm0 = st->sum;
+  // the partial sums are read before the stop flag is looked at (a stopped
+  // cycle's are stale and go unused), so the two loads overlap
+  reduce_partials(d.partials2, d.mv_grid, j + 2, out);
+  if (sm0.done) {
+    // the cycle already stopped: still tell a polling host so
+    if (t == 0) publish(host, sm0, seq);
+    return;
+  }
+  if (t <= j) {
+    s_h1[t] = r_h1;
+    s_h2[t] = r_h2;
+    s_vs[t] = r_vs;
+    s_g[t] = r_g;
+  }
+  if (t < j) {
+    s_cs[t] = r_cs;
+    s_sn[t] = r_sn;
+  }
+#pragma unroll
+  for (int c = 0; c < HPT; ++c) {
+    const int e = t + c * FT;
+    if (e < nR) s_R[e] = r_R[c];
+  }
+  __syncthreads();
+  if (t != 0) return;
+  GSummary sm = sm0;
+  const double hn = sqrt(out[0]);
+  double* col = s_col;
+  for (int q = 0; q <= j; ++q) col[q] = s_h1[q] + s_h2[q];
+  col[j + 1] = hn;
+  for (int q = 0; q < j; ++q) {
+    const double t0 = s_cs[q] * col[q] + s_sn[q] * col[q + 1];
+    const double t1 = -s_sn[q] * col[q] + s_cs[q] * col[q + 1];
+    col[q] = t0;
+    col[q + 1] = t1;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  double cs = 1.0, sn = 0.0;
+  if (den > 0.0) {
+    cs = col[j] / den;
+    sn = col[j + 1] / den;
+  }
+  st->cs[j] = cs;
+  st->sn[j] = sn;
+  col[j] = den;
+  for (int q = 0; q <= j; ++q) st->H[j * LDH + q] = col[q];
+  const double gj = s_g[j];
+  const double gnew = cs * gj, gnext = -sn * gj;
+  st->g[j] = gnew;
+  st->g[j + 1] = gnext;
+  s_g[j] = gnew;
+  const double est = fabs(gnext);
+  sm.est = sm.bnorm > 0.0 ? est / sm.bnorm : 0.0;
+  const double sn1 = hn > 0.0 ? 1.0 / hn : 0.0;
+  st->vscale[j + 1] = sn1;
+  double* grow = st->gram + (size_t)(j + 1) * NVMAX;
+  for (int q = 0; q <= j; ++q) {
+    const double gq = out[1 + q] * s_vs[q] * sn1;
+    grow[q] = gq;
+    st->gram[(size_t)q * NVMAX + j + 1] = gq;
+  }
+  grow[j + 1] = 1.0;
+  sm.k = j + 1;
+  const bool brk = !(hn > 1e-300 * (sm.beta > 0.0 ? sm.beta : 1.0));
+  sm.breakdown = brk ? 1 : 0;
+  if (est <= rtol * sm.bnorm || brk || j + 1 >= stop_iter) {
+    sm.done = 1;
+    // the cycle stops here: y = R^{-1} g for the cycle end (column j of R is
+    // the one just formed, the others were loaded above)
+    for (int q = j; q >= 0; --q) {
+      double s = s_g[q];
+      for (int r = q + 1; r <= j; ++r) s -= (r == j ? col[q] : s_R[r * LDH + q]) * s_y[r];
+      const double dd = q == j ? col[j] : s_R[q * LDH + q];
+      const double yq = dd != 0.0 ? s / dd : 0.0;
+      s_y[q] = yq;
+      st->y[q] = yq;
+    }
+  }
+  st->sum.est = sm.est;
+  st->sum.k = sm.k;
+  st->sum.breakdown = sm.breakdown;
+  st->sum.done = sm.done;
+  publish(host, sm, seq);
+}
+
 template <int FIN>
 __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, int j,
                                                int stop_iter, double rtol, int slot, int seq) {
+  static_assert(FIN == 1 || FIN == 4, "finishing kernels: cycle start and Givens step");
   __shared__ double out[NVMAX];
   const InstDesc& d = D[blockIdx.x];
   GState* st = d.st;
   GSummary* host = d.host != nullptr ? d.host + slot : nullptr;
-  // FIN 1 with stop_iter != 0: speculative cycle start, only after a stopped cycle
-  if (FIN == 1 && stop_iter != 0 && !st->sum.done) return;
-  if (FIN != 1 && st->sum.done) {
-    // the cycle already stopped: still tell a polling host so
-    if (FIN == 4 && threadIdx.x == 0) publish(host, st->sum, seq);
+  if constexpr (FIN == 4) {
+    givens_step(d, st, host, j, stop_iter, rtol, seq, out);
     return;
   }
-  static_assert(FIN == 1 || FIN == 4, "finishing kernels: cycle start and Givens step");
-  const int nq = FIN == 1 ? 2 : j + 2;
-  const int nblk = d.mv_grid;
-  reduce_partials(FIN == 1 ? d.partials : d.partials2, nblk, nq, out);
+  // FIN 1 with stop_iter != 0: speculative cycle start, only after a stopped cycle
+  if (stop_iter != 0 && !st->sum.done) return;
+  reduce_partials(d.partials, d.mv_grid, 2, out);
   if (threadIdx.x != 0) return;
   GSummary& sm = st->sum;
-  if (FIN == 1) {
-    // start of a cycle: beta = ||r||, v_0 = r / beta (stored unnormalised)
-    sm.bnorm = sqrt(out[1]);
-    double beta = sqrt(out[0]);
-    if (j >= 1) sm.x0_rejected = 0;
-    if (j == 2 && beta >= sm.bnorm && sm.bnorm > 0.0) {
-      sm.x0_rejected = 1;
-      beta = sm.bnorm;
-    }
-    sm.beta = beta;
-    st->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
-    st->gram[0] = 1.0;
-    st->g[0] = beta;
-    for (int q = 1; q <= MMAX; ++q) st->g[q] = 0.0;
-    sm.relres = sm.bnorm > 0.0 ? beta / sm.bnorm : 0.0;
-    sm.breakdown = 0;
-    sm.k = 0;
-    sm.done = (sm.relres <= rtol || beta == 0.0) ? 1 : 0;
-    publish(host, sm, seq);
-  } else {
-    const double hn = sqrt(out[0]);
-    double col[MMAX + 1];
-    for (int q = 0; q <= j; ++q) col[q] = st->h1[q] + st->h2[q];
-    col[j + 1] = hn;
-    for (int q = 0; q < j; ++q) {
-      const double t0 = st->cs[q] * col[q] + st->sn[q] * col[q + 1];
-      const double t1 = -st->sn[q] * col[q] + st->cs[q] * col[q + 1];
-      col[q] = t0;
-      col[q + 1] = t1;
-    }
-    const double den = hypot(col[j], col[j + 1]);
-    double cs = 1.0, sn = 0.0;
-    if (den > 0.0) {
-      cs = col[j] / den;
-      sn = col[j + 1] / den;
-    }
-    st->cs[j] = cs;
-    st->sn[j] = sn;
-    col[j] = den;
-    for (int q = 0; q <= j; ++q) st->H[j * (MMAX + 1) + q] = col[q];
-    const double gj = st->g[j];
-    st->g[j] = cs * gj;
-    st->g[j + 1] = -sn * gj;
-    const double est = fabs(st->g[j + 1]);
-    sm.est = sm.bnorm > 0.0 ? est / sm.bnorm : 0.0;
-    const double sn1 = hn > 0.0 ? 1.0 / hn : 0.0;
-    st->vscale[j + 1] = sn1;
-    double* grow = st->gram + (size_t)(j + 1) * NVMAX;
-    for (int q = 0; q <= j; ++q) {
-      const double gq = out[1 + q] * st->vscale[q] * sn1;
-      grow[q] = gq;
-      st->gram[(size_t)q * NVMAX + j + 1] = gq;
-    }
-    grow[j + 1] = 1.0;
-    sm.k = j + 1;
-    const bool brk = !(hn > 1e-300 * (sm.beta > 0.0 ? sm.beta : 1.0));
-    sm.breakdown = brk ? 1 : 0;
-    if (est <= rtol * sm.bnorm || brk || j + 1 >= stop_iter) {
-      sm.done = 1;
-      // the cycle stops here: y = R^{-1} g for the cycle end
-      for (int q = j; q >= 0; --q) {
-        double s = st->g[q];
-        for (int r = q + 1; r <= j; ++r) s -= st->H[r * (MMAX + 1) + q] * st->y[r];
-        const double dd = st->H[q * (MMAX + 1) + q];
-        st->y[q] = dd != 0.0 ? s / dd : 0.0;
-      }
-    }
-    publish(host, sm, seq);
+  // start of a cycle: beta = ||r||, v_0 = r / beta (stored unnormalised)
+  sm.bnorm = sqrt(out[1]);
+  double beta = sqrt(out[0]);
+  if (j >= 1) sm.x0_rejected = 0;
+  if (j == 2 && beta >= sm.bnorm && sm.bnorm > 0.0) {
+    sm.x0_rejected = 1;
+    beta = sm.bnorm;
   }
+  sm.beta = beta;
+  st->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+  st->gram[0] = 1.0;
+  st->g[0] = beta;
+  for (int q = 1; q <= MMAX; ++q) st->g[q] = 0.0;
+  sm.relres = sm.bnorm > 0.0 ? beta / sm.bnorm : 0.0;
+  sm.breakdown = 0;
+  sm.k = 0;
+  sm.done = (sm.relres <= rtol || beta == 0.0) ? 1 : 0;
+  publish(host, sm, seq);
 }
 
 // Fallback start: an instance whose initial guess was rejected by the first
