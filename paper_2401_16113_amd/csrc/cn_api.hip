@@ -873,7 +873,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
             spec_res = ++(*c.seqc);
             if (x_zero) {
               HIP_TRY(launch_cycle_end_zero(c.L, c.mv, enq, b, x, rtol, 3, spec_fin, 2, spec_res,
-                                            c.s, true));
+                                            c.s, true, false));
             } else {
               HIP_TRY(launch_cycle_end(c.L, c.stv, x, 0, 3, spec_fin, c.s, true));
               HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, spec_res, c.s, 0, true));
@@ -892,7 +892,9 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
     }
     // y from the triangular factors (cycle summaries -> slot 3), x += Z y,
     // then the true residuals (-> slot 2), unless already queued; a cycle
-    // from x = 0 does the update and the residual in one pass
+    // from x = 0 does the update and the residual in one pass, and for one
+    // instance leaves r unstored (formed again below if the cycle restarts)
+    const bool r_unstored = x_zero && !c.batched;
     int seq_fin = spec_fin;
     if (spec_taken) {
       seq_res = spec_res;
@@ -900,7 +902,8 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
       seq_fin = c.batched ? 0 : ++(*c.seqc);
       seq_res = c.batched ? 0 : ++(*c.seqc);
       if (x_zero) {
-        HIP_TRY(launch_cycle_end_zero(c.L, c.mv, enq, b, x, rtol, 3, seq_fin, 2, seq_res, c.s));
+        HIP_TRY(launch_cycle_end_zero(c.L, c.mv, enq, b, x, rtol, 3, seq_fin, 2, seq_res, c.s,
+                                      false, c.batched));
       } else {
         HIP_TRY(launch_cycle_end(c.L, c.stv, x, 0, 3, seq_fin, c.s));
         HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, seq_res, c.s, 0));
@@ -938,6 +941,12 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
     }
     done_iters += kmax;
     if (kmax == 0 || all_conv || done_iters >= opts->max_iters) break;
+    if (r_unstored) {
+      // the restart's v_0: r = b - M x again (and FIN 1 on it)
+      seq_res = ++(*c.seqc);
+      HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, rtol, 2, seq_res, c.s, 0));
+      ++mvs[0];
+    }
     for (int i = 0; i < ninst; ++i)
       if (!(cur[i].relres <= rtol)) ++rest[i];
   }

@@ -171,13 +171,13 @@ hipError_t launch_arnoldi(const Launch& L, const Items& mv, const Items& stv, in
 hipError_t launch_cycle_end(const Launch& L, const Items& stv, double* x_base, int x_zero,
                             int slot, int seq, hipStream_t s, bool guard = false);
 // end of a cycle that started from x = 0 (every instance of the launch), in
-// two kernels: y, x = Z y and the true residual into V_0 in one pass (cycle
-// summary -> slot_fin), then FIN 1 in restart mode (-> slot_res).  kmax: the
-// most inner iterations any instance of this cycle can have run.
+// two kernels: y, x = Z y and the true residual (into V_0 when store_r) in one
+// pass (cycle summary -> slot_fin), then FIN 1 in restart mode (-> slot_res).
+// kmax: the most inner iterations any instance of this cycle can have run.
 hipError_t launch_cycle_end_zero(const Launch& L, const Items& mv, int kmax,
                                  const double* b_base, double* x_base, double rtol, int slot_fin,
                                  int seq_fin, int slot_res, int seq_res, hipStream_t s,
-                                 bool guard = false);
+                                 bool guard = false, bool store_r = true);
 // publish the number of instances still iterating (batch polling)
 hipError_t launch_batch_summary(const Launch& L, int* counter, GSummary* host, hipStream_t s);
 hipError_t launch_rhs(const double* lo, const double* di, const double* up, const double* dw,

@@ -560,8 +560,10 @@ __global__ void k_cycle_finish(const InstDesc* __restrict__ D, int ninst, int sl
 // End of a cycle that started from x = 0, in one pass (y = R^{-1} g was formed
 // by the Givens kernel that stopped the cycle; block 0 publishes the cycle
 // summary to host slot `slot`): x = Z y,
-// and the true residual r = b - M x into V_0 with the partial sums of ||r||^2
-// and ||b||^2 for FIN 1.  The matvec's blocks (MVT columns x `rows` levels),
+// and the true residual r = b - M x with the partial sums of ||r||^2 and
+// ||b||^2 for FIN 1; r itself goes to V_0 only when store_r is set (a restart
+// starts from it; a caller that skips it forms r again before restarting,
+// which saves a vector's write whenever the cycle converges).  The matvec's blocks (MVT columns x `rows` levels),
 // walked UR_R levels at a time: every thread forms x at its column for the
 // UR_R levels with all loads in flight, the values go through LDS so that
 // each residual sees its neighbours' x, and an extra wavefront forms the two
@@ -577,7 +579,7 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
                                                           const int2* __restrict__ items,
                                                           const double* __restrict__ bo,
                                                           double* __restrict__ xo, int guard,
-                                                          int slot, int seq) {
+                                                          int store_r, int slot, int seq) {
   __shared__ double red[(UR_T / 64) * 2];
   __shared__ double ys[KB];
   __shared__ double xs[UR_R + 1][MVT + 2];  // level above the step + its UR_R levels
@@ -676,7 +678,7 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
     const double w = d.dw != nullptr ? gp(d.dw)[k] : 1.0;
     const double ax = lo * (cm + pm) + di * (cc + pc) + up * (cp + pp);
     const double rv = bv - ((cc - pc) - 0.5 * w * ax);
-    v0[(size_t)k * ldx + col] = rv;
+    if (store_r) v0[(size_t)k * ldx + col] = rv;
     acc[0] += rv * rv;
     acc[1] += bv * bv;
   };
@@ -907,17 +909,19 @@ hipError_t launch_cycle_end(const Launch& L, const Items& stv, double* x_base, i
 hipError_t launch_cycle_end_zero(const Launch& L, const Items& mv, int kmax,
                                  const double* b_base, double* x_base, double rtol, int slot_fin,
                                  int seq_fin, int slot_res, int seq_res, hipStream_t s,
-                                 bool guard) {
+                                 bool guard, bool store_r) {
   const int bk = nv_bucket(kmax < 1 ? 1 : kmax);
   switch (bk) {
 #define UR(KB)                                                                                \
   case KB:                                                                                    \
     if (L.zf)                                                                                 \
       hipLaunchKernelGGL((k_update_residual<float, KB>), dim3(mv.n), dim3(UR_T), 0, s, L.D,   \
-                         mv.it, b_base, x_base, guard ? 1 : 0, slot_fin, seq_fin);            \
+                         mv.it, b_base, x_base, guard ? 1 : 0, store_r ? 1 : 0, slot_fin,   \
+                         seq_fin);                                                            \
     else                                                                                      \
       hipLaunchKernelGGL((k_update_residual<double, KB>), dim3(mv.n), dim3(UR_T), 0, s, L.D,  \
-                         mv.it, b_base, x_base, guard ? 1 : 0, slot_fin, seq_fin);            \
+                         mv.it, b_base, x_base, guard ? 1 : 0, store_r ? 1 : 0, slot_fin,   \
+                         seq_fin);                                                            \
     break;
     UR(1) UR(2) UR(4) UR(8) UR(16) UR(32) UR(64)
 #undef UR
