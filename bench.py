@@ -344,7 +344,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the solver has no multi-GPU path in this build.", file=sys.stderr)
+              "the solver has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2401_16113_amd import binding as B
