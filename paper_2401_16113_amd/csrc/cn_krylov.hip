@@ -261,7 +261,12 @@ __device__ __forceinline__ void update_coeffs(const double* __restrict__ partial
 // (v_{j+1} is the basis buffer's next vector, disjoint from the vectors read).
 // Vectors q >= nv re-read v_{nv-1} (cache hits) with coefficient 0; their
 // dots are never written: no branch between the loads.
-template <typename TX, int NV>
+// Every thread of the workgroup calls this (act: the column exists) and
+// coeffs() -- the coefficient reduction, with workgroup barriers -- runs
+// after the column's first levels have been requested: the barriers wait for
+// LDS only, so those loads are in flight during the reduction instead of
+// starting after it.
+template <typename TX, int NV, typename Coeffs>
 __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
                                               const CN_G double* __restrict__ V,
                                               CN_G double* __restrict__ vout,
@@ -270,17 +275,11 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
                                               const CN_G double* __restrict__ pup,
                                               const CN_G double* __restrict__ dw,
                                               long long vstride, int ldx, int nx, int nv, int i,
-                                              int k0, int k1, const double* c,
+                                              bool act, int k0, int k1, Coeffs&& coeffs,
                                               double (&acc)[NV + 1]) {
-  const double lo = plo[i], di = pdi[i], up = pup[i];
+  // levels in flight together: fewer for long bases (registers)
+  constexpr int UNR = NV <= 4 ? 4 : (NV <= 8 ? 2 : 1);
   const bool hl = i > 0, hr = i < nx - 1;
-  double pm = 0.0, pc = 0.0, pp = 0.0;  // z at the previous level, i-1, i, i+1
-  if (k0 > 0) {
-    const CN_G TX* zr = z + (size_t)(k0 - 1) * ldx;
-    pc = (double)zr[i];
-    if (hl) pm = (double)zr[i - 1];
-    if (hr) pp = (double)zr[i + 1];
-  }
   // basis offsets in registers for short bases, formed per load for long ones
   constexpr int NVO = NV <= 8 ? NV : 1;
   size_t vo[NVO];
@@ -290,19 +289,41 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
     if constexpr (NV <= 8) return vo[q];
     else return (size_t)(q < nv ? q : nv - 1) * vstride;
   };
-  // levels in flight together: fewer for long bases (registers)
-  constexpr int UNR = NV <= 4 ? 4 : (NV <= 8 ? 2 : 1);
-#pragma unroll UNR
-  for (int k = k0; k < k1; ++k) {
-    const size_t off = (size_t)k * ldx;
-    const double cc = (double)z[off + i];
-    const double cm = hl ? (double)z[off + i - 1] : 0.0;
-    const double cp = hr ? (double)z[off + i + 1] : 0.0;
-    double vq[NV];
+  double lo = 0.0, di = 0.0, up = 0.0;
+  double pm = 0.0, pc = 0.0, pp = 0.0;  // z at the previous level, i-1, i, i+1
+  // the first PF levels, requested before the coefficients exist (few: the
+  // registers they hold must not cost the kernel its second workgroup per CU)
+  constexpr int PF = NV <= 4 ? 2 : 1;
+  double fc[PF], fm[PF], fp[PF], fv[PF][NV], fw[PF];
+  if (act) {
+    lo = plo[i];
+    di = pdi[i];
+    up = pup[i];
+    if (k0 > 0) {
+      const CN_G TX* zr = z + (size_t)(k0 - 1) * ldx;
+      pc = (double)zr[i];
+      if (hl) pm = (double)zr[i - 1];
+      if (hr) pp = (double)zr[i + 1];
+    }
 #pragma unroll
-    for (int q = 0; q < NV; ++q) vq[q] = V[voff(q) + off + i];
-    const double w = dw != nullptr ? dw[k] : 1.0;
-    // (M z)^k = (z^k - z^{k-1}) - (w/2) A~ (z^k + z^{k-1})
+    for (int u = 0; u < PF; ++u) {
+      // levels past k1 re-read level k1-1 (in bounds, never used)
+      const int k = min(k0 + u, k1 - 1);
+      const size_t off = (size_t)k * ldx;
+      fc[u] = (double)z[off + i];
+      fm[u] = hl ? (double)z[off + i - 1] : 0.0;
+      fp[u] = hr ? (double)z[off + i + 1] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) fv[u][q] = V[voff(q) + off + i];
+      fw[u] = dw != nullptr ? dw[k] : 1.0;
+    }
+  }
+  const double* c = coeffs();
+  if (!act) return;
+  // one level: (M z)^k = (z^k - z^{k-1}) - (w/2) A~ (z^k + z^{k-1}), then the
+  // projections
+  auto level = [&](int k, double cc, double cm, double cp, const double (&vq)[NV], double w) {
+    const size_t off = (size_t)k * ldx;
     const double sm = cm + pm, s0 = cc + pc, sp = cp + pp;
     const double ax = lo * sm + di * s0 + up * sp;
     double v = (cc - pc) - 0.5 * w * ax;
@@ -315,6 +336,21 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
     pm = cm;
     pc = cc;
     pp = cp;
+  };
+#pragma unroll
+  for (int u = 0; u < PF; ++u)
+    if (k0 + u < k1) level(k0 + u, fc[u], fm[u], fp[u], fv[u], fw[u]);
+#pragma unroll UNR
+  for (int k = k0 + PF; k < k1; ++k) {
+    const size_t off = (size_t)k * ldx;
+    const double cc = (double)z[off + i];
+    const double cm = hl ? (double)z[off + i - 1] : 0.0;
+    const double cp = hr ? (double)z[off + i + 1] : 0.0;
+    double vq[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) vq[q] = V[voff(q) + off + i];
+    const double w = dw != nullptr ? dw[k] : 1.0;
+    level(k, cc, cm, cp, vq, w);
   }
 }
 
@@ -332,10 +368,6 @@ __global__ __launch_bounds__(MVT) void k_cgs_update(const InstDesc* __restrict__
   GState* st = d.st;
   if (st->sum.done) return;
   const int nv = j + 1;
-  update_coeffs(d.partials, d.mv_grid, nv, st, wi.y == 0, sh, sc);
-  // coefficients of vectors past the live count are zero
-  if (threadIdx.x >= nv && threadIdx.x < NV) sc[threadIdx.x] = 0.0;
-  __syncthreads();
   double acc[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = 0.0;
@@ -343,10 +375,17 @@ __global__ __launch_bounds__(MVT) void k_cgs_update(const InstDesc* __restrict__
   const int cb = blk % d.mv_cols, rb = blk / d.mv_cols;
   const int i = cb * MVT + threadIdx.x;
   const int k0 = rb * d.rows, k1 = min(d.nt, k0 + d.rows);
-  if (i < d.nx)
-    update_column<TX, NV>(gp((const TX*)d.Z + (size_t)j * d.vstride), gp(d.V),
-                          gp(d.V + (size_t)(j + 1) * d.vstride), gp(d.pl.lo), gp(d.pl.di),
-                          gp(d.pl.up), gp(d.dw), d.vstride, d.ldx, d.nx, nv, i, k0, k1, sc, acc);
+  auto coeffs = [&]() -> const double* {
+    update_coeffs(d.partials, d.mv_grid, nv, st, wi.y == 0, sh, sc);
+    // coefficients of vectors past the live count are zero
+    if (threadIdx.x >= nv && threadIdx.x < NV) sc[threadIdx.x] = 0.0;
+    __syncthreads();
+    return sc;
+  };
+  update_column<TX, NV>(gp((const TX*)d.Z + (size_t)j * d.vstride), gp(d.V),
+                        gp(d.V + (size_t)(j + 1) * d.vstride), gp(d.pl.lo), gp(d.pl.di),
+                        gp(d.pl.up), gp(d.dw), d.vstride, d.ldx, d.nx, nv, i, i < d.nx, k0, k1,
+                        coeffs, acc);
   block_partials<NA, MVT>(acc, nv + 1, red, d.partials2, blk, d.mv_grid);
 }
 
