@@ -423,3 +423,122 @@ def test_pc_matvec_equals_dense_preconditioner_and_inverts_pc_apply():
     assert np.max(np.abs(O.pc_matvec(*args, 0.05, zz) - v)) <= 1e-12
     # a missing alpha on the wrap-around block is visible
     assert np.max(np.abs(O.pc_matvec(*args, 1.0, zz) - v)) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# time-dependent coefficients L(t) = d(t) L, eq. (5.8) of Sec. 5.2
+# ---------------------------------------------------------------------------
+
+def _mid_weights(T, nt, r):
+    """The diagonal of D~ in eq. (5.8): d(t) = exp(-r t) at t_{k+1/2}."""
+    return np.exp(-r * (np.arange(nt) + 0.5) * T / nt)
+
+
+def _laplacian_mode(nx):
+    """Dirichlet Laplacian on (0, 1) (eq. (1.2), constant diffusion) and its
+    lowest eigenpair: s_i = sin(pi x_i), mu = -(4/h^2) sin^2(pi h / 2)
+    (textbook Toeplitz spectrum)."""
+    h = 1.0 / (nx + 1)
+    x = h * np.arange(1, nx + 1)
+    lo = np.full(nx, 1.0 / h ** 2)
+    up = np.full(nx, 1.0 / h ** 2)
+    di = np.full(nx, -2.0 / h ** 2)
+    lo[0] = 0.0
+    up[-1] = 0.0
+    return lo, di, up, np.sin(np.pi * x), -(4.0 / h ** 2) * np.sin(np.pi * h / 2) ** 2
+
+
+def test_time_weights_matvec_kronecker_form():
+    """eq. (5.8): the block loop with weight d_k on row k equals the dense
+    B1 (x) I - (D~ B2) (x) A~ with D~ = diag(d(t_{1/2}), ..., d(t_{N_t-1/2}))."""
+    inst = tiny_localvol(nx=7, nt=8)
+    args = (inst.a_lo, inst.a_di, inst.a_up, inst.T, 8)
+    d = _mid_weights(inst.T, 8, 0.4)
+    At = (inst.T / 8) * O.tridiag_dense(inst.a_lo, inst.a_di, inst.a_up)
+    B1 = np.eye(8) - np.eye(8, k=-1)
+    B2 = 0.5 * (np.eye(8) + np.eye(8, k=-1))
+    Md = np.kron(B1, np.eye(7)) - np.kron(np.diag(d) @ B2, At)
+    u = np.random.default_rng(5).standard_normal(56)
+    assert np.max(np.abs(O.aao_matvec(*args, u, d=d) - Md @ u)) <= 1e-13 * np.max(np.abs(Md @ u))
+    # weights on the wrong side (B2 D~, a plausible slip) are a different matrix
+    Mw = np.kron(B1, np.eye(7)) - np.kron(B2 @ np.diag(d), At)
+    assert np.max(np.abs(O.aao_matvec(*args, u, d=d) - Mw @ u)) > 1e-3 * np.max(np.abs(Mw @ u))
+
+
+def test_time_weights_eigenmode_closed_form():
+    """For u^0 = s (an eigenvector of A, eigenvalue mu) and f = 0, the CN
+    steps of the weighted scheme multiply s by R(tau d(t_{k+1/2}) mu),
+    R(z) = (1 + z/2)/(1 - z/2), so level k holds prod_{q<=k} R_q s exactly.
+    Pins the block forward substitution, and (through M u = b) the weighted
+    matvec and the first block of xi, which uses d(t_{1/2})."""
+    nx, nt, T, r = 31, 16, 1.0, 0.7
+    lo, di, up, s, mu = _laplacian_mode(nx)
+    d = _mid_weights(T, nt, r)
+    tau = T / nt
+    f = np.zeros((nt, nx))
+    u = O.sequential_cn(lo, di, up, T, nt, s, f, d=d).reshape(nt, nx)
+    z = tau * d * mu
+    g = np.cumprod((1 + z / 2) / (1 - z / 2))
+    assert np.max(np.abs(u - g[:, None] * s[None, :])) <= 1e-13
+    b = O.aao_rhs(lo, di, up, T, nt, s, f, d=d)
+    Mu = O.aao_matvec(lo, di, up, T, nt, u.reshape(-1), d=d)
+    assert np.max(np.abs(Mu - b)) <= 1e-13
+    # xi's first block is R-scaled data: (1 + tau d(t_1/2) mu / 2) s
+    assert np.max(np.abs(b[:nx] - (1 + z[0] / 2) * s)) <= 1e-13
+
+
+def _weighted_mode_error(nt, weights_at, T=1.0, r=1.5):
+    """Error at t = T of the weighted CN steps against the semi-discrete
+    solution exp(mu int_0^T d) s, with d = exp(-r t) sampled by
+    `weights_at(T, nt)`."""
+    lo, di, up, s, mu = _laplacian_mode(15)
+    d = weights_at(T, nt)
+    u = O.sequential_cn(lo, di, up, T, nt, s, np.zeros((nt, 15)), d=d).reshape(nt, 15)
+    exact = np.exp(mu * (1 - np.exp(-r * T)) / r) * s
+    return np.max(np.abs(u[-1] - exact))
+
+
+def test_time_weights_second_order():
+    """Sec. 2.1/5.2: with the weights at the midpoints t_{k+1/2} the scheme
+    stays second order in time (error ratio ~4 per halving of tau)."""
+    errs = [_weighted_mode_error(nt, lambda T, n: _mid_weights(T, n, 1.5)) for nt in (8, 16, 32, 64)]
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(ratios > 3.6) and np.all(ratios < 4.4), (errs, ratios)
+
+
+def test_planted_weights_at_left_points_are_caught():
+    """Planted: d sampled at t_k instead of t_{k+1/2}.  The order drops to
+    one and the second-order pin fails."""
+    left = lambda T, n: np.exp(-1.5 * np.arange(n) * T / n)
+    errs = [_weighted_mode_error(nt, left) for nt in (8, 16, 32, 64)]
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    with pytest.raises(AssertionError):
+        assert np.all(ratios > 3.6) and np.all(ratios < 4.4), (errs, ratios)
+
+
+def _dbar_error(c, alpha=0.05):
+    """P_alpha with C2 replaced by dbar C2 (Sec. 5.2) is, for constant
+    weights d = c, the preconditioner of Sec. 4 built from the weighted
+    system: M(c) - alpha R(c), where the operator c A~ enters M and the
+    coupling block Q2 = I + c A~/2 (the Sec. 4 identity with tau -> c tau).
+    Returns the relative error of pc_apply(dbar = c) against its dense solve."""
+    inst = tiny_localvol(nx=7, nt=8)
+    lo, di, up, T = inst.a_lo, inst.a_di, inst.a_up, inst.T
+    P = O.aao_matrix_dense(lo, di, up, c * T, 8) - alpha * O.coupling_matrix_dense(lo, di, up, c * T, 8)
+    v = np.random.default_rng(6).standard_normal(56)
+    zr = np.linalg.solve(P, v)
+    z = O.pc_apply(lo, di, up, T, 8, alpha, v, dbar=c)
+    return np.max(np.abs(z - zr)) / np.max(np.abs(zr))
+
+
+def test_dbar_preconditioner_is_averaged_system():
+    for c in (0.6, 0.93, 1.0, 1.4):
+        assert _dbar_error(c) <= 1e-12
+
+
+def test_planted_dbar_on_c1_is_caught(monkeypatch):
+    """Planted: the mean weight applied to C1 as well as C2."""
+    assert _dbar_error(0.9) <= 1e-12
+    orig = O.pc_eigenvalues
+    monkeypatch.setattr(O, "pc_eigenvalues", lambda a, n: (0.9 * orig(a, n)[0], orig(a, n)[1]))
+    assert _dbar_error(0.9) > 1e-3
