@@ -272,7 +272,7 @@ def form_production(B, W, torch, reps):
     if r.status != B.CN_OK:
         raise RuntimeError(f"production shape did not converge: {r}")
     prof = s.profile_step(j=1, reps=5)
-    pc_keys = [k for k in ("pc_forward", "pc_reduced", "pc_inverse", "pc_fused") if k in prof]
+    pc_keys = [k for k in ("pc_forward", "pc_reduced", "pc_inverse") if k in prof]
     pc_ms = sum(prof[k]["ms"] for k in pc_keys)
     pc_bytes = sum(prof[k]["bytes"] for k in pc_keys)
     out = {"nx": inst.nx, "nt": inst.nt, "unknowns": inst.n, "pc_variant": s.query(),

@@ -148,19 +148,6 @@ cn_status cn_gmres_solve(cn_aao *h, const double *b, double *x,
 cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
                        int32_t *threads);
 
-/* Form of the preconditioner apply chosen at create time (autotuned, like
- * the tile shape): *single_launch = 1 when steps (a)-(c) run as one kernel
- * whose workgroups (one per tile, all resident on the device at once) meet
- * at two grid-wide barriers around the interface systems, so the tile image
- * stays in on-chip memory; 0 for the three launches K1, K2, K3.  Only a
- * stand-alone handle whose tiles all fit on the device at once is eligible.
- * The environment variable CN_PC_FUSED=0 or =1 at create time restricts the
- * choice to the three-launch or (where eligible) the single-launch form.  A
- * barrier that times out (never expected: eligibility is checked against
- * the device's occupancy) makes the next call on the handle return CN_EHIP
- * and switches the handle to three launches. */
-cn_status cn_aao_pc_mode(const cn_aao *h, int32_t *single_launch);
-
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems of uneven sizes solved together.  Every
  * step of the method (each transform, interface solve, matvec, Gram-Schmidt
@@ -208,16 +195,11 @@ cn_status cn_batch_solve(cn_batch *b, const double *bp, double *xp, const cn_gmr
  * (reads + writes of its inputs and outputs, each touched once).  Kernel
  * order: 0 pc_forward (steps (a) + local (b)), 1 pc_reduced (interface
  * systems of (b)), 2 pc_inverse (correction + step (c)), 3 matvec fused with
- * the dots against the basis, 4 unused (ms and bytes 0: the second CGS2
- * projection takes its coefficients from the basis' Gram matrix and has no
- * pass of its own), 5 CGS2 update (both projections, with the reduction of
- * the matvec's dots) + norm + Gram row of the new vector; the one-workgroup
- * Givens kernel is not included; 6 the single-launch apply (steps (a)-(c) in
- * one kernel, see cn_aao_pc_mode).  Only the apply form the handle's solves
- * use is timed: ms is 0 for kernels 0-2 of a single-launch handle, and ms and
- * bytes are 0 for kernel 6 of a three-launch handle.  ms and bytes: host
+ * the dots against the basis, 4 Gram-Schmidt update (both projections, with
+ * the reduction of the matvec's dots) + norm + Gram row of the new vector;
+ * the one-workgroup Givens kernel is not included.  ms and bytes: host
  * arrays of CN_PROFILE_KERNELS doubles.  Synchronises. */
-#define CN_PROFILE_KERNELS 7
+#define CN_PROFILE_KERNELS 5
 cn_status cn_profile_step(cn_aao *h, int32_t j, int32_t reps, double *ms, double *bytes);
 
 const char *cn_status_string(cn_status s);

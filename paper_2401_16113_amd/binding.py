@@ -71,7 +71,6 @@ def load():
         "cn_aao_destroy": (ctypes.c_int, [vp]),
         "cn_aao_query": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                         ctypes.POINTER(i32)]),
-        "cn_aao_pc_mode": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
         "cn_rhs": (ctypes.c_int, [vp, vp, vp, vp]),
         "cn_matvec": (ctypes.c_int, [vp, vp, vp]),
         "cn_pc_apply": (ctypes.c_int, [vp, vp, vp]),
@@ -195,10 +194,7 @@ class Solver:
         b, p, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(self._lib.cn_aao_query(self._h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(t)),
                "cn_aao_query")
-        f = ctypes.c_int32()
-        _check(self._lib.cn_aao_pc_mode(self._h, ctypes.byref(f)), "cn_aao_pc_mode")
-        return {"tile_cols": b.value, "tiles": p.value, "threads": t.value,
-                "single_launch": bool(f.value)}
+        return {"tile_cols": b.value, "tiles": p.value, "threads": t.value}
 
     def rhs(self, u0, f, out):
         _check(self._lib.cn_rhs(self._h, _ptr(u0), _ptr(f), _ptr(out)), "cn_rhs")
@@ -212,16 +208,14 @@ class Solver:
         _check(self._lib.cn_pc_apply(self._h, _ptr(v), _ptr(out)), "cn_pc_apply")
         return out
 
-    # entry 4 is retired (no second dot pass); entries with ms = 0 are dropped
-    KERNELS = ("pc_forward", "pc_reduced", "pc_inverse", "matvec_dots", "retired",
-               "cgs_update", "pc_fused")
+    KERNELS = ("pc_forward", "pc_reduced", "pc_inverse", "matvec_dots", "cgs_update")
 
     def profile_step(self, j: int, reps: int = 20):
         """Average launch time (ms) and algorithmic bytes of the kernels of
         inner iteration j (after a solve with more than j iterations): the
-        preconditioner apply in the form the handle uses (pc_forward,
-        pc_reduced, pc_inverse, or the single-launch pc_fused) and the two
-        streaming Krylov kernels (matvec with the basis dots, CGS2 update)."""
+        preconditioner apply (pc_forward, pc_reduced, pc_inverse) and the two
+        streaming Krylov kernels (matvec with the basis dots, Gram-Schmidt
+        update)."""
         n = len(self.KERNELS)
         ms = (ctypes.c_double * n)()
         by = (ctypes.c_double * n)()

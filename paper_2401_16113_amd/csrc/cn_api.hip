@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <atomic>
@@ -27,10 +28,90 @@ using namespace cn;
 
 static thread_local std::string g_err;
 
-// Process-wide cache of the autotuned transform variant per
-// (precision, log2 N_t, N_x): later handles of the same shape skip tuning.
+// Autotuned transform variant per (precision, log2 N_t, N_x) on this device:
+// kept per process, and on disk so that later processes skip the timing.  The
+// file (CN_TUNE_CACHE, else $XDG_CACHE_HOME/cn_aao/tune.txt, else
+// $HOME/.cache/cn_aao/tune.txt; CN_TUNE_CACHE="" turns it off) holds one line
+// per choice: tag, device, precision, log2 N_t, N_x, tile width, workgroup
+// size.  The tag is the build time of this library, so a rebuilt library
+// tunes again; the device is its architecture name and compute-unit count.
+struct TuneKey {
+  int prec, log2n, nx;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(prec, log2n, nx) < std::tie(o.prec, o.log2n, o.nx);
+  }
+};
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int, int>, int> g_tune;
+static std::map<TuneKey, int> g_tune;
+
+static std::string tune_tag() {
+  std::string t = __DATE__ "T" __TIME__;
+  for (char& c : t)
+    if (c == ' ') c = '_';
+  return t;
+}
+
+static std::string tune_device() {
+  int dev = 0;
+  hipDeviceProp_t pr;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess)
+    return "";
+  std::string a = pr.gcnArchName;
+  for (char& c : a)
+    if (c == ' ') c = '_';
+  return a + "/" + std::to_string(pr.multiProcessorCount);
+}
+
+static std::string tune_path() {
+  if (const char* e = getenv("CN_TUNE_CACHE")) return e;
+  const char* x = getenv("XDG_CACHE_HOME");
+  if (x != nullptr && *x) return std::string(x) + "/cn_aao/tune.txt";
+  const char* hm = getenv("HOME");
+  if (hm != nullptr && *hm) return std::string(hm) + "/.cache/cn_aao/tune.txt";
+  return "";
+}
+
+// Compiled candidate of `cands` recorded for key (process map, then file), or -1.
+static int tune_lookup(const TuneKey& k, const std::vector<int>& cands) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(k);
+  if (it != g_tune.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end())
+    return it->second;
+  const std::string path = tune_path(), dev = tune_device(), tag = tune_tag();
+  if (path.empty() || dev.empty()) return -1;
+  FILE* f = fopen(path.c_str(), "r");
+  if (f == nullptr) return -1;
+  int found = -1;
+  char line[512], ftag[128], fdev[256];
+  while (fgets(line, sizeof line, f) != nullptr) {
+    int pr = -1, l2 = -1, nx = -1, B = 0, T = 0;
+    if (sscanf(line, "%127s %255s %d %d %d %d %d", ftag, fdev, &pr, &l2, &nx, &B, &T) != 7) continue;
+    if (tag != ftag || dev != fdev || pr != k.prec || l2 != k.log2n || nx != k.nx) continue;
+    for (int ci : cands) {
+      int cb = 0, ct = 0;
+      if (pc_candidate(k.prec, k.log2n, ci, &cb, &ct) && cb == B && ct == T) found = ci;
+    }
+  }
+  fclose(f);
+  if (found >= 0) g_tune[k] = found;
+  return found;
+}
+
+static void tune_store(const TuneKey& k, int ci) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[k] = ci;
+  const std::string path = tune_path(), dev = tune_device();
+  int B = 0, T = 0;
+  if (path.empty() || dev.empty() || !pc_candidate(k.prec, k.log2n, ci, &B, &T)) return;
+  // create the directory levels of the default location (failures only
+  // mean that nothing is kept)
+  for (size_t p = path.find('/', 1); p != std::string::npos; p = path.find('/', p + 1))
+    (void)mkdir(path.substr(0, p).c_str(), 0755);
+  FILE* f = fopen(path.c_str(), "a");
+  if (f == nullptr) return;
+  fprintf(f, "%s %s %d %d %d %d %d\n", tune_tag().c_str(), dev.c_str(), k.prec, k.log2n, k.nx, B, T);
+  fclose(f);
+}
 
 static cn_status fail(cn_status s, const std::string& msg) {
   g_err = msg;
@@ -104,13 +185,6 @@ struct cn_aao {
   WorkLists wl;
   Launch L{};
   int k2_thr = 32 * 16;  // interface-solve variant (k2_chunk_class)
-  // single-launch apply (one instance, all tiles resident): chosen by the
-  // autotuner; its grid-barrier words and host-visible time-out flag
-  int fused = 0;
-  unsigned long long* bar = nullptr;  // grid-barrier arrival counter
-  int* ferr = nullptr;      // pinned coherent host memory
-  int* ferr_dev = nullptr;
-  unsigned polls = 1u << 22;  // bound of a barrier wait (CN_PC_BARRIER_POLLS)
   std::vector<void*> dev_allocs;
 };
 
@@ -120,7 +194,6 @@ static void release(cn_aao* h) {
   h->wl.release();
   for (void* p : h->dev_allocs) (void)hipFree(p);
   if (h->hsum != nullptr) (void)hipHostFree(h->hsum);
-  if (h->ferr != nullptr) (void)hipHostFree(h->ferr);
   delete h;
 }
 
@@ -265,9 +338,7 @@ const char* cn_last_error(void) { return g_err.c_str(); }
 }  // extern "C"
 
 // Create a handle; force_cand >= 0 skips autotuning and uses that variant.
-// single: a stand-alone handle (may use the single-launch apply), not a
-// batch member.
-static cn_status create_handle(const cn_problem* p, int force_cand, bool single, cn_aao** out) {
+static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out) {
   if (out == nullptr) return fail(CN_EINVAL, "out is NULL");
   *out = nullptr;
   if (p == nullptr) return fail(CN_EINVAL, "problem is NULL");
@@ -510,14 +581,6 @@ static cn_status create_handle(const cn_problem* p, int force_cand, bool single,
   memset(h->hsum, 0, 4 * sizeof(GSummary));
   TRY(hipHostGetDevicePointer((void**)&h->hsum_dev, h->hsum, 0));
   TRY(dalloc(h, &h->d_desc, sizeof(InstDesc)));
-  if (single) {
-    TRY(dalloc(h, &h->bar, sizeof(unsigned long long)));
-    TRY(hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream));
-    TRY(hipHostMalloc((void**)&h->ferr, sizeof(int), hipHostMallocCoherent | hipHostMallocMapped));
-    *h->ferr = 0;
-    TRY(hipHostGetDevicePointer((void**)&h->ferr_dev, h->ferr, 0));
-    if (const char* bp = getenv("CN_PC_BARRIER_POLLS")) h->polls = (unsigned)strtoul(bp, nullptr, 10);
-  }
 
   // -- preconditioner workspace, interface factorisation, variant choice -------------
   TRY(dalloc(h, &pl.spec, spec_elems * rsz));
@@ -557,23 +620,10 @@ static cn_status create_handle(const cn_problem* p, int force_cand, bool single,
       *singular = herr != 0;
       return e;
     };
-    // CN_PC_FUSED=0 / 1 restricts a stand-alone handle to the three-launch /
-    // single-launch apply (the latter where eligible)
-    int fused_mode = single ? 2 : 0;
-    if (const char* fz = getenv("CN_PC_FUSED"); fz != nullptr && single)
-      fused_mode = fz[0] == '0' ? 0 : 1;
-    int best = -1, best_fused = 0;
-    const auto key = std::make_tuple(pl.prec, pl.log2n, nx, fused_mode);
-    if (force_cand < 0) {
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      auto it = g_tune.find(key);
-      if (it != g_tune.end() &&
-          std::find(cands.begin(), cands.end(), it->second / 2) != cands.end()) {
-        best = it->second / 2;
-        best_fused = it->second % 2;
-      }
-    }
-    if (best < 0 && cands.size() == 1 && fused_mode == 0) best = cands[0];
+    int best = -1;
+    const TuneKey key{pl.prec, pl.log2n, nx};
+    if (force_cand < 0) best = tune_lookup(key, cands);
+    if (best < 0 && cands.size() == 1) best = cands[0];
     hipError_t e = hipSuccess;
     if (best < 0) {
       // time every candidate on this problem's shape as it runs inside a
@@ -587,14 +637,6 @@ static cn_status create_handle(const cn_problem* p, int force_cand, bool single,
                                             (size_t)1 << 30);
       if (e == hipSuccess) e = hipMemsetAsync(h->V, 0, flush, h->stream);
       float best_ms = 1e30f;
-      auto fusable = [&](int ci) {
-        int B = 0, T = 0;
-        pc_candidate(pl.prec, pl.log2n, ci, &B, &T);
-        const int P = (nx + B - 1) / B;
-        return pc_fused_ok(pl.prec, pl.log2n, ci, P, P - 1);
-      };
-      bool any_fuse = false;
-      for (int ci : cands) any_fuse = any_fuse || (fused_mode != 0 && fusable(ci));
       for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
         const int ci = cands[c];
         int sing = 0;
@@ -607,75 +649,29 @@ static cn_status create_handle(const cn_problem* p, int force_cand, bool single,
             r = pc_inverse(pl.prec, pl.log2n, ci, h->L, h->wl.I_pc, 0, h->Z, pl.prec, 0, h->stream);
           return r;
         };
-        auto apply1 = [&]() -> hipError_t {
-          return pc_fused(pl.prec, pl.log2n, ci, h->L, pl.P, 0, h->V, 0, h->Z, pl.prec, 0,
-                          h->bar, h->polls, h->ferr_dev, h->stream);
-        };
-        auto time_of = [&](auto&& fn) -> float {
-          float best_t = 1e30f;
-          e = fn();
-          for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-            e = hipMemsetAsync(h->V, 0, flush, h->stream);
-            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-            if (e == hipSuccess) e = fn();
-            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess) best_t = std::min(best_t, ms);
-          }
-          return best_t;
-        };
-        const bool can_fuse = fused_mode != 0 && fusable(ci);
-        // CN_PC_FUSED=1: three launches only where no candidate can fuse
-        if (fused_mode != 1 || !any_fuse) {
-          const float t3 = time_of(apply);
-          if (e == hipSuccess && t3 < best_ms) {
-            best_ms = t3;
-            best = ci;
-            best_fused = 0;
-          }
+        float t3 = 1e30f;
+        e = apply();
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+          e = hipMemsetAsync(h->V, 0, flush, h->stream);
+          if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+          if (e == hipSuccess) e = apply();
+          if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e == hipSuccess) t3 = std::min(t3, ms);
         }
-        if (e == hipSuccess && can_fuse) {
-          // the arrival counter restarts for this candidate's grid size
-          e = hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream);
-          const float t1 = e == hipSuccess ? time_of(apply1) : 0.f;
-          bool timed_out = false;
-          if (e == hipSuccess && *(volatile int*)h->ferr != 0) {
-            // a barrier wait ran out: clear its words, keep three launches
-            e = hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-            *(volatile int*)h->ferr = 0;
-            timed_out = true;
-            if (fused_mode == 1 && any_fuse) {
-              // the three-launch form was not timed for this candidate
-              const float t3 = time_of(apply);
-              if (e == hipSuccess && t3 < best_ms) {
-                best_ms = t3;
-                best = ci;
-                best_fused = 0;
-              }
-            }
-          }
-          if (e == hipSuccess && !timed_out && t1 < best_ms) {
-            best_ms = t1;
-            best = ci;
-            best_fused = 1;
-          }
+        if (e == hipSuccess && t3 < best_ms) {
+          best_ms = t3;
+          best = ci;
         }
       }
       if (e0 != nullptr) (void)hipEventDestroy(e0);
       if (e1 != nullptr) (void)hipEventDestroy(e1);
-      if (e == hipSuccess && best >= 0 && force_cand < 0) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[key] = 2 * best + best_fused;
-      }
+      if (e == hipSuccess && best >= 0 && force_cand < 0) tune_store(key, best);
     }
     int sing = 1;
     if (e == hipSuccess && best >= 0) e = setup(best, &sing);
-    if (e == hipSuccess && h->bar != nullptr)
-      e = hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream);
-    h->fused = best_fused && pc_fused_ok(pl.prec, pl.log2n, best, pl.P, pl.NS) ? 1 : 0;
     free_tmp();
     if (e != hipSuccess) {
       fail(CN_EHIP, std::string("preconditioner set-up: ") + hipGetErrorString(e));
@@ -721,11 +717,6 @@ struct SolveCtx {
   std::vector<long long> off, len;   // packed offsets and lengths
   // batch: captured inner iterations (null: launch kernel by kernel)
   struct GraphCache* graphs = nullptr;
-  // one instance: single-launch apply on P tiles (fused = 0: three launches)
-  int fused = 0, P = 0;
-  unsigned long long* bar = nullptr;
-  unsigned polls = 0;
-  int* ferr_dev = nullptr;
 };
 
 // One captured graph per inner-iteration index j of a batch: the transform
@@ -755,18 +746,12 @@ struct GraphCache {
 static hipError_t enqueue_iteration(SolveCtx& c, int j, int stop_iter, double rtol, int slot,
                                     int seq) {
   hipError_t e = hipSuccess;
-  if (c.fused) {
-    const PcGroup& g = c.groups[0];
-    e = pc_fused(g.prec, g.log2n, g.cand, c.L, c.P, j, nullptr, 0, nullptr, c.L.zf, 0, c.bar,
-                 c.polls, c.ferr_dev, c.s);
-  } else {
-    for (const PcGroup& g : c.groups)
-      if (e == hipSuccess) e = pc_forward(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, 0, c.s);
-    if (e == hipSuccess) e = pc_reduced(c.prec, c.L, c.k2, c.k2_thr, j, 0, c.s);
-    for (const PcGroup& g : c.groups)
-      if (e == hipSuccess)
-        e = pc_inverse(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, c.L.zf, 0, c.s);
-  }
+  for (const PcGroup& g : c.groups)
+    if (e == hipSuccess) e = pc_forward(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, 0, c.s);
+  if (e == hipSuccess) e = pc_reduced(c.prec, c.L, c.k2, c.k2_thr, j, 0, c.s);
+  for (const PcGroup& g : c.groups)
+    if (e == hipSuccess)
+      e = pc_inverse(g.prec, g.log2n, g.cand, c.L, g.items, j, nullptr, c.L.zf, 0, c.s);
   if (e == hipSuccess) e = launch_arnoldi(c.L, c.mv, c.stv, j, stop_iter, rtol, slot, seq, c.s);
   return e;
 }
@@ -1000,11 +985,6 @@ static SolveCtx handle_ctx(cn_aao* h) {
   c.batched = false;
   c.hs = h->hsum;
   c.seqc = &h->seqc;
-  c.fused = h->fused;
-  c.P = h->pl.P;
-  c.bar = h->bar;
-  c.polls = h->polls;
-  c.ferr_dev = h->ferr_dev;
   c.off.assign(1, 0);
   c.len.assign(1, h->n);
   return c;
@@ -1044,23 +1024,9 @@ static void batch_release(cn_batch* b) {
   delete b;
 }
 
-// A grid barrier of the single-launch apply that timed out (its workgroups
-// were not all resident) leaves its counter undefined: clear it, fall back to
-// the three-launch apply for the rest of the handle's life, and report.
-static cn_status check_fused(cn_aao* h) {
-  if (h->ferr == nullptr || *(volatile int*)h->ferr == 0) return CN_OK;
-  HIP_TRY(hipStreamSynchronize(h->stream));
-  HIP_TRY(hipMemsetAsync(h->bar, 0, sizeof(unsigned long long), h->stream));
-  HIP_TRY(hipStreamSynchronize(h->stream));
-  *(volatile int*)h->ferr = 0;
-  h->fused = 0;
-  return fail(CN_EHIP, "single-launch preconditioner: grid barrier timed out (three-launch "
-                       "apply from now on)");
-}
-
 extern "C" {
 
-cn_status cn_aao_create(const cn_problem* p, cn_aao** out) { return create_handle(p, -1, true, out); }
+cn_status cn_aao_create(const cn_problem* p, cn_aao** out) { return create_handle(p, -1, out); }
 
 cn_status cn_aao_destroy(cn_aao* h) {
   if (h == nullptr) return fail(CN_EINVAL, "handle is NULL");
@@ -1073,12 +1039,6 @@ cn_status cn_aao_query(const cn_aao* h, int32_t* tile_cols, int32_t* tiles, int3
   if (tile_cols != nullptr) *tile_cols = h->pl.B;
   if (tiles != nullptr) *tiles = h->pl.P;
   if (threads != nullptr) *threads = h->pl.T;
-  return CN_OK;
-}
-
-cn_status cn_aao_pc_mode(const cn_aao* h, int32_t* single_launch) {
-  if (h == nullptr || single_launch == nullptr) return fail(CN_EINVAL, "NULL argument");
-  *single_launch = h->fused;
   return CN_OK;
 }
 
@@ -1101,13 +1061,7 @@ cn_status cn_matvec(cn_aao* h, const double* x, double* y) {
 
 cn_status cn_pc_apply(cn_aao* h, const double* v, double* z) {
   if (h == nullptr || v == nullptr || z == nullptr) return fail(CN_EINVAL, "NULL argument");
-  CN_TRY(check_fused(h));
   const PcPlan& pl = h->pl;
-  if (h->fused) {
-    HIP_TRY(pc_fused(pl.prec, pl.log2n, pl.cand, h->L, pl.P, 0, v, h->nx, z, 0, h->nx, h->bar,
-                     h->polls, h->ferr_dev, h->stream));
-    return CN_OK;
-  }
   HIP_TRY(pc_forward(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, v, h->nx, h->stream));
   HIP_TRY(pc_reduced(pl.prec, h->L, h->wl.I_k2, h->k2_thr, 0, 1, h->stream));
   HIP_TRY(pc_inverse(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, 0, z, 0, h->nx, h->stream));
@@ -1125,10 +1079,8 @@ cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_o
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
   if (overlaps(b, x, h->n * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
-  CN_TRY(check_fused(h));
   SolveCtx c = handle_ctx(h);
   const cn_status st = run_solve(c, b, x, opts, info, nullptr);
-  CN_TRY(check_fused(h));
   return st;
 }
 
@@ -1154,35 +1106,19 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   bytes[1] = nsep * (6 * rsz + 6 * rsz + 2 * rsz);  // interface values, factor records, S
   bytes[2] = nimg * rsz + (double)pl.F * pl.P * 4 * rsz + n * zes;
   bytes[3] = n * zes + (double)(j + 1) * n * 8;  // z_j and the basis (w is not stored)
-  bytes[4] = (double)(j + 2) * n * 8;
-  bytes[5] = n * zes + (double)(j + 2) * n * 8;  // z_j, the basis, v_{j+1}
-  // the single-launch apply: no tile image through memory
-  bytes[6] = h->fused ? n * 8 + (double)pl.F * pl.P * 10 * rsz + nsep * 14 * rsz + n * zes : 0.0;
-  ms[6] = 0.0;
+  bytes[4] = n * zes + (double)(j + 2) * n * 8;  // z_j, the basis, v_{j+1}
   cn_status rc = CN_OK;
   for (int kk = 0; kk < CN_PROFILE_KERNELS && rc == CN_OK; ++kk) {
-    // the apply the handle's solves run: three launches or the single launch;
-    // kernel 4 no longer exists (the second projection has no pass of its own)
-    if ((kk == 6 && !h->fused) || (kk <= 2 && h->fused) || kk == 4) {
-      ms[kk] = 0.0;
-      if (kk == 4) bytes[kk] = 0.0;
-      continue;
-    }
     hipError_t e = hipEventRecord(ev[0], s);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       switch (kk) {
         case 0: e = pc_forward(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, j, nullptr, 0, s); break;
         case 1: e = pc_reduced(pl.prec, h->L, h->wl.I_k2, h->k2_thr, j, 0, s); break;
         case 2: e = pc_inverse(pl.prec, pl.log2n, pl.cand, h->L, h->wl.I_pc, j, nullptr, zf, 0, s); break;
-        // the three streaming Krylov kernels alone (their one-workgroup
+        // the two streaming Krylov kernels alone (their one-workgroup
         // finishing reductions are left out, so each entry is one kernel)
         case 3: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 1, false); break;
-        case 4: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 2, false); break;
-        case 5: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 4, false); break;
-        case 6:
-          e = pc_fused(pl.prec, pl.log2n, pl.cand, h->L, pl.P, j, nullptr, 0, nullptr, zf, 0, h->bar,
-                       h->polls, h->ferr_dev, s);
-          break;
+        case 4: e = launch_arnoldi(h->L, h->wl.I_mv, h->wl.I_st, j, 1 << 30, 0.0, 0, 0, s, 4, false); break;
       }
     }
     if (e == hipSuccess) e = hipEventRecord(ev[1], s);
@@ -1197,7 +1133,6 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
-  if (rc == CN_OK) rc = check_fused(h);
   return rc;
 }
 
@@ -1229,7 +1164,7 @@ cn_status cn_batch_create(const cn_problem* probs, int32_t count, cn_batch** out
     while ((1 << l2) < probs[i].nt && l2 < 31) ++l2;
     auto it = group_cand.find(l2);
     cn_aao* h = nullptr;
-    const cn_status st = create_handle(&probs[i], it == group_cand.end() ? -1 : it->second, false, &h);
+    const cn_status st = create_handle(&probs[i], it == group_cand.end() ? -1 : it->second, &h);
     if (st != CN_OK) {
       g_err = "problem " + std::to_string(i) + ": " + g_err;
       batch_release(b);

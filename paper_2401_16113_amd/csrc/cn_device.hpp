@@ -76,41 +76,6 @@ __device__ __forceinline__ Cx<R> mul_mi(Cx<R> a) {
   return INV ? Cx<R>{-a.y, a.x} : Cx<R>{a.y, -a.x};
 }
 
-// Device-coherent (agent-scope) stores and loads of complex values, for data
-// that workgroups of one launch exchange across a grid barrier: they write
-// through to, and read from, the level where the XCDs' caches agree, so the
-// barrier itself needs no cache write-back or invalidation.
-__device__ __forceinline__ void st_dev(Cx<float>* p, Cx<float> v) {
-  unsigned long long u;
-  __builtin_memcpy(&u, &v, sizeof(u));
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), u, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_dev(Cx<double>* p, Cx<double> v) {
-  __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ Cx<float> ld_dev(const Cx<float>* p) {
-  const unsigned long long u = __hip_atomic_load(
-      reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  Cx<float> v;
-  __builtin_memcpy(&v, &u, sizeof(v));
-  return v;
-}
-__device__ __forceinline__ Cx<double> ld_dev(const Cx<double>* p) {
-  return Cx<double>{__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                    __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
-}
-// plain (COH = false) or device-coherent (COH = true) access
-template <bool COH, typename R>
-__device__ __forceinline__ void st_x(Cx<R>* p, Cx<R> v) {
-  if constexpr (COH) st_dev(p, v); else *p = v;
-}
-template <bool COH, typename R>
-__device__ __forceinline__ Cx<R> ld_x(const Cx<R>* p) {
-  if constexpr (COH) return ld_dev(p); else return *p;
-}
-
 // Reciprocals.  float64: hardware estimate refined by two Newton steps
 // (error ~1 ulp); float32: hardware estimate (1 ulp).
 __device__ __forceinline__ double rcp(double a) {

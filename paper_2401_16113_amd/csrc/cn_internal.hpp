@@ -125,18 +125,6 @@ hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Item
                       void* z, int zf, int pitch, hipStream_t s);
 // (B, T) of compiled candidate `ci`; false if that candidate is not compiled
 bool pc_candidate(int prec, int log2n, int ci, int* B, int* T);
-// Single-launch apply of one instance (grid = its P tiles, all resident):
-// K1, interface solves and K3 with grid-wide barriers on the arrival counter
-// *bar (zero at first use and whenever P changes; a completed launch leaves
-// it a multiple of P); a barrier wait that exceeds `polls` polls raises *err
-// (host-visible) and the apply is abandoned.
-// v/z override V_j/Z_j as for pc_forward/pc_inverse, with their own pitches.
-hipError_t pc_fused(int prec, int log2n, int cand, const Launch& L, int P, int j,
-                    const double* v, int vpitch, void* z, int zf, int zpitch, unsigned long long* bar,
-                    unsigned polls, int* err, hipStream_t s);
-// true when candidate `cand` may run the single-launch apply on P tiles
-bool pc_fused_ok(int prec, int log2n, int cand, int P, int NS);
-
 // Krylov launchers (cn_krylov.hip)
 constexpr int KT = 512;     // threads per workgroup of the streaming Krylov kernels
 constexpr int KGRID = 512;  // most workgroups of a streaming pass (= partial sums

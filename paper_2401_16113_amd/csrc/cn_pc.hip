@@ -326,29 +326,6 @@ hipError_t pc_inverse_f32(int, int, const Launch&, const Items&, int, void*, int
                           hipStream_t);
 bool pc_candidate_f64(int log2n, int ci, int* B, int* T);
 bool pc_candidate_f32(int log2n, int ci, int* B, int* T);
-hipError_t pc_fused_f64(int, int, const Launch&, int, int, const double*, int, void*, int, int,
-                        unsigned long long*, unsigned, int*, hipStream_t);
-hipError_t pc_fused_f32(int, int, const Launch&, int, int, const double*, int, void*, int, int,
-                        unsigned long long*, unsigned, int*, hipStream_t);
-int pc_fused_capacity_f64(int log2n, int cand, int zf);
-int pc_fused_capacity_f32(int log2n, int cand, int zf);
-
-hipError_t pc_fused(int prec, int log2n, int cand, const Launch& L, int P, int j,
-                    const double* v, int vpitch, void* z, int zf, int zpitch, unsigned long long* bar,
-                    unsigned polls, int* err, hipStream_t s) {
-  return prec ? pc_fused_f32(log2n, cand, L, P, j, v, vpitch, z, zf, zpitch, bar, polls, err, s)
-              : pc_fused_f64(log2n, cand, L, P, j, v, vpitch, z, zf, zpitch, bar, polls, err, s);
-}
-
-bool pc_fused_ok(int prec, int log2n, int cand, int P, int NS) {
-  // every tile resident (both output precisions of a float32 plan), and the
-  // interface lines within the register chunk of the one-wavefront line solver
-  if (P < 1 || NS > 256) return false;
-  int cap = prec ? pc_fused_capacity_f32(log2n, cand, 1) : pc_fused_capacity_f64(log2n, cand, 0);
-  if (prec) cap = std::min(cap, pc_fused_capacity_f32(log2n, cand, 0));
-  return P <= cap;
-}
-
 bool pc_candidate(int prec, int log2n, int ci, int* B, int* T) {
   return prec ? pc_candidate_f32(log2n, ci, B, T) : pc_candidate_f64(log2n, ci, B, T);
 }

@@ -13,13 +13,6 @@ namespace cn {
   case L:                  \
     return cand_info<float, L>(ci, B, T);
 
-#define CN_FUSED_CASE_f32(L) \
-  case L:                   \
-    return fused_cand<float, L>(cand, Lc, P, j, v, vpitch, z, zf, zpitch, bar, polls, err, s);
-#define CN_FCAP_CASE_f32(L) \
-  case L:                  \
-    return fused_capacity<float, L>(cand, zf);
-
 CN_DEFINE_PC_PRECISION(float, f32)
 
 }  // namespace cn

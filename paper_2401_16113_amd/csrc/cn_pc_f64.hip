@@ -13,13 +13,6 @@ namespace cn {
   case L:                  \
     return cand_info<double, L>(ci, B, T);
 
-#define CN_FUSED_CASE_f64(L) \
-  case L:                   \
-    return fused_cand<double, L>(cand, Lc, P, j, v, vpitch, z, zf, zpitch, bar, polls, err, s);
-#define CN_FCAP_CASE_f64(L) \
-  case L:                  \
-    return fused_capacity<double, L>(cand, zf);
-
 CN_DEFINE_PC_PRECISION(double, f64)
 
 }  // namespace cn

@@ -1,6 +1,5 @@
 // Interface (separator) systems of the partitioned step-(b) solve: the
-// per-frequency line solver shared by the stand-alone interface kernel and
-// the single-launch apply.
+// per-frequency line solver.
 #pragma once
 #include "cn_internal.hpp"
 
@@ -83,10 +82,7 @@ struct RedRec {
   Cx<R> a, ap, inv;
 };
 
-// COH: interface values read and separator values written device-coherently
-// (the single-launch apply, where other workgroups of the same launch are the
-// producers and consumers)
-template <typename R, int W, int CH, bool COH = false>
+template <typename R, int W, int CH>
 __device__ __forceinline__ void reduced_line(
     const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const RedRec<R>* __restrict__ rec,
     Cx<double>* __restrict__ rtmp, const double* __restrict__ lo,
@@ -96,8 +92,7 @@ __device__ __forceinline__ void reduced_line(
   const int s0 = min(NS, t * chunk), s1 = min(NS, s0 + chunk);
   auto rho = [&](int s) -> Cx<double> {
     const int is = (s + 1) * B - 1;
-    const Cx<R> d = ld_x<COH>(f + (size_t)s * 3 + 0), yl = ld_x<COH>(f + (size_t)s * 3 + 1),
-                yf = ld_x<COH>(f + (size_t)(s + 1) * 3 + 2);
+    const Cx<R> d = f[(size_t)s * 3 + 0], yl = f[(size_t)s * 3 + 1], yf = f[(size_t)(s + 1) * 3 + 2];
     const double l = lo[is], u = up[is];
     return Cx<double>{(double)d.x + l * (double)yl.x + u * (double)yf.x,
                       (double)d.y + l * (double)yl.y + u * (double)yf.y};
@@ -150,7 +145,7 @@ __device__ __forceinline__ void reduced_line(
     for (int q = CH - 1; q >= 0; --q) {
       S = wide(ap[q]) * S + wide(iv[q]) * rh[q];
       const int s = s0 + q;
-      if (s < s1) st_x<COH>(sep + s, Cx<R>{(R)S.x, (R)S.y});
+      if (s < s1) sep[s] = Cx<R>{(R)S.x, (R)S.y};
     }
   } else {
     Cx<double> A = one, Bv = zero;
@@ -180,7 +175,7 @@ __device__ __forceinline__ void reduced_line(
     for (int s = s1 - 1; s >= s0; --s) {
       const RedRec<R> q = rec[s];
       S = wide(q.ap) * S + wide(q.inv) * rtmp[s];
-      st_x<COH>(sep + s, Cx<R>{(R)S.x, (R)S.y});
+      sep[s] = Cx<R>{(R)S.x, (R)S.y};
     }
   }
 }
