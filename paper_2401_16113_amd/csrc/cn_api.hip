@@ -482,7 +482,7 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   need += (size_t)h->m_max * h->npad * rsz;                           // Z
   need += (size_t)h->npad * sizeof(double);                           // w
   need += spec_elems * rsz;                                           // spectrum tiles
-  need += (size_t)pl.F * ptile_max * 3 * 2 * rsz;                     // interface values
+  need += (size_t)pl.F * ptile_max * 2 * 2 * rsz;                     // interface values
   need += (size_t)pl.F * nsep_max * 2 * rsz + (size_t)pl.F * nsep_max * 4 * sizeof(Cx<double>);
   need += (size_t)pl.F * ptile_max * 4 * sizeof(Cx<double>);          // set-up spikes
   size_t freeb = 0, totalb = 0;
@@ -584,9 +584,10 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
 
   // -- preconditioner workspace, interface factorisation, variant choice -------------
   TRY(dalloc(h, &pl.spec, spec_elems * rsz));
-  TRY(dalloc(h, &pl.iface, (size_t)pl.F * ptile_max * 3 * 2 * rsz));
+  TRY(dalloc(h, &pl.iface, (size_t)pl.F * ptile_max * 2 * 2 * rsz));
   TRY(dalloc(h, &pl.sep, (size_t)pl.F * nsep_max * 2 * rsz));
-  TRY(dalloc(h, &pl.red, (size_t)pl.F * nsep_max * 3 * 2 * rsz));
+  TRY(dalloc(h, &pl.recf, (size_t)pl.F * nsep_max * 2 * 2 * rsz));
+  TRY(dalloc(h, &pl.recb, (size_t)pl.F * nsep_max * 2 * rsz));
   TRY(dalloc(h, &pl.red_tmp, (size_t)pl.F * nsep_max * sizeof(Cx<double>)));
   {
     Cx<double>* spk = nullptr;
@@ -1102,8 +1103,9 @@ cn_status cn_profile_step(cn_aao* h, int32_t j, int32_t reps, double* ms, double
   const double n = (double)h->n;
   const double nimg = (double)pl.P * pl.B * pl.nt;
   const double nsep = (double)pl.F * pl.NS;
-  bytes[0] = n * 8 + nimg * rsz + (double)pl.F * pl.P * 6 * rsz;
-  bytes[1] = nsep * (6 * rsz + 6 * rsz + 2 * rsz);  // interface values, factor records, S
+  bytes[0] = n * 8 + nimg * rsz + (double)pl.F * pl.P * 4 * rsz;
+  // partial right-hand sides (two per separator), factor records (three), S
+  bytes[1] = nsep * (4 * rsz + 6 * rsz + 2 * rsz);
   bytes[2] = nimg * rsz + (double)pl.F * pl.P * 4 * rsz + n * zes;
   bytes[3] = n * zes + (double)(j + 1) * n * 8;  // z_j and the basis (w is not stored)
   bytes[4] = n * zes + (double)(j + 2) * n * 8;  // z_j, the basis, v_{j+1}

@@ -27,10 +27,13 @@ struct PcPlan {
   Cx<float>* tw_f = nullptr;
   Cx<double>* mu = nullptr;                             // lambda1/lambda2, [F]
   Cx<double>* il2 = nullptr;                            // 1/lambda2, [F]
-  void* red = nullptr;  // interface system factors [F][NS] x {a, ap, inv}, precision of the PC
+  // interface system factors [F][NS], precision of the PC: forward {a, inv}
+  // (recf) and backward ap (recb)
+  void* recf = nullptr;
+  void* recb = nullptr;
   Cx<double>* red_tmp = nullptr;
   void* spec = nullptr;                                 // tile images
-  void* iface = nullptr;                                // [F][P][3]
+  void* iface = nullptr;                                // [F][P][2] partial rhs
   void* sep = nullptr;                                  // [F][NS]
 };
 

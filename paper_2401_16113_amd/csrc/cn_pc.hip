@@ -9,7 +9,7 @@
 //     are used, Remark 1), then for every frequency j solves the shifted
 //     system (lambda_{1,j} I - lambda_{2,j} A~) restricted to the tile's
 //     interior columns (step (b), local part) and writes the tile image plus
-//     three interface values per (j, tile).
+//     two partial right-hand sides of the separator systems per (j, tile).
 //  K2 (pc_reduced): for every j, the tridiagonal system of the separator
 //     columns (one per tile boundary), factored once at set-up; solved by two
 //     chunked affine scans.
@@ -93,48 +93,40 @@ __device__ __forceinline__ void block_affine(Cx<double>& A, Cx<double>& Bv, Cx<d
 
 template <typename R, int W, int CH>
 __device__ __forceinline__ void reduced_line_strided(
-    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const RedRec<R>* __restrict__ rec,
-    Cx<double>* __restrict__ rtmp, const double* __restrict__ lo,
-    const double* __restrict__ up, int NS, int B, int t, Cx<double> (*sA)[2 * W + 1],
-    Cx<double> (*sB)[2 * W + 1]) {
-  // rho' of up to four blocks stays in registers; beyond, it goes through
+    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const RedFwd<R>* __restrict__ rf,
+    const Cx<R>* __restrict__ rb, Cx<double>* __restrict__ rtmp, int NS, int t,
+    Cx<double> (*sA)[2 * W + 1], Cx<double> (*sB)[2 * W + 1]) {
+  // rr of up to four blocks stays in registers; beyond, it goes through
   // the (coalesced) scratch array
   constexpr bool KEEP = CH <= 4;
   constexpr int L = 64 * W;
   const int lane = t & 63, wave = t >> 6;
-  auto rho = [&](int s) -> Cx<double> {
-    const int is = (s + 1) * B - 1;
-    const Cx<R> d = f[(size_t)s * 3 + 0], yl = f[(size_t)s * 3 + 1], yf = f[(size_t)(s + 1) * 3 + 2];
-    const double l = lo[is], u = up[is];
-    return Cx<double>{(double)d.x + l * (double)yl.x + u * (double)yf.x,
-                      (double)d.y + l * (double)yl.y + u * (double)yf.y};
-  };
   const Cx<double> zero{0.0, 0.0};
   const Cx<R> onef{R(1), R(0)}, zerof{R(0), R(0)};
   // operands of block q + 1 are loaded while block q is scanned
-  auto fwd_ops = [&](int q, Cx<R>& a, Cx<double>& r) {
+  auto fwd_ops = [&](int q, RedFwd<R>& r, Cx<double>& rho) {
     const int s = q * L + t;
-    a = s < NS ? rec[s].a : onef;
-    r = s < NS ? rho(s) : zero;
+    r = s < NS ? rf[s] : RedFwd<R>{onef, zerof};
+    rho = s < NS ? line_rho(f, s) : zero;
   };
-  auto bwd_ops = [&](int q, Cx<R>& ap, Cx<R>& iv) {
+  auto bwd_ops = [&](int q, Cx<R>& ap) {
     const int s = q * L + t;
-    ap = s < NS ? rec[s].ap : onef;
-    iv = s < NS ? rec[s].inv : zerof;
+    ap = s < NS ? rb[s] : onef;
   };
   Cx<double> rh[KEEP ? CH : 1];
-  Cx<R> an;
-  Cx<double> rn;
-  fwd_ops(0, an, rn);
+  RedFwd<R> rn;
+  Cx<double> pn;
+  fwd_ops(0, rn, pn);
   int buf = 0;
   Cx<double> carry = zero;
 #pragma unroll
   for (int q = 0; q < CH; ++q) {
-    Cx<double> A = wide(an), Bv = rn, At, Bt;
-    if (q + 1 < CH) fwd_ops(q + 1, an, rn);
+    const Cx<double> inv = wide(rn.inv);
+    Cx<double> A = wide(rn.a), Bv = pn, At, Bt;
+    if (q + 1 < CH) fwd_ops(q + 1, rn, pn);
     block_affine<true, W>(A, Bv, At, Bt, lane, wave, sA[buf], sB[buf]);
     buf ^= 1;
-    const Cx<double> r = A * carry + Bv;  // rho'_s
+    const Cx<double> r = inv * (A * carry + Bv);  // rr_s = inv_s rho'_s
     if constexpr (KEEP) {
       rh[q] = r;
     } else {
@@ -143,8 +135,8 @@ __device__ __forceinline__ void reduced_line_strided(
     }
     carry = At * carry + Bt;
   }
-  Cx<R> apn, ivn;
-  bwd_ops(CH - 1, apn, ivn);
+  Cx<R> apn;
+  bwd_ops(CH - 1, apn);
   carry = zero;
 #pragma unroll
   for (int q = CH - 1; q >= 0; --q) {
@@ -155,8 +147,8 @@ __device__ __forceinline__ void reduced_line_strided(
       const int s = q * L + t;
       rq = s < NS ? rtmp[s] : zero;
     }
-    Cx<double> A = wide(apn), Bv = wide(ivn) * rq, At, Bt;
-    if (q > 0) bwd_ops(q - 1, apn, ivn);
+    Cx<double> A = wide(apn), Bv = rq, At, Bt;
+    if (q > 0) bwd_ops(q - 1, apn);
     block_affine<false, W>(A, Bv, At, Bt, lane, wave, sA[buf], sB[buf]);
     buf ^= 1;
     const Cx<double> S = A * carry + Bv;
@@ -178,10 +170,10 @@ __global__ __launch_bounds__(64 * W) void k_pc_reduced_strided(
   if (!standalone && d.st->sum.done) return;
   const int j = wi.y;
   const size_t row = (size_t)j * pl.NS;
-  reduced_line_strided<R, W, CH>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 3,
-                                 (Cx<R>*)pl.sep + row, (const RedRec<R>*)pl.red + row,
-                                 pl.red_tmp + row, pl.lo, pl.up, pl.NS, pl.B, threadIdx.x, sA,
-                                 sB);
+  reduced_line_strided<R, W, CH>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 2,
+                                 (Cx<R>*)pl.sep + row, (const RedFwd<R>*)pl.recf + row,
+                                 (const Cx<R>*)pl.recb + row, pl.red_tmp + row, pl.NS,
+                                 threadIdx.x, sA, sB);
 }
 
 template <typename R, int W, int CH>
@@ -198,9 +190,9 @@ __global__ __launch_bounds__(W == 1 ? K2_THREADS : 64 * W) void k_pc_reduced(
   if (!standalone && d.st->sum.done) return;
   const int j = wi.y;
   const size_t row = (size_t)j * pl.NS;
-  reduced_line<R, W, CH>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 3, (Cx<R>*)pl.sep + row,
-                         (const RedRec<R>*)pl.red + row, pl.red_tmp + row, pl.lo, pl.up, pl.NS,
-                         pl.B, t, sA, sB);
+  reduced_line<R, W, CH>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 2, (Cx<R>*)pl.sep + row,
+                         (const RedFwd<R>*)pl.recf + row, (const Cx<R>*)pl.recb + row,
+                         pl.red_tmp + row, pl.NS, t, sA, sB);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,7 +269,8 @@ template <typename R>
 __global__ void k_setup_reduced(const double* __restrict__ lo, const double* __restrict__ di,
                                 const double* __restrict__ up, const Cx<double>* __restrict__ mu,
                                 const Cx<double>* __restrict__ spk, int P, int NS, int B, int F,
-                                RedRec<R>* __restrict__ rec, int* __restrict__ err) {
+                                RedFwd<R>* __restrict__ rf, Cx<R>* __restrict__ rb,
+                                int* __restrict__ err) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= F) return;
   const Cx<double> m = mu[j];
@@ -305,8 +298,8 @@ __global__ void k_setup_reduced(const double* __restrict__ lo, const double* __r
     if (!(mag > 1e-13 * scl) || !isfinite(mag)) bad = true;
     const Cx<double> inv = cdiv(Cx<double>{1.0, 0.0}, beta);
     const Cx<double> capi = Cm * inv;
-    rec[row + s] = RedRec<R>{Cx<R>{(R)-mlt.x, (R)-mlt.y}, Cx<R>{(R)-capi.x, (R)-capi.y},
-                             Cx<R>{(R)inv.x, (R)inv.y}};
+    rf[row + s] = RedFwd<R>{Cx<R>{(R)-mlt.x, (R)-mlt.y}, Cx<R>{(R)inv.x, (R)inv.y}};
+    rb[row + s] = Cx<R>{(R)-capi.x, (R)-capi.y};
     beta_prev = beta;
     cm_prev = Cm;
   }
@@ -419,10 +412,12 @@ hipError_t pc_setup(PcPlan& pl, Cx<double>* spk, int* err, hipStream_t s) {
     const int t2 = 64, b2 = (pl.F + t2 - 1) / t2;
     if (pl.prec)
       hipLaunchKernelGGL(k_setup_reduced<float>, dim3(b2), dim3(t2), 0, s, pl.lo, pl.di, pl.up,
-                         pl.mu, spk, pl.P, pl.NS, pl.B, pl.F, (RedRec<float>*)pl.red, err);
+                         pl.mu, spk, pl.P, pl.NS, pl.B, pl.F, (RedFwd<float>*)pl.recf,
+                         (Cx<float>*)pl.recb, err);
     else
       hipLaunchKernelGGL(k_setup_reduced<double>, dim3(b2), dim3(t2), 0, s, pl.lo, pl.di, pl.up,
-                         pl.mu, spk, pl.P, pl.NS, pl.B, pl.F, (RedRec<double>*)pl.red, err);
+                         pl.mu, spk, pl.P, pl.NS, pl.B, pl.F, (RedFwd<double>*)pl.recf,
+                         (Cx<double>*)pl.recb, err);
     e = hipGetLastError();
   }
   return e;

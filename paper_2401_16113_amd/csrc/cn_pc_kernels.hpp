@@ -8,7 +8,7 @@
 //     are used, Remark 1), then for every frequency j solves the shifted
 //     system (lambda_{1,j} I - lambda_{2,j} A~) restricted to the tile's
 //     interior columns (step (b), local part) and writes the tile image plus
-//     three interface values per (j, tile).
+//     two partial right-hand sides of the separator systems per (j, tile).
 //  K3 (k_pc_inverse): per tile, adds the separator contributions to the local
 //     solution, runs the inverse FFT, multiplies by Lambda_alpha^{-1}/N_t
 //     (step (c)) and writes z.
@@ -77,10 +77,14 @@ __device__ __forceinline__ void pc_forward_tile(
   __syncthreads();
   fft_tile<Cfg, R, LOG2N, false>(lds, ltw, tw, threadIdx.x);
 
-  // step (b), tile-local part
+  // step (b), tile-local part.  Per frequency the tile leaves two partial
+  // right-hand sides of the separator systems: d + lo y_last for its own
+  // separator (its last column) and up y_first for the separator left of it.
   const bool has_sep = p < P - 1;
   const int nb = has_sep ? B - 1 : ncols;
-  CN_G Cx<R>* ifc = iface + (size_t)p * 3;
+  const R lsep = has_sep ? co[3 * (B - 1)] : R(0);
+  const R uprev = p > 0 ? (R)up[i0 - 1] : R(0);
+  CN_G Cx<R>* ifc = iface + (size_t)p * 2;
   for (int t = tid; t < Cfg::TASKS; t += T) {
     if (t == 0) {
       // j = 0 and j = N/2: real modes, real shifts
@@ -105,10 +109,9 @@ __device__ __forceinline__ void pc_forward_tile(
           if (b == nb - 1) ylast = d[b];
 #pragma unroll
         for (int c = 0; c < NSEQ; ++c) lds[lidx<N>(c, j)] = Cx<R>{d[2 * c], d[2 * c + 1]};
-        CN_G Cx<R>* f = ifc + (size_t)j * P * 3;
-        gst(f, Cx<R>{has_sep ? sepv : R(0), R(0)});
-        gst(f + 1, Cx<R>{ylast, R(0)});
-        gst(f + 2, Cx<R>{d[0], R(0)});
+        CN_G Cx<R>* f = ifc + (size_t)j * P * 2;
+        gst(f, Cx<R>{has_sep ? sepv + lsep * ylast : R(0), R(0)});
+        gst(f + 1, Cx<R>{uprev * d[0], R(0)});
       }
     } else {
       const int j = t;
@@ -135,10 +138,9 @@ __device__ __forceinline__ void pc_forward_tile(
         lds[lidx<N>(c, j)] = d[2 * c];
         lds[lidx<N>(c, N - j)] = d[2 * c + 1];
       }
-      CN_G Cx<R>* f = ifc + (size_t)j * P * 3;
-      gst(f, has_sep ? sepv : Cx<R>{R(0), R(0)});
-      gst(f + 1, ylast);
-      gst(f + 2, d[0]);
+      CN_G Cx<R>* f = ifc + (size_t)j * P * 2;
+      gst(f, has_sep ? sepv + lsep * ylast : Cx<R>{R(0), R(0)});
+      gst(f + 1, uprev * d[0]);
     }
   }
   __syncthreads();

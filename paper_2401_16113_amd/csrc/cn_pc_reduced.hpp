@@ -6,17 +6,21 @@
 namespace cn {
 
 // ---------------------------------------------------------------------------
-// K2: interface (separator) systems, one line (frequency j) per W wavefronts:
-//   rho_s = d_s + lo_s y_last(s) + up_s y_first(s+1)           (s = 0..NS-1)
-//   forward  rho'_s = a_s rho'_{s-1} + rho_s,       a_s  = -m_s
-//   backward S_s    = ap_s S_{s+1} + inv_s rho'_s,  ap_s = -c_s inv_s
-// Each recurrence is an affine scan: every lane composes the maps of its
-// chunk of consecutive separators, a Hillis-Steele scan of the lane maps runs
-// on cross-lane shuffles, the W wave aggregates are chained through LDS
-// (W > 1), then every lane replays its chunk from the carried value.  With
-// CH > 0 a lane loads its whole chunk (<= CH separators) up front and keeps
-// rho' in registers; CH = 0 (very wide instances) streams through the rho'
-// scratch array.  W = 1 packs four lines into a 256-thread workgroup.
+// K2: interface (separator) systems, one line (frequency j) per W wavefronts.
+// K1 leaves two partial right-hand sides per tile p: p1_p = d + lo y_last
+// (its own separator) and p2_p = up y_first (the separator left of it), so
+//   rho_s = p1_s + p2_{s+1}                                      (s = 0..NS-1)
+//   forward  rho'_s = a_s rho'_{s-1} + rho_s,   rr_s = inv_s rho'_s
+//   backward S_s    = ap_s S_{s+1} + rr_s
+// with a_s = -m_s, ap_s = -c_s inv_s from the LU factors of the separator
+// system (computed at set-up).  Each recurrence is an affine scan: every lane
+// composes the maps of its chunk of consecutive separators, a Hillis-Steele
+// scan of the lane maps runs on cross-lane shuffles, the W wave aggregates
+// are chained through LDS (W > 1), then every lane replays its chunk from the
+// carried value.  With CH > 0 a lane loads its whole chunk (<= CH
+// separators) up front and keeps rr in registers; CH = 0 (very wide
+// instances) streams through the rr scratch array.  W = 1 packs four lines
+// into a 256-thread workgroup.
 // ---------------------------------------------------------------------------
 constexpr int K2_THREADS = 256;
 constexpr int K2_STRIDED = 4096;  // variant code offset of the strided layout
@@ -75,43 +79,47 @@ __device__ __forceinline__ Cx<double> wide(Cx<R> v) {
   return Cx<double>{(double)v.x, (double)v.y};
 }
 
-// Factor record of separator s: {a_s, ap_s, inv_s} in the preconditioner's
-// precision (the substitutions run in float64).
+// Forward factor record of separator s, {a_s, inv_s}; the backward one is
+// ap_s alone.  Precision of the preconditioner (the substitutions run in
+// float64).
 template <typename R>
-struct RedRec {
-  Cx<R> a, ap, inv;
+struct RedFwd {
+  Cx<R> a, inv;
 };
 
+// rho_s of one line from the partial right-hand sides f[2p], f[2p+1] of the tiles
+template <typename R>
+__device__ __forceinline__ Cx<double> line_rho(const Cx<R>* __restrict__ f, int s) {
+  const Cx<R> p1 = f[(size_t)2 * s], p2 = f[(size_t)2 * s + 3];
+  return Cx<double>{(double)p1.x + (double)p2.x, (double)p1.y + (double)p2.y};
+}
+
 template <typename R, int W, int CH>
-__device__ __forceinline__ void reduced_line(
-    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const RedRec<R>* __restrict__ rec,
-    Cx<double>* __restrict__ rtmp, const double* __restrict__ lo,
-    const double* __restrict__ up, int NS, int B, int t, Cx<double>* sA, Cx<double>* sB) {
+__device__ __forceinline__ void reduced_line(const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep,
+                                             const RedFwd<R>* __restrict__ rf,
+                                             const Cx<R>* __restrict__ rb,
+                                             Cx<double>* __restrict__ rtmp, int NS, int t,
+                                             Cx<double>* sA, Cx<double>* sB) {
   const int lane = t & 63, wave = t >> 6;
   const int chunk = (NS + 64 * W - 1) / (64 * W);
   const int s0 = min(NS, t * chunk), s1 = min(NS, s0 + chunk);
-  auto rho = [&](int s) -> Cx<double> {
-    const int is = (s + 1) * B - 1;
-    const Cx<R> d = f[(size_t)s * 3 + 0], yl = f[(size_t)s * 3 + 1], yf = f[(size_t)(s + 1) * 3 + 2];
-    const double l = lo[is], u = up[is];
-    return Cx<double>{(double)d.x + l * (double)yl.x + u * (double)yf.x,
-                      (double)d.y + l * (double)yl.y + u * (double)yf.y};
-  };
   const Cx<double> one{1.0, 0.0}, zero{0.0, 0.0};
   if constexpr (CH > 0) {
-    // the forward operands of the lane's chunk are loaded up front
-    // (independent loads, one memory latency), the backward ones once the
-    // forward sweep is done (fewer live registers); padding entries are
-    // identity maps
-    Cx<R> a[CH];
+    // every operand of the lane's chunk is requested up front (independent
+    // loads, one memory latency); padding entries are identity maps
+    Cx<R> a[CH], iv[CH], ap[CH];
     Cx<double> rh[CH];
     const Cx<R> onef{R(1), R(0)}, zerof{R(0), R(0)};
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int s = s0 + q;
-      a[q] = s < s1 ? rec[s].a : onef;
-      rh[q] = s < s1 ? rho(s) : zero;
+      const RedFwd<R> r = s < s1 ? rf[s] : RedFwd<R>{onef, zerof};
+      a[q] = r.a;
+      iv[q] = r.inv;
+      rh[q] = s < s1 ? line_rho(f, s) : zero;
     }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) ap[q] = s0 + q < s1 ? rb[s0 + q] : onef;
     Cx<double> A = one, Bv = zero;
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
@@ -123,27 +131,20 @@ __device__ __forceinline__ void reduced_line(
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       r = wide(a[q]) * r + rh[q];
-      rh[q] = r;  // rho'_s
-    }
-    Cx<R> ap[CH], iv[CH];
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int s = s0 + q;
-      ap[q] = s < s1 ? rec[s].ap : onef;
-      iv[q] = s < s1 ? rec[s].inv : zerof;
+      rh[q] = wide(iv[q]) * r;  // rr_s
     }
     A = one;
     Bv = zero;
 #pragma unroll
     for (int q = CH - 1; q >= 0; --q) {
       const Cx<double> apw = wide(ap[q]);
-      Bv = apw * Bv + wide(iv[q]) * rh[q];
+      Bv = apw * Bv + rh[q];
       A = apw * A;
     }
     Cx<double> S = line_carry<false, W>(A, Bv, lane, wave, sA, sB);
 #pragma unroll
     for (int q = CH - 1; q >= 0; --q) {
-      S = wide(ap[q]) * S + wide(iv[q]) * rh[q];
+      S = wide(ap[q]) * S + rh[q];
       const int s = s0 + q;
       if (s < s1) sep[s] = Cx<R>{(R)S.x, (R)S.y};
     }
@@ -151,30 +152,29 @@ __device__ __forceinline__ void reduced_line(
     Cx<double> A = one, Bv = zero;
 #pragma unroll 4
     for (int s = s0; s < s1; ++s) {
-      const Cx<double> a = wide(rec[s].a);
-      Bv = a * Bv + rho(s);
+      const Cx<double> a = wide(rf[s].a);
+      Bv = a * Bv + line_rho(f, s);
       A = a * A;
     }
     Cx<double> r = line_carry<true, W>(A, Bv, lane, wave, sA, sB);
 #pragma unroll 4
     for (int s = s0; s < s1; ++s) {
-      r = wide(rec[s].a) * r + rho(s);
-      rtmp[s] = r;
+      const RedFwd<R> q = rf[s];
+      r = wide(q.a) * r + line_rho(f, s);
+      rtmp[s] = wide(q.inv) * r;
     }
     A = one;
     Bv = zero;
 #pragma unroll 4
     for (int s = s1 - 1; s >= s0; --s) {
-      const RedRec<R> q = rec[s];
-      const Cx<double> ap = wide(q.ap);
-      Bv = ap * Bv + wide(q.inv) * rtmp[s];
+      const Cx<double> ap = wide(rb[s]);
+      Bv = ap * Bv + rtmp[s];
       A = ap * A;
     }
     Cx<double> S = line_carry<false, W>(A, Bv, lane, wave, sA, sB);
 #pragma unroll 4
     for (int s = s1 - 1; s >= s0; --s) {
-      const RedRec<R> q = rec[s];
-      S = wide(q.ap) * S + wide(q.inv) * rtmp[s];
+      S = wide(rb[s]) * S + rtmp[s];
       sep[s] = Cx<R>{(R)S.x, (R)S.y};
     }
   }

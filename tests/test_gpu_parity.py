@@ -347,7 +347,6 @@ def test_pc_apply_every_variant(nx, nt, prec, monkeypatch):
     v = W.random_vector(inst.n, 11)
     ref = O.pc_apply(*oracle_args(inst), inst.alpha, v)
     ran = 0
-    monkeypatch.setenv("CN_PC_FUSED", "0")  # the three-launch kernels of each variant
     for bcols, thr in VARIANTS:
         monkeypatch.setenv("CN_PC_TILE", f"{bcols},{thr}")
         try:
@@ -377,7 +376,6 @@ def test_interface_solve_variants(nx, nt, tile, prec, monkeypatch):
     systems' condition number, which reaches ~1e6 on this grid); the widest
     through the defining operator of eq. (3.1) (P_alpha z = v)."""
     monkeypatch.setenv("CN_PC_TILE", tile)
-    monkeypatch.setenv("CN_PC_FUSED", "0")
     inst = localvol(nx, nt)
     banner(f"interface solve {prec} nx={nx} tile={tile}")
     s = solver(inst, pc_prec=prec)
@@ -407,7 +405,6 @@ def test_every_interface_solve_variant_matches_oracle(prec, monkeypatch):
     with block scans, rho' in registers or in scratch) forced on the same
     255-separator system, every element against the oracle."""
     monkeypatch.setenv("CN_PC_TILE", "16,256")
-    monkeypatch.setenv("CN_PC_FUSED", "0")
     inst = localvol(4095, 64)
     v = W.random_vector(inst.n, 23)
     ref = O.pc_apply(*oracle_args(inst), inst.alpha, v)
