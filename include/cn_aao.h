@@ -65,7 +65,8 @@ typedef enum {
 
 typedef struct {
     int32_t nx;             /* spatial unknowns N_x >= 1                       */
-    int32_t nt;             /* time steps N_t: power of two in [1, 8192]       */
+    int32_t nt;             /* time steps N_t: power of two in [1, 8192];      */
+                            /* N_t * (N_x rounded up to 16) < 2^29            */
     int32_t m_max;          /* largest GMRES restart length used, 1..64        */
     int32_t flags;          /* CN_FLAG_* bits                                  */
     double T;               /* final time, > 0 (tau = T/nt)                    */
@@ -111,7 +112,25 @@ typedef struct {
                             /*    is no smaller than ||b|| starts from x0 = 0  */
     int32_t flags;          /* CN_SOLVE_* bits, 0 for the defaults             */
     double rtol;            /* stop when ||b - M x||_2 / ||b||_2 <= rtol       */
+    double err_tol;         /* > 0: error-controlled stopping (below); 0: off  */
 } cn_gmres_opts;
+
+/* Error-controlled stopping.  A residual bound does not bound the error: the
+ * error of x is M^{-1} r, and for stiff operators max|M^{-1} r| / max|x| can
+ * be tens of times ||r|| / ||b||.  With err_tol > 0 (and rtol > 0), each
+ * instance first stops at its own target relres <= rt_i <= rtol, where rt_i
+ * is remembered by the handle or batch from its previous solve with the same
+ * rtol and err_tol (initially min(rtol, err_tol / 10)).  Then every
+ * instance's relative max-norm error is estimated as ||r|| max|z| / max|x|
+ * with z = P_alpha^{-1} r / ||r|| (one preconditioner apply and one reduction
+ * on the final residual; P_alpha^{-1} M = I + O(alpha), so the estimate is within a
+ * relative O(alpha) of the error, Sec. 3).  An instance above err_tol
+ * continues from its x with rt_i = relres * err_tol / (4 * estimate) (at
+ * least halving it) and is estimated again, at most three times; the status
+ * is CN_NOT_CONVERGED if an estimate still exceeds err_tol.  The targets
+ * only tighten (they start over when rtol or err_tol change).  Counters in
+ * cn_gmres_info add up over the continuations; err_est holds the last
+ * estimate (-1 when off), err_passes the continuation solves. */
 
 /* cn_batch_solve launches each inner iteration as one captured HIP graph
  * (captured on first use per iteration index, restart length and rtol, and
@@ -124,10 +143,11 @@ typedef struct {
     int32_t matvecs;        /* all products with M, residual checks included  */
     int32_t pc_applies;     /* preconditioner applications                    */
     int32_t x0_rejected;    /* 1: use_x0 = 2 replaced the initial guess by 0  */
-    int32_t reserved;
+    int32_t err_passes;     /* continuation solves of error-controlled stopping */
     double relres_true;     /* ||b - M x|| / ||b|| at return (recomputed)      */
     double relres_est;      /* last least-squares residual estimate / ||b||   */
     double seconds;         /* wall time of the call                          */
+    double err_est;         /* error estimate (err_tol > 0), else -1          */
 } cn_gmres_info;
 
 /* Right-preconditioned restarted GMRES(m) (flexible form: the preconditioned
@@ -147,6 +167,23 @@ cn_status cn_gmres_solve(cn_aao *h, const double *b, double *x,
  * transform kernels.  Any pointer may be NULL. */
 cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
                        int32_t *threads);
+
+/* Inspection of the last cycle's Arnoldi process (for tests; synchronises the
+ * handle's stream).  The Gram-Schmidt step keeps the Gram matrix of the
+ * normalised basis, G_pq = <v_p, v_q>/(||v_p|| ||v_q||), formed from the
+ * stored vectors.  k: the inner iterations of the last cycle of the latest
+ * cn_gmres_solve (its cn_gmres_info.iters when it did not restart; basis
+ * vectors 0..k exist; CN_EINVAL outside [0, m_max]).  cn_aao_cycle returns G
+ * (gram: (k+1)^2 doubles, row-major), the columns of the least-squares
+ * triangular factor after the Givens rotations (rfac: k (k+1) doubles,
+ * column j at j (k+1), rows 0..j) and the scales 1/||v_q|| of the stored,
+ * unnormalised vectors (scale: k+1 doubles; scale[0] is overwritten by the
+ * solve's final residual check and does not describe v_0).  Host arrays,
+ * each may be NULL.  cn_aao_basis copies the stored basis vector q
+ * (0 <= q <= m_max, unnormalised) into out (device, N_t N_x doubles, row
+ * pitch N_x). */
+cn_status cn_aao_cycle(cn_aao *h, int32_t k, double *gram, double *rfac, double *scale);
+cn_status cn_aao_basis(cn_aao *h, int32_t q, double *out);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems of uneven sizes solved together.  Every

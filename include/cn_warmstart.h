@@ -109,6 +109,21 @@ cn_status cn_ws_predict(cn_mlp *net, const float *features, int32_t count, int32
                         int32_t nt, const double *u0, const double *gl, const double *gr,
                         const double *scale, float *coarse, double *x0);
 
+/* The initial guess of every instance of a batch in one call, instances of
+ * uneven N_x and N_t included: the network's forward pass on the batch's
+ * feature rows (features: count x n_in, count = the batch's instances, in
+ * chunks of max_batch) into `coarse` (count x 8192 floats, left holding the
+ * predictions), then each instance's interpolation to its own grid, written
+ * into x0 at the batch's packed offsets (cn_batch_offsets).  u0: the packed
+ * initial conditions (space offsets of cn_batch_offsets), gl, gr: the packed
+ * Dirichlet data at the levels t_{k+1} (instance i's N_t values after those of
+ * the instances before it), scale: count factors.  Every instance needs
+ * N_x + 1 a multiple of 128 (>= 256) and N_t a multiple of 64 (CN_EINVAL
+ * otherwise).  All on the network's stream.  Device pointers throughout. */
+cn_status cn_ws_predict_batch(cn_mlp *net, const float *features, const cn_batch *b,
+                              const double *u0, const double *gl, const double *gr,
+                              const double *scale, float *coarse, double *x0);
+
 const char *cn_ws_last_error(void);
 
 #ifdef __cplusplus

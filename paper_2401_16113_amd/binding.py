@@ -40,15 +40,15 @@ class CnProblem(ctypes.Structure):
 class CnGmresOpts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("rtol", ctypes.c_double)]
+                ("rtol", ctypes.c_double), ("err_tol", ctypes.c_double)]
 
 
 class CnGmresInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("matvecs", ctypes.c_int32), ("pc_applies", ctypes.c_int32),
-                ("x0_rejected", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x0_rejected", ctypes.c_int32), ("err_passes", ctypes.c_int32),
                 ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("err_est", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -71,6 +71,9 @@ def load():
         "cn_aao_destroy": (ctypes.c_int, [vp]),
         "cn_aao_query": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                         ctypes.POINTER(i32)]),
+        "cn_aao_cycle": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                        ctypes.POINTER(dbl)]),
+        "cn_aao_basis": (ctypes.c_int, [vp, i32, vp]),
         "cn_rhs": (ctypes.c_int, [vp, vp, vp, vp]),
         "cn_matvec": (ctypes.c_int, [vp, vp, vp]),
         "cn_pc_apply": (ctypes.c_int, [vp, vp, vp]),
@@ -102,6 +105,7 @@ def load():
         "cn_ws_restrict": (ctypes.c_int, [vp, i32, i32, i32, vp, vp, vp]),
         "cn_ws_interpolate": (ctypes.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "cn_ws_predict": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "cn_ws_predict_batch": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "cn_ws_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -153,6 +157,8 @@ class SolveResult:
     relres_est: float
     seconds: float
     x0_rejected: int = 0
+    err_est: float = -1.0  # error estimate of error-controlled stopping (-1: off)
+    err_passes: int = 0    # continuation solves error-controlled stopping took
 
 
 class Solver:
@@ -178,6 +184,7 @@ class Solver:
         self._h = h
         self.nx, self.nt = nx, int(nt)
         self.n = nx * int(nt)
+        self.m_max = int(m_max)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -195,6 +202,26 @@ class Solver:
         _check(self._lib.cn_aao_query(self._h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(t)),
                "cn_aao_query")
         return {"tile_cols": b.value, "tiles": p.value, "threads": t.value}
+
+    def cycle(self, k: int):
+        """The Arnoldi record of the last cycle, which ran k inner
+        iterations: the Gram matrix of the normalised basis ((k+1) x (k+1)),
+        the triangular factor's columns (k x (k+1), column j in row j) and
+        the basis scales 1/||v_q|| (entry 0 excepted, see cn_aao.h)."""
+        import numpy as np
+        kk = int(k)
+        g = (ctypes.c_double * ((kk + 1) * (kk + 1)))()
+        r = (ctypes.c_double * max(1, kk * (kk + 1)))()
+        sc = (ctypes.c_double * (kk + 1))()
+        _check(self._lib.cn_aao_cycle(self._h, kk, g, r, sc), "cn_aao_cycle")
+        gram = np.array(g[:]).reshape(kk + 1, kk + 1)
+        rfac = np.array(r[:kk * (kk + 1)]).reshape(kk, kk + 1)
+        return gram, rfac, np.array(sc[:])
+
+    def basis(self, q: int, out):
+        """Copy the stored (unnormalised) basis vector q into out."""
+        _check(self._lib.cn_aao_basis(self._h, int(q), _ptr(out)), "cn_aao_basis")
+        return out
 
     def rhs(self, u0, f, out):
         _check(self._lib.cn_rhs(self._h, _ptr(u0), _ptr(f), _ptr(out)), "cn_rhs")
@@ -223,15 +250,19 @@ class Solver:
         return {k: {"ms": ms[i], "bytes": by[i]} for i, k in enumerate(self.KERNELS) if ms[i] > 0}
 
     def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
-              use_x0: bool = False, allow_not_converged: bool = True) -> SolveResult:
+              use_x0: bool = False, allow_not_converged: bool = True,
+              err_tol: float = 0.0) -> SolveResult:
+        """err_tol > 0: error-controlled stopping (the estimated relative
+        max-norm error must also fall below err_tol)."""
         opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=int(use_x0),
-                           flags=0, rtol=float(rtol))
+                           flags=0, rtol=float(rtol), err_tol=float(err_tol))
         info = CnGmresInfo()
         ok = (CN_OK, CN_NOT_CONVERGED) if allow_not_converged else (CN_OK,)
         st = _check(self._lib.cn_gmres_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(opts),
                                              ctypes.byref(info)), "cn_gmres_solve", ok)
         return SolveResult(st, info.iters, info.restarts, info.matvecs, info.pc_applies,
-                           info.relres_true, info.relres_est, info.seconds, info.x0_rejected)
+                           info.relres_true, info.relres_est, info.seconds, info.x0_rejected,
+                           info.err_est, info.err_passes)
 
 
 class Batch:
@@ -284,21 +315,25 @@ class Batch:
         return out
 
     def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
-              use_x0: int = 0, graphs: bool = True):
+              use_x0: int = 0, graphs: bool = True, err_tol: float = 0.0):
         """use_x0: 0 zero start, 1 x holds the guess, 2 guess with fallback
-        to zero; graphs: launch each inner iteration as a captured graph."""
+        to zero; graphs: launch each inner iteration as a captured graph;
+        err_tol > 0: error-controlled stopping per instance."""
         opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=int(use_x0),
-                           flags=0 if graphs else CN_SOLVE_NO_GRAPHS, rtol=float(rtol))
+                           flags=0 if graphs else CN_SOLVE_NO_GRAPHS, rtol=float(rtol),
+                           err_tol=float(err_tol))
         infos = (CnGmresInfo * self.count)()
         total = CnGmresInfo()
         st = _check(self._lib.cn_batch_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(opts), infos,
                                              ctypes.byref(total)), "cn_batch_solve",
                     (CN_OK, CN_NOT_CONVERGED))
-        per = [SolveResult(CN_OK if i.relres_true <= rtol else CN_NOT_CONVERGED, i.iters,
+        per = [SolveResult(CN_OK if i.relres_true <= rtol and (err_tol <= 0 or i.err_est <= err_tol)
+                           else CN_NOT_CONVERGED, i.iters,
                            i.restarts, i.matvecs, i.pc_applies, i.relres_true, i.relres_est,
-                           i.seconds, i.x0_rejected) for i in infos]
+                           i.seconds, i.x0_rejected, i.err_est, i.err_passes) for i in infos]
         tot = SolveResult(st, total.iters, total.restarts, total.matvecs, total.pc_applies,
-                          total.relres_true, total.relres_est, total.seconds, total.x0_rejected)
+                          total.relres_true, total.relres_est, total.seconds, total.x0_rejected,
+                          total.err_est, total.err_passes)
         return tot, per
 
 
@@ -369,6 +404,14 @@ class Mlp:
         _check(self._lib.cn_ws_predict(self._h, _f32(features), int(features.shape[0]), nx, nt,
                                        _ptr(u0), _ptr(gl), _ptr(gr), _ptr(scale), _f32(coarse),
                                        _ptr(x0)), "cn_ws_predict")
+        return x0
+
+    def predict_batch(self, features, batch, u0, gl, gr, scale, coarse, x0):
+        """Forward pass + interpolation of every instance of an uneven batch
+        to its own grid (cn_ws_predict_batch)."""
+        _check(self._lib.cn_ws_predict_batch(self._h, _f32(features), batch._h, _ptr(u0),
+                                             _ptr(gl), _ptr(gr), _ptr(scale), _f32(coarse),
+                                             _ptr(x0)), "cn_ws_predict_batch")
         return x0
 
 

@@ -182,10 +182,15 @@ struct cn_aao {
   // launch context: one descriptor and its work lists
   InstDesc desc{};
   InstDesc* d_desc = nullptr;
+  StopCtl* d_ctl = nullptr;        // stopping controls (device) and their host
+  StopCtl* h_ctl = nullptr;        // staging copy (pinned); see SolveCtx::ctl
+  StopCtl last_ctl{1.0, 0, 0};     // what the device holds
   WorkLists wl;
   Launch L{};
   int k2_thr = 32 * 16;  // interface-solve variant (k2_chunk_class)
   std::vector<void*> dev_allocs;
+  std::vector<double> rt;    // remembered rtol target (SolveCtx::rt)
+  double rt_for[2] = {0.0, 0.0};
 };
 
 static void release(cn_aao* h) {
@@ -194,6 +199,7 @@ static void release(cn_aao* h) {
   h->wl.release();
   for (void* p : h->dev_allocs) (void)hipFree(p);
   if (h->hsum != nullptr) (void)hipHostFree(h->hsum);
+  if (h->h_ctl != nullptr) (void)hipHostFree(h->h_ctl);
   delete h;
 }
 
@@ -237,6 +243,10 @@ static void fill_desc(cn_aao* h, InstDesc* d) {
   d->st = h->st;
   d->host = h->hsum_dev;
   d->zf = h->prec;
+  int zl = 0;
+  while ((1 << zl) < h->pl.B) ++zl;
+  d->zlog = zl;
+  d->ctl = h->d_ctl;
 }
 
 // Work items of one instance (appended with instance index `inst`).
@@ -271,7 +281,9 @@ static hipError_t build_launch(cn_aao* h) {
   // register variant too small for the chunk falls back to the default
   if (const char* f = getenv("CN_K2_CLASS")) {
     const int c = atoi(f);
-    if (c >= 4096) {  // strided layout: blocks of 1024 separators per lane set
+    if (c >= K2_ROUNDS) {  // rounds layout: two rounds of 4096 separators
+      if (c == K2_ROUNDS + 2 && h->pl.NS <= 2 * 4096) h->k2_thr = c;
+    } else if (c >= 4096) {  // strided layout: blocks of 1024 separators per lane set
       const int ch = c - 4096, blocks = (h->pl.NS + 1023) / 1024;
       if ((ch == 1 || ch == 2 || ch == 4 || ch == 8 || ch == 16) && blocks <= ch) h->k2_thr = c;
     } else {
@@ -345,6 +357,9 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   if (p->nx < 1) return fail(CN_EINVAL, "nx must be >= 1");
   if (p->nt < 1 || p->nt > 8192 || (p->nt & (p->nt - 1)) != 0)
     return fail(CN_EINVAL, "nt must be a power of two in [1, 8192]");
+  // the transform reads a tile's column block through 32-bit byte offsets
+  if ((unsigned long long)p->nt * ((p->nx + 15) / 16 * 16) * 8 >= (1ull << 32))
+    return fail(CN_EINVAL, "nt * nx must stay below 2^29 (about 5.4e8 unknowns per instance)");
   if (p->m_max < 1 || p->m_max > MMAX) return fail(CN_EINVAL, "m_max must be in [1, 64]");
   if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(CN_EINVAL, "T must be finite and > 0");
   const bool allow1 = (p->flags & CN_FLAG_ALLOW_ALPHA_ONE) != 0;
@@ -517,6 +532,14 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
     tw[k] = Cx<double>{(double)cosl(ang), (double)sinl(ang)};
     twf[k] = Cx<float>{(float)tw[k].x, (float)tw[k].y};
   }
+  const int wsl = std::min(nt, 64), wsh = nt / wsl;   // two-level twiddle table
+  std::vector<Cx<double>> tw2(wsl + wsh);
+  std::vector<Cx<float>> tw2f(wsl + wsh);
+  for (int e = 0; e < wsl + wsh; ++e) {
+    const int k = e < wsl ? e : (e - wsl) * wsl;
+    tw2[e] = tw[k];
+    tw2f[e] = twf[k];
+  }
   const long double a1 = expl(la / nt);                  // alpha^{1/N_t}
   for (int j = 0; j < pl.F; ++j) {
     // omega^j; the modes j = 0 and j = N_t/2 are real (omega^j = +-1 exactly)
@@ -558,6 +581,10 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   TRY(hipMemcpy(pl.winv, winv.data(), nt * sizeof(double), hipMemcpyHostToDevice));
   TRY(hipMemcpy(pl.tw, tw.data(), nt * sizeof(Cx<double>), hipMemcpyHostToDevice));
   TRY(hipMemcpy(pl.tw_f, twf.data(), nt * sizeof(Cx<float>), hipMemcpyHostToDevice));
+  TRY(dalloc(h, &pl.tw2, (wsl + wsh) * sizeof(Cx<double>)));
+  TRY(dalloc(h, &pl.tw2_f, (wsl + wsh) * sizeof(Cx<float>)));
+  TRY(hipMemcpy(pl.tw2, tw2.data(), (wsl + wsh) * sizeof(Cx<double>), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(pl.tw2_f, tw2f.data(), (wsl + wsh) * sizeof(Cx<float>), hipMemcpyHostToDevice));
   TRY(hipMemcpy(pl.mu, mu.data(), pl.F * sizeof(Cx<double>), hipMemcpyHostToDevice));
   TRY(hipMemcpy(pl.il2, il2.data(), pl.F * sizeof(Cx<double>), hipMemcpyHostToDevice));
 
@@ -581,6 +608,10 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   memset(h->hsum, 0, 4 * sizeof(GSummary));
   TRY(hipHostGetDevicePointer((void**)&h->hsum_dev, h->hsum, 0));
   TRY(dalloc(h, &h->d_desc, sizeof(InstDesc)));
+  TRY(dalloc(h, &h->d_ctl, sizeof(StopCtl)));
+  TRY(hipHostMalloc((void**)&h->h_ctl, sizeof(StopCtl), hipHostMallocDefault));
+  *h->h_ctl = h->last_ctl;
+  TRY(hipMemcpyAsync(h->d_ctl, h->h_ctl, sizeof(StopCtl), hipMemcpyHostToDevice, h->stream));
 
   // -- preconditioner workspace, interface factorisation, variant choice -------------
   TRY(dalloc(h, &pl.spec, spec_elems * rsz));
@@ -716,6 +747,16 @@ struct SolveCtx {
   int* bseq = nullptr;
   std::vector<GSummary*> inst_host;  // per-instance host slots
   std::vector<long long> off, len;   // packed offsets and lengths
+  // per-instance stopping controls: the host staging array (pinned, so its
+  // upload is asynchronous; every solve ends with a stream synchronisation
+  // before the host writes it again), the device array the descriptors point
+  // to, and the last values uploaded (uploads are skipped when unchanged);
+  // rt: the rtol targets error-controlled stopping remembers between solves
+  StopCtl* ctl = nullptr;
+  StopCtl* ctl_dev = nullptr;
+  StopCtl* ctl_last = nullptr;
+  std::vector<double>* rt = nullptr;
+  double* rt_for = nullptr;  // the (rtol, err_tol) the targets were made for
   // batch: captured inner iterations (null: launch kernel by kernel)
   struct GraphCache* graphs = nullptr;
 };
@@ -793,11 +834,30 @@ static cn_status launch_iteration_graph(SolveCtx& c, int j, int stop_iter, doubl
   return CN_OK;
 }
 
+// Summary slot `slot` of instance i (read after the stream has drained).
+static const volatile GSummary* inst_slot(const SolveCtx& c, int i, int slot) {
+  return (c.batched ? c.inst_host[i] : c.hs) + slot;
+}
+
+// Copy the stopping controls to the device (if they changed).
+static hipError_t upload_ctl(SolveCtx& c) {
+  const size_t bytes = (size_t)c.L.ninst * sizeof(StopCtl);
+  if (memcmp(c.ctl, c.ctl_last, bytes) == 0) return hipSuccess;
+  memcpy(c.ctl_last, c.ctl, bytes);
+  return hipMemcpyAsync(c.ctl_dev, c.ctl, bytes, hipMemcpyHostToDevice, c.s);
+}
+
+// One restarted GMRES solve of every instance of the context; instance i
+// stops at relres <= rtol * (*c.ctl)[i].rscale (uploaded by the caller).
+// Fills infos[0..ninst).
 static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmres_opts* opts,
-                           cn_gmres_info* infos, cn_gmres_info* total) {
+                           cn_gmres_info* infos) {
   const auto wall0 = std::chrono::steady_clock::now();
   const int ninst = c.L.ninst;
   const double rtol = opts->rtol;
+  std::vector<double> fac(ninst);
+  for (int i = 0; i < ninst; ++i) fac[i] = c.ctl[i].rscale;
+  const double rtol_min = rtol * *std::min_element(fac.begin(), fac.end());
   std::vector<int> iters(ninst, 0), pcs(ninst, 0), mvs(ninst, 1), rest(ninst, 0);
   std::vector<double> est(ninst, 0.0);
   std::vector<GSummary> cur(ninst), fin(ninst);
@@ -850,7 +910,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
           prev = (r0->seq == seq_res && r0->relres > 0.0) ? r0->relres : 1.0;
         }
         const double rate = prev > 0.0 ? ests[j - 1] / prev : 1.0;
-        if (j + 1 < m_eff && ests[j - 1] * rate < 50.0 * rtol) {
+        if (j + 1 < m_eff && ests[j - 1] * rate < 50.0 * rtol_min) {
           // one instance: queue the cycle end behind iteration j before
           // waiting (its kernels return at entry unless the cycle stopped),
           // so a converged solve goes on without a host round trip
@@ -923,7 +983,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
       pcs[i] += k;
       mvs[i] += k + 1;
       kmax = std::max(kmax, k);
-      if (!(cur[i].relres <= rtol)) all_conv = false;
+      if (!(cur[i].relres <= rtol * fac[i])) all_conv = false;
     }
     done_iters += kmax;
     if (kmax == 0 || all_conv || done_iters >= opts->max_iters) break;
@@ -934,7 +994,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
       ++mvs[0];
     }
     for (int i = 0; i < ninst; ++i)
-      if (!(cur[i].relres <= rtol)) ++rest[i];
+      if (!(cur[i].relres <= rtol * fac[i])) ++rest[i];
   }
   // b = 0: the solution is x = 0 whatever the initial guess
   for (int i = 0; i < ninst; ++i) {
@@ -947,20 +1007,132 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
   HIP_TRY(hipStreamSynchronize(c.s));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
   bool ok = true;
-  cn_gmres_info tot{0, 0, 0, 0, 0, 0, 0.0, 0.0, secs};
   for (int i = 0; i < ninst; ++i) {
-    cn_gmres_info in;
+    cn_gmres_info in{};
     in.iters = iters[i];
     in.restarts = rest[i];
     in.matvecs = mvs[i];
     in.pc_applies = pcs[i];
     in.x0_rejected = cur[i].x0_rejected;
-    in.reserved = 0;
     in.relres_true = cur[i].relres;
     in.relres_est = iters[i] > 0 ? est[i] : cur[i].relres;
     in.seconds = secs;
+    in.err_est = -1.0;
+    infos[i] = in;
+    if (!(cur[i].relres <= rtol * fac[i])) ok = false;
+  }
+  return ok ? CN_OK : CN_NOT_CONVERGED;
+}
+
+// Relative max-norm error estimate of every instance's x whose est_skip is 0
+// (see launch_err_estimate): r = b - M x in V_0 (a batch's last cycle end
+// left it there; one instance forms it again), the preconditioner of
+// iteration 0 on it, the estimate into summary slot 2.  err[i] < 0: not
+// estimated.
+static cn_status estimate_errors(SolveCtx& c, const double* b, double* x, std::vector<double>* err) {
+  const int seq = c.batched ? 0 : ++(*c.seqc);
+  if (c.batched)
+    HIP_TRY(launch_err_begin(c.L, c.s));
+  else
+    HIP_TRY(launch_residual(c.L, c.mv, c.stv, b, x, 0, -1.0, 2, seq, c.s, 0));
+  for (const PcGroup& g : c.groups)
+    HIP_TRY(pc_forward(g.prec, g.log2n, g.cand, c.L, g.items, 0, nullptr, 0, c.s));
+  HIP_TRY(pc_reduced(c.prec, c.L, c.k2, c.k2_thr, 0, 0, c.s));
+  for (const PcGroup& g : c.groups)
+    HIP_TRY(pc_inverse(g.prec, g.log2n, g.cand, c.L, g.items, 0, nullptr, c.L.zf, 0, c.s));
+  HIP_TRY(launch_err_estimate(c.L, c.stv, x, 2, seq, c.s));
+  HIP_TRY(hipStreamSynchronize(c.s));
+  std::atomic_thread_fence(std::memory_order_acquire);
+  for (int i = 0; i < c.L.ninst; ++i) (*err)[i] = inst_slot(c, i, 2)->err;
+  return CN_OK;
+}
+
+// The solve of cn_gmres_solve / cn_batch_solve.
+//
+// Error-controlled stopping (opts->err_tol > 0): instance i first stops at its
+// remembered target rt_i <= rtol (on a handle's or batch's first such solve
+// with these rtol and err_tol, min(rtol, err_tol / 10)).  Then every
+// instance's error is estimated; an instance above err_tol continues from
+// its x with the target relres times err_tol / (4 * estimate) (on the
+// assumption that its error falls in proportion to its residual, at least
+// halving the target), and only the instances that continued are estimated
+// again, at most kErrRounds times.  The targets only tighten and are kept for
+// the next solve (a relaxed target can miss by a whole inner iteration's
+// reduction and cost a continuation pass on the next solve).
+constexpr int kErrRounds = 3;
+static cn_status solve_driver(SolveCtx& c, const double* b, double* x, const cn_gmres_opts* opts,
+                              cn_gmres_info* infos, cn_gmres_info* total) {
+  const auto wall0 = std::chrono::steady_clock::now();
+  const int ninst = c.L.ninst;
+  const double rtol = opts->rtol, etol = opts->err_tol;
+  const bool ec = etol > 0.0 && rtol > 0.0;
+  StopCtl* ctl = c.ctl;
+  std::vector<double>& rt = *c.rt;
+  for (int i = 0; i < ninst; ++i) ctl[i] = StopCtl{1.0, 0, 0};
+  if (ec) {
+    if ((int)rt.size() != ninst || c.rt_for[0] != rtol || c.rt_for[1] != etol) {
+      rt.assign(ninst, std::min(rtol, 0.1 * etol));
+      c.rt_for[0] = rtol;
+      c.rt_for[1] = etol;
+    }
+    for (int i = 0; i < ninst; ++i) ctl[i].rscale = std::min(1.0, rt[i] / rtol);
+  }
+  HIP_TRY(upload_ctl(c));
+  std::vector<cn_gmres_info> inf(ninst), more(ninst);
+  int passes = 0;
+  cn_status rc = run_solve(c, b, x, opts, inf.data());
+  if (rc == CN_OK && ec) {
+    std::vector<double> err(ninst, 0.0);
+    cn_gmres_opts o2 = *opts;
+    o2.use_x0 = 1;
+    for (int round = 0;; ++round) {
+      CN_TRY(estimate_errors(c, b, x, &err));
+      bool above = false;
+      for (int i = 0; i < ninst; ++i) {
+        StopCtl& ci = ctl[i];
+        if (ci.est_skip) continue;
+        inf[i].err_est = err[i];
+        if (err[i] <= etol) {
+          ci.est_skip = 1;  // accurate: nothing more to do
+        } else {
+          above = true;
+          const double want = inf[i].relres_true * 0.25 * etol / err[i];
+          ci.rscale = std::max(1e-8, std::min(0.5 * ci.rscale, want / rtol));
+          rt[i] = rtol * ci.rscale;
+        }
+      }
+      if (!above) break;
+      if (round == kErrRounds) {
+        rc = CN_NOT_CONVERGED;
+        break;
+      }
+      // instances already accurate stop at their first residual (their
+      // threshold is left loose enough to hold: relres <= rtol)
+      for (int i = 0; i < ninst; ++i)
+        if (ctl[i].est_skip) ctl[i].rscale = 1.0;
+      HIP_TRY(upload_ctl(c));
+      rc = run_solve(c, b, x, &o2, more.data());
+      ++passes;
+      for (int i = 0; i < ninst; ++i) {
+        if (ctl[i].est_skip) continue;
+        ++inf[i].err_passes;
+        inf[i].iters += more[i].iters;
+        inf[i].restarts += more[i].restarts;
+        inf[i].matvecs += more[i].matvecs;
+        inf[i].pc_applies += more[i].pc_applies;
+        inf[i].relres_true = more[i].relres_true;
+        if (more[i].iters > 0) inf[i].relres_est = more[i].relres_est;
+      }
+      if (rc != CN_OK) break;
+    }
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  cn_gmres_info tot{};
+  tot.err_est = -1.0;
+  for (int i = 0; i < ninst; ++i) {
+    cn_gmres_info& in = inf[i];
+    in.seconds = secs;
     if (infos != nullptr) infos[i] = in;
-    if (!(cur[i].relres <= rtol)) ok = false;
     tot.iters = std::max(tot.iters, in.iters);
     tot.restarts = std::max(tot.restarts, in.restarts);
     tot.matvecs += in.matvecs;
@@ -968,9 +1140,12 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
     tot.x0_rejected += in.x0_rejected;
     tot.relres_true = std::max(tot.relres_true, in.relres_true);
     tot.relres_est = std::max(tot.relres_est, in.relres_est);
+    tot.err_est = std::max(tot.err_est, in.err_est);
   }
+  tot.seconds = secs;
+  tot.err_passes = passes;
   if (total != nullptr) *total = tot;
-  return ok ? CN_OK : CN_NOT_CONVERGED;
+  return rc;
 }
 
 static SolveCtx handle_ctx(cn_aao* h) {
@@ -988,6 +1163,11 @@ static SolveCtx handle_ctx(cn_aao* h) {
   c.seqc = &h->seqc;
   c.off.assign(1, 0);
   c.len.assign(1, h->n);
+  c.ctl = h->h_ctl;
+  c.ctl_dev = h->d_ctl;
+  c.ctl_last = &h->last_ctl;
+  c.rt = &h->rt;
+  c.rt_for = h->rt_for;
   return c;
 }
 
@@ -1010,6 +1190,13 @@ struct cn_batch {
   int* dcounter = nullptr;
   int bseq = 0;
   GraphCache graphs;
+  long long* d_layout = nullptr;   // BatchLayout::dev
+  std::vector<int> nxs, nts;       // per-instance N_x, N_t (host)
+  StopCtl* d_ctl = nullptr;        // stopping controls (SolveCtx::ctl): device,
+  StopCtl* h_ctl = nullptr;        // pinned host staging,
+  std::vector<StopCtl> last_ctl;   // last uploaded
+  std::vector<double> rt;          // remembered rtol targets (SolveCtx::rt)
+  double rt_for[2] = {0.0, 0.0};
 };
 
 static void batch_release(cn_batch* b) {
@@ -1020,6 +1207,9 @@ static void batch_release(cn_batch* b) {
   b->wl.release();
   for (int2* p : b->pc_lists) (void)hipFree(p);
   if (b->d_desc != nullptr) (void)hipFree(b->d_desc);
+  if (b->d_ctl != nullptr) (void)hipFree(b->d_ctl);
+  if (b->h_ctl != nullptr) (void)hipHostFree(b->h_ctl);
+  if (b->d_layout != nullptr) (void)hipFree(b->d_layout);
   if (b->dcounter != nullptr) (void)hipFree(b->dcounter);
   if (b->bh != nullptr) (void)hipHostFree(b->bh);
   delete b;
@@ -1040,6 +1230,33 @@ cn_status cn_aao_query(const cn_aao* h, int32_t* tile_cols, int32_t* tiles, int3
   if (tile_cols != nullptr) *tile_cols = h->pl.B;
   if (tiles != nullptr) *tiles = h->pl.P;
   if (threads != nullptr) *threads = h->pl.T;
+  return CN_OK;
+}
+
+cn_status cn_aao_cycle(cn_aao* h, int32_t k, double* gram, double* rfac, double* scale) {
+  if (h == nullptr) return fail(CN_EINVAL, "handle is NULL");
+  if (k < 0 || k > h->m_max) return fail(CN_EINVAL, "k must be in [0, m_max]");
+  std::vector<char> buf(sizeof(GState));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(buf.data(), h->st, sizeof(GState), hipMemcpyDeviceToHost));
+  const GState& st = *reinterpret_cast<const GState*>(buf.data());
+  const int kk = k;
+  for (int p = 0; p <= kk; ++p) {
+    if (scale != nullptr) scale[p] = st.vscale[p];
+    for (int q = 0; q <= kk && gram != nullptr; ++q) gram[p * (kk + 1) + q] = st.gram[p * NVMAX + q];
+  }
+  for (int j = 0; j < kk && rfac != nullptr; ++j)
+    for (int q = 0; q <= kk; ++q) rfac[j * (kk + 1) + q] = q <= j ? st.H[j * (MMAX + 1) + q] : 0.0;
+  return CN_OK;
+}
+
+cn_status cn_aao_basis(cn_aao* h, int32_t q, double* out) {
+  if (h == nullptr || out == nullptr) return fail(CN_EINVAL, "NULL argument");
+  if (q < 0 || q > h->m_max) return fail(CN_EINVAL, "basis index out of range");
+  HIP_TRY(hipMemcpy2DAsync(out, (size_t)h->nx * sizeof(double), h->V + (size_t)q * h->npad,
+                           (size_t)h->ldx * sizeof(double), (size_t)h->nx * sizeof(double), h->nt,
+                           hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
   return CN_OK;
 }
 
@@ -1079,9 +1296,11 @@ cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_o
   if (opts->flags & ~CN_SOLVE_NO_GRAPHS) return fail(CN_EINVAL, "unknown bits in opts->flags");
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
+  if (!(opts->err_tol >= 0.0) || !std::isfinite(opts->err_tol))
+    return fail(CN_EINVAL, "opts->err_tol must be finite and >= 0");
   if (overlaps(b, x, h->n * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
   SolveCtx c = handle_ctx(h);
-  const cn_status st = run_solve(c, b, x, opts, info, nullptr);
+  const cn_status st = solve_driver(c, b, x, opts, info, nullptr);
   return st;
 }
 
@@ -1201,7 +1420,13 @@ cn_status cn_batch_create(const cn_problem* probs, int32_t count, cn_batch** out
     append_items(desc[i], i, &pcs[b->inst[i]->pl.log2n], &k2, &mv, &stv);
     max_ns = std::max(max_ns, desc[i].pl.NS);
   }
-  hipError_t e = hipMalloc((void**)&b->d_desc, count * sizeof(InstDesc));
+  b->last_ctl.assign(count, StopCtl{1.0, 0, 0});
+  hipError_t e = hipMalloc((void**)&b->d_ctl, count * sizeof(StopCtl));
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_ctl, b->last_ctl.data(), count * sizeof(StopCtl), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_ctl, count * sizeof(StopCtl), hipHostMallocDefault);
+  for (int i = 0; i < count; ++i) desc[i].ctl = b->d_ctl + i;
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_desc, count * sizeof(InstDesc));
   if (e == hipSuccess)
     e = hipMemcpy(b->d_desc, desc.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = upload_items(k2, &b->wl.k2, &b->wl.I_k2);
@@ -1216,6 +1441,26 @@ cn_status cn_batch_create(const cn_problem* probs, int32_t count, cn_batch** out
     b->groups.push_back(PcGroup{b->prec, kv.first, group_cand[kv.first], it});
   }
   b->k2_thr = k2_chunk_class(max_ns, b->prec);
+  {
+    // layout for per-instance kernels outside the solver (the learned guess)
+    std::vector<long long> lay(1 + 5 * (size_t)count);
+    long long go = 0;
+    for (int i = 0; i < count; ++i) {
+      b->nxs.push_back(b->inst[i]->nx);
+      b->nts.push_back(b->inst[i]->nt);
+    }
+    for (int i = 0; i <= count; ++i) lay[i] = b->off[i];
+    for (int i = 0; i < count; ++i) {
+      lay[count + 1 + i] = b->uoff[i];
+      lay[2 * count + 1 + i] = go;
+      go += b->nts[i];
+      lay[3 * count + 1 + i] = b->nxs[i];
+      lay[4 * count + 1 + i] = b->nts[i];
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_layout, lay.size() * sizeof(long long));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_layout, lay.data(), lay.size() * sizeof(long long), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMalloc((void**)&b->dcounter, sizeof(int));
   if (e == hipSuccess) e = hipMemset(b->dcounter, 0, sizeof(int));
   if (e == hipSuccess)
@@ -1234,6 +1479,20 @@ cn_status cn_batch_create(const cn_problem* probs, int32_t count, cn_batch** out
   *out = b;
   return CN_OK;
 }
+
+}  // extern "C"
+
+bool cn::batch_layout(const cn_batch* b, BatchLayout* out) {
+  if (b == nullptr || out == nullptr || b->d_layout == nullptr) return false;
+  out->dev = b->d_layout;
+  out->count = (int)b->inst.size();
+  out->nx = b->nxs.data();
+  out->nt = b->nts.data();
+  out->total = b->off.back();
+  return true;
+}
+
+extern "C" {
 
 cn_status cn_batch_destroy(cn_batch* b) {
   if (b == nullptr) return fail(CN_EINVAL, "batch is NULL");
@@ -1271,6 +1530,8 @@ cn_status cn_batch_solve(cn_batch* b, const double* bp, double* xp, const cn_gmr
   if (opts->flags & ~CN_SOLVE_NO_GRAPHS) return fail(CN_EINVAL, "unknown bits in opts->flags");
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
+  if (!(opts->err_tol >= 0.0) || !std::isfinite(opts->err_tol))
+    return fail(CN_EINVAL, "opts->err_tol must be finite and >= 0");
   if (overlaps(bp, xp, b->off.back() * sizeof(double))) return fail(CN_EINVAL, "b and x overlap");
   SolveCtx c;
   c.s = b->stream;
@@ -1292,7 +1553,12 @@ cn_status cn_batch_solve(cn_batch* b, const double* bp, double* xp, const cn_gmr
     c.off.push_back(b->off[i]);
     c.len.push_back(b->inst[i]->n);
   }
-  return run_solve(c, bp, xp, opts, infos, total);
+  c.ctl = b->h_ctl;
+  c.ctl_dev = b->d_ctl;
+  c.ctl_last = b->last_ctl.data();
+  c.rt = &b->rt;
+  c.rt_for = b->rt_for;
+  return solve_driver(c, bp, xp, opts, infos, total);
 }
 
 }  // extern "C"

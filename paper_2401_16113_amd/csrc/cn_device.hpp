@@ -156,6 +156,42 @@ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int clog2(int v) { return v <= 1 ? 0 : 1 + clog2(v / 2); }
 
+// Reads through a buffer resource: a uniform base address, a per-thread
+// 32-bit byte offset and a uniform 32-bit byte offset per load, so a run of
+// loads whose addresses differ by uniform amounts needs one address register
+// in all (global loads take a 64-bit address register pair each).  The
+// caller keeps every offset below 2^32 bytes (the resource's range is not
+// used as a bound).  Word 3 = 0x00020000: 32-bit data format, which raw
+// (untyped) loads of the CDNA family require.
+struct BufRd {
+  __amdgpu_buffer_rsrc_t r;
+  template <typename P>
+  __device__ __forceinline__ explicit BufRd(P base)
+      : r(__builtin_amdgcn_make_buffer_rsrc((void*)(base), (short)0, -1, 0x00020000)) {}
+  __device__ __forceinline__ double f64(unsigned voff, unsigned soff) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+};
+
+// Two-level tables of a length-N sequence (N a power of two): entry k is
+// lo[k mod SL] * hi[k / SL], with lo = the first SL entries and hi = every
+// SL-th one, SL = min(N, 64).  Used for the twiddles when the full table
+// would cost the tile a workgroup per CU: 64 + N/64 entries instead of N,
+// at the price of one extra product (about one unit of rounding).
+template <int N>
+struct Split2 {
+  static constexpr int SL = N < 64 ? N : 64;
+  static constexpr int LOGSL = clog2(SL);
+  static constexpr int SH = N / SL;
+  static constexpr int SIZE = SL + SH;
+};
+
+constexpr int kLdsCap = 160 * 1024;  // LDS of a gfx950 compute unit (and most per workgroup)
+// a table of `extra` bytes beside `base` fits and keeps `wgs` workgroups per CU
+constexpr bool lds_keeps(int base, int extra, int wgs) {
+  return base + extra <= kLdsCap && kLdsCap / (base + extra) >= wgs;
+}
+
 // Default tile width B (columns, even) and workgroup size T of the transform
 // kernels: the widest tile whose image fits 128 KB of LDS, ~16 complex
 // elements per thread.
@@ -179,18 +215,21 @@ struct PcCfg {
   static constexpr int SSTRIDE = N + N / 16 + 1;
   static constexpr int LDS_ELEMS = NSEQ * SSTRIDE;
   static constexpr int LDS_BASE = LDS_ELEMS * 2 * (int)sizeof(R) + 3 * B * (int)sizeof(R);
-  // the twiddle table e^{-2 pi i m/N} is staged in LDS when it fits beside
-  // the tile (its global reads would otherwise sit on every FFT pass): the
-  // whole table, else its first half (w^{m+N/2} = -w^m), else none
+  // the twiddle table e^{-2 pi i m/N} sits in LDS (its global reads would
+  // otherwise sit on every FFT pass): whole, first half (w^{m+N/2} = -w^m) or
+  // two-level, the largest that keeps the workgroups per CU the tile allows
   static constexpr int TW_BYTES = N * 2 * (int)sizeof(R);
-  static constexpr int TWMODE = LDS_BASE + TW_BYTES <= 150 * 1024       ? 2
-                                : LDS_BASE + TW_BYTES / 2 <= 150 * 1024 ? 1
-                                                                        : 0;
-  static constexpr bool TWL = TWMODE > 0;
-  static constexpr int TWN = TWMODE == 2 ? N : (TWMODE == 1 ? (N > 1 ? N / 2 : 1) : 1);
-  static constexpr int LDS_BYTES = LDS_BASE + (TWL ? TWN * 2 * (int)sizeof(R) : 0);
+  static constexpr int TW2_BYTES = Split2<N>::SIZE * 2 * (int)sizeof(R);
+  static constexpr int WGS = kLdsCap / (LDS_BASE + TW2_BYTES);
+  static constexpr int TWMODE = lds_keeps(LDS_BASE, TW_BYTES, WGS)       ? 2
+                                : lds_keeps(LDS_BASE, TW_BYTES / 2, WGS) ? 1
+                                                                         : 3;
+  static constexpr bool TWL = true;
+  static constexpr int TWN = TWMODE == 2 ? N : (TWMODE == 1 ? cmax(1, N / 2) : Split2<N>::SIZE);
+  static constexpr int LDS_BYTES = LDS_BASE + TWN * 2 * (int)sizeof(R);
   static constexpr int TWPT = (TWN + T - 1) / T;            // table entries per thread
   static constexpr int TASKS = N >= 2 ? N / 2 : 1;          // step-(b) tasks
+  static constexpr int NTK = (TASKS + T - 1) / T;           // tasks per thread
 };
 
 // Candidate (B, T) variants the create-time autotuner times; index 0 is the
@@ -208,7 +247,7 @@ struct PcCand {
   using Cfg = PcCfg<R, LOG2N, B, T>;
   static constexpr bool dup = CI != 0 && B == PcDefault<R, LOG2N>::B && T == PcDefault<R, LOG2N>::T;
   static constexpr bool ok =
-      CI == 0 || (!dup && LOG2N >= 6 && LOG2N <= 12 && Cfg::LDS_BYTES <= 150 * 1024 &&
+      CI == 0 || (!dup && LOG2N >= 6 && LOG2N <= 12 && Cfg::LDS_BYTES <= kLdsCap &&
                   Cfg::ELEMS >= T && (T < 1024 || B * (int)sizeof(R) <= 64));
 };
 
@@ -313,6 +352,16 @@ struct TwTab {
   }
 };
 
+// Twiddle w^m from the two-level table: w^{m mod SL} w^{SL floor(m/SL)}.
+template <typename R, int N>
+struct TwTab2 {
+  const Cx<R>* t;
+  __device__ __forceinline__ Cx<R> operator()(int m) const {
+    using S = Split2<N>;
+    return t[m & (S::SL - 1)] * t[S::SL + (m >> S::LOGSL)];
+  }
+};
+
 template <typename R, int LOG2N, int NSEQ, int T, bool INV, int MAXLOG, int DONE, typename TW>
 __device__ __forceinline__ void fft_run(Cx<R>* lds, const TW& tw, int tid) {
   if constexpr (DONE < LOG2N) {
@@ -322,19 +371,20 @@ __device__ __forceinline__ void fft_run(Cx<R>* lds, const TW& tw, int tid) {
   }
 }
 
-// FFT with the twiddles from LDS (staged as Cfg says) or from global memory.
-template <typename Cfg, typename R, int LOG2N, bool INV>
+// FFT with the twiddles from the LDS table staged as Cfg says.
 // tid: the thread index the passes derive their element indices from (one
 // opaque value per transform, see phase_tid)
+template <typename Cfg, typename R, int LOG2N, bool INV>
 __device__ __forceinline__ void fft_tile(Cx<R>* lds, const Cx<R>* ltw, const Cx<R>* __restrict__ tw,
                                          int tid) {
   constexpr int N = 1 << LOG2N;
+  (void)tw;
   if constexpr (Cfg::TWMODE == 2) {
     fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, false>{ltw}, tid);
   } else if constexpr (Cfg::TWMODE == 1) {
     fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, true>{ltw}, tid);
   } else {
-    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab<R, N, false>{tw}, tid);
+    fft_run<R, LOG2N, Cfg::NSEQ, Cfg::T, INV, Cfg::MAXLOG, 0>(lds, TwTab2<R, N>{ltw}, tid);
   }
 }
 

@@ -25,6 +25,8 @@ struct PcPlan {
   double *wfw = nullptr, *winv = nullptr;               // alpha^{k/N}, alpha^{-k/N}/N
   Cx<double>* tw = nullptr;                             // exp(-2 pi i m/N)
   Cx<float>* tw_f = nullptr;
+  Cx<double>* tw2 = nullptr;                            // two-level form (64 + N/64 entries)
+  Cx<float>* tw2_f = nullptr;
   Cx<double>* mu = nullptr;                             // lambda1/lambda2, [F]
   Cx<double>* il2 = nullptr;                            // 1/lambda2, [F]
   // interface system factors [F][NS], precision of the PC: forward {a, inv}
@@ -49,6 +51,7 @@ struct GSummary {
   int breakdown;  // lucky breakdown (h_{j+1,j} == 0)
   int x0_rejected;  // the initial guess was replaced by zero (fallback start)
   int pad;
+  double err;     // error estimate of a stopped solve (error-controlled stopping)
   int seq;        // sequence number of the write (host polling), written last
 };
 
@@ -65,6 +68,17 @@ struct GState {
   // Gram matrix of the normalised basis, gram[p*NVMAX + q] = <v_p, v_q> /
   // (||v_p|| ||v_q||) (unit diagonal), rows 0..k of the current cycle
   double gram[NVMAX * NVMAX];
+  // error estimate in progress: max |Z_0| and max |x| as float64 bit patterns
+  // (zero between estimates)
+  unsigned long long emax[2];
+};
+
+// Per-instance stopping controls, set by the host for each solve.
+struct StopCtl {
+  double rscale;  // the instance stops at relres <= rtol * rscale (1 unless
+                  // error-controlled stopping tightened it)
+  int est_skip;   // an error estimate is not asked for this instance
+  int pad;
 };
 
 // Everything a kernel needs to know about one instance.  Kernels receive an
@@ -79,7 +93,7 @@ struct InstDesc {
   int mv_grid;            // matvec workgroups (partials per dot)
   int st_grid;            // workgroups of the streaming passes
   long long n;            // unknowns (caller layout: row k of N_x values at k N_x)
-  int ldx;                // row pitch of the internal vectors (V, Z, w): N_x rounded
+  int ldx;                // row pitch of the internal row-major vectors (V, w): N_x rounded
                           // up to 16, so every row starts on a 128-byte line
   long long nin;          // elements of an internal vector, N_t ldx (pads stay 0)
   long long vstride;      // elements between basis vectors
@@ -93,8 +107,29 @@ struct InstDesc {
   GState* st;             // solver state
   GSummary* host;         // the instance's summary slot in pinned host memory
   int zf;                 // Z stored in float32
-  int pad;
+  int zlog;               // Z is tile-blocked with tile width 2^zlog (the
+                          // transform tile width): element (k, i) of Z_j at
+                          // ((i >> zlog) N_t + k) 2^zlog + (i mod 2^zlog)
+  const StopCtl* ctl;     // per-solve stopping controls of the instance
 };
+
+// Element addressing of one column of a space-time vector: element (k, i) at
+// col(i) + k * row.  Row-major vectors (the caller's, the basis): col(i) = i,
+// row = the pitch.  The preconditioned vectors Z: tile-blocked, so that the
+// inverse transform writes each tile as one contiguous block.
+struct VecLayout {
+  int row;   // elements between consecutive levels of one column
+  int zlog;  // tile-blocked: log2 of the tile width; -1: row-major
+  int nt;
+  __device__ __forceinline__ size_t col(int i) const {
+    return zlog < 0 ? (size_t)i
+                    : (((size_t)(i >> zlog) * (size_t)nt) << zlog) + (size_t)(i & ((1 << zlog) - 1));
+  }
+};
+__device__ __forceinline__ VecLayout row_major(int pitch, int nt) { return VecLayout{pitch, -1, nt}; }
+__device__ __forceinline__ VecLayout z_layout(const InstDesc& d) {
+  return VecLayout{1 << d.zlog, d.zlog, d.nt};
+}
 
 // Launch context shared by the kernels of one handle or batch.
 struct Launch {
@@ -116,11 +151,16 @@ __device__ __forceinline__ int2 work_item(const int2* __restrict__ items, int i)
 
 // Launchers (cn_pc.hip, cn_pc_f64.hip, cn_pc_f32.hip).  `v`/`z` override the
 // basis vector V_j / Z_j of a single instance (standalone apply, no stop flag);
-// `pitch` is their row pitch (0: the internal pitch ldx of V and Z).
+// `pitch` is their row pitch (0: the internal layout: V_j row-major with pitch
+// ldx, Z_j tile-blocked).
 hipError_t pc_setup(PcPlan& pl, Cx<double>* spk, int* err_dev, hipStream_t s);
 hipError_t pc_forward(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
                       const double* v, int pitch, hipStream_t s);
-// chunk_class: k2_chunk_class(largest NS of the launch, precision)
+// chunk_class: k2_chunk_class(largest NS of the launch, precision): 32 W + CH
+// (W wavefronts per line, CH separators per lane), K2_STRIDED + CH (blocks
+// of 1024 separators) or K2_ROUNDS + 2 (two rounds of 4096 separators)
+constexpr int K2_STRIDED = 4096;
+constexpr int K2_ROUNDS = 8192;
 int k2_chunk_class(int ns, int prec);
 hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int chunk_class, int j,
                       int standalone, hipStream_t s);
@@ -169,8 +209,28 @@ hipError_t launch_cycle_end_zero(const Launch& L, const Items& mv, int kmax,
                                  const double* b_base, double* x_base, double rtol, int slot_fin,
                                  int seq_fin, int slot_res, int seq_res, hipStream_t s,
                                  bool guard = false, bool store_r = true);
+// start of an error estimate of a batch from the residual its last cycle end
+// stored in V_0 (instead of launch_residual with rtol < 0)
+hipError_t launch_err_begin(const Launch& L, hipStream_t s);
+// error estimate of a stopped solve, after launch_residual (V_0 = r) and the
+// preconditioner of iteration 0 (Z_0 = P^{-1} r / ||r||): ||r|| max|Z_0| /
+// max|x| of every instance into its summary slot `slot` (field err)
+hipError_t launch_err_estimate(const Launch& L, const Items& stv, const double* x_base, int slot,
+                               int seq, hipStream_t s);
 // publish the number of instances still iterating (batch polling)
 hipError_t launch_batch_summary(const Launch& L, int* counter, GSummary* host, hipStream_t s);
+// Per-instance layout of a batch for kernels outside the solver: `dev` (device)
+// holds 1 + 5 count int64 values: the packed offsets of the space-time vectors
+// [count + 1], of the initial conditions [count] (sums of N_x), of the
+// boundary data [count] (sums of N_t), then N_x [count] and N_t [count].
+struct BatchLayout {
+  const long long* dev = nullptr;
+  int count = 0;
+  const int* nx = nullptr;  // host copies
+  const int* nt = nullptr;
+  long long total = 0;      // space-time unknowns of the batch
+};
+bool batch_layout(const cn_batch* b, BatchLayout* out);
 hipError_t launch_rhs(const double* lo, const double* di, const double* up, const double* dw,
                       double tau, const double* u0, const double* f, double* b, int nx,
                       long long n, hipStream_t s);

@@ -93,6 +93,7 @@ __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int 
   host->done = sm.done;
   host->breakdown = sm.breakdown;
   host->x0_rejected = sm.x0_rejected;
+  host->err = sm.err;
   __threadfence_system();
   *(volatile int*)&host->seq = seq;
 }
@@ -120,16 +121,19 @@ __device__ __forceinline__ void matvec_column(const CN_G TX* __restrict__ x,
                                               const CN_G double* __restrict__ pdi,
                                               const CN_G double* __restrict__ pup,
                                               const CN_G double* __restrict__ dw, long long vstride,
-                                              int px, int py, int nx, int nv, int i, int k0,
-                                              int k1, double (&acc)[NA]) {
+                                              VecLayout xl, int px, int py, int nx, int nv, int i,
+                                              int k0, int k1, double (&acc)[NA]) {
   const double lo = plo[i], di = pdi[i], up = pup[i];
   const bool hl = i > 0, hr = i < nx - 1;
+  // x's columns i-1, i, i+1 (layout xl); b and y are row-major (pitches px, py)
+  const size_t xm = hl ? xl.col(i - 1) : 0, xc = xl.col(i), xp = hr ? xl.col(i + 1) : 0;
+  const size_t xrow = (size_t)xl.row;
   double pm = 0.0, pc = 0.0, pp = 0.0;  // previous level at i-1, i, i+1
   if (k0 > 0 && x != nullptr) {
-    const CN_G TX* xr = x + (size_t)(k0 - 1) * px;
-    pc = (double)xr[i];
-    if (hl) pm = (double)xr[i - 1];
-    if (hr) pp = (double)xr[i + 1];
+    const size_t o = (size_t)(k0 - 1) * xrow;
+    pc = (double)x[o + xc];
+    if (hl) pm = (double)x[o + xm];
+    if (hr) pp = (double)x[o + xp];
   }
   size_t vo[NV];
 #pragma unroll
@@ -138,11 +142,11 @@ __device__ __forceinline__ void matvec_column(const CN_G TX* __restrict__ x,
 #pragma unroll UNR
   for (int k = k0; k < k1; ++k) {
     double cm = 0.0, cc = 0.0, cp = 0.0;
-    const size_t off = (size_t)k * px, offy = (size_t)k * py;
+    const size_t off = (size_t)k * px, offy = (size_t)k * py, offx = (size_t)k * xrow;
     if (x != nullptr) {
-      cc = (double)x[off + i];
-      if (hl) cm = (double)x[off + i - 1];
-      if (hr) cp = (double)x[off + i + 1];
+      cc = (double)x[offx + xc];
+      if (hl) cm = (double)x[offx + xm];
+      if (hr) cp = (double)x[offx + xp];
     }
     const double w = dw != nullptr ? dw[k] : 1.0;
     // (M x)^k = (x^k - x^{k-1}) - (w/2) A~ (x^k + x^{k-1})
@@ -197,9 +201,11 @@ __global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
   }
   const int nv = j + 1;
   const int nx = d.nx;
-  // row pitches: caller vectors use N_x, internal ones (V, Z, w) ldx
-  const int px = MODE == 2 ? d.ldx : nx;   // x (and b)
+  // row pitches: caller vectors use N_x, the basis ldx; Z_j (MODE 2) is
+  // tile-blocked
+  const int px = nx;                       // b (and x for MODE 0, 1)
   const int py = MODE == 0 ? nx : d.ldx;   // y (and the basis V)
+  const VecLayout xl = MODE == 2 ? z_layout(d) : row_major(nx, d.nt);
   const int blk = wi.y;
   const int cb = blk % d.mv_cols, rb = blk / d.mv_cols;
   const int i = cb * MVT + threadIdx.x;
@@ -209,8 +215,8 @@ __global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
   for (int q = 0; q < NA; ++q) acc[q] = 0.0;
   if (i < nx)
     matvec_column<TX, MODE, NV, NA>(gp(x), gp(b), gp(y), gp(d.V), gp(d.pl.lo), gp(d.pl.di),
-                                    gp(d.pl.up), gp(d.dw), d.vstride, px, py, nx, nv, i, k0, k1,
-                                    acc);
+                                    gp(d.pl.up), gp(d.dw), d.vstride, xl, px, py, nx, nv, i, k0,
+                                    k1, acc);
   if (MODE == 0) return;
   block_partials<NA, MVT>(acc, MODE == 1 ? 2 : nv, red, d.partials, blk, d.mv_grid);
 }
@@ -274,9 +280,9 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
                                               const CN_G double* __restrict__ pdi,
                                               const CN_G double* __restrict__ pup,
                                               const CN_G double* __restrict__ dw,
-                                              long long vstride, int ldx, int nx, int nv, int i,
-                                              bool act, int k0, int k1, Coeffs&& coeffs,
-                                              double (&acc)[NV + 1]) {
+                                              long long vstride, VecLayout zl, int ldx, int nx,
+                                              int nv, int i, bool act, int k0, int k1,
+                                              Coeffs&& coeffs, double (&acc)[NV + 1]) {
   // levels in flight together: fewer for long bases (registers)
   constexpr int UNR = NV <= 4 ? 4 : (NV <= 8 ? 2 : 1);
   const bool hl = i > 0, hr = i < nx - 1;
@@ -291,6 +297,10 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
   };
   double lo = 0.0, di = 0.0, up = 0.0;
   double pm = 0.0, pc = 0.0, pp = 0.0;  // z at the previous level, i-1, i, i+1
+  // z's columns i-1, i, i+1 in its (tile-blocked) layout
+  const size_t zm = act && hl ? zl.col(i - 1) : 0, zc = act ? zl.col(i) : 0,
+               zp = act && hr ? zl.col(i + 1) : 0;
+  const size_t zrow = (size_t)zl.row;
   // the first PF levels, requested before the coefficients exist (few: the
   // registers they hold must not cost the kernel its second workgroup per CU)
   constexpr int PF = NV <= 4 ? 2 : 1;
@@ -300,19 +310,19 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
     di = pdi[i];
     up = pup[i];
     if (k0 > 0) {
-      const CN_G TX* zr = z + (size_t)(k0 - 1) * ldx;
-      pc = (double)zr[i];
-      if (hl) pm = (double)zr[i - 1];
-      if (hr) pp = (double)zr[i + 1];
+      const size_t o = (size_t)(k0 - 1) * zrow;
+      pc = (double)z[o + zc];
+      if (hl) pm = (double)z[o + zm];
+      if (hr) pp = (double)z[o + zp];
     }
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       // levels past k1 re-read level k1-1 (in bounds, never used)
       const int k = min(k0 + u, k1 - 1);
-      const size_t off = (size_t)k * ldx;
-      fc[u] = (double)z[off + i];
-      fm[u] = hl ? (double)z[off + i - 1] : 0.0;
-      fp[u] = hr ? (double)z[off + i + 1] : 0.0;
+      const size_t off = (size_t)k * ldx, oz = (size_t)k * zrow;
+      fc[u] = (double)z[oz + zc];
+      fm[u] = hl ? (double)z[oz + zm] : 0.0;
+      fp[u] = hr ? (double)z[oz + zp] : 0.0;
 #pragma unroll
       for (int q = 0; q < NV; ++q) fv[u][q] = V[voff(q) + off + i];
       fw[u] = dw != nullptr ? dw[k] : 1.0;
@@ -342,10 +352,10 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
     if (k0 + u < k1) level(k0 + u, fc[u], fm[u], fp[u], fv[u], fw[u]);
 #pragma unroll UNR
   for (int k = k0 + PF; k < k1; ++k) {
-    const size_t off = (size_t)k * ldx;
-    const double cc = (double)z[off + i];
-    const double cm = hl ? (double)z[off + i - 1] : 0.0;
-    const double cp = hr ? (double)z[off + i + 1] : 0.0;
+    const size_t off = (size_t)k * ldx, oz = (size_t)k * zrow;
+    const double cc = (double)z[oz + zc];
+    const double cm = hl ? (double)z[oz + zm] : 0.0;
+    const double cp = hr ? (double)z[oz + zp] : 0.0;
     double vq[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) vq[q] = V[voff(q) + off + i];
@@ -384,8 +394,8 @@ __global__ __launch_bounds__(MVT) void k_cgs_update(const InstDesc* __restrict__
   };
   update_column<TX, NV>(gp((const TX*)d.Z + (size_t)j * d.vstride), gp(d.V),
                         gp(d.V + (size_t)(j + 1) * d.vstride), gp(d.pl.lo), gp(d.pl.di),
-                        gp(d.pl.up), gp(d.dw), d.vstride, d.ldx, d.nx, nv, i, i < d.nx, k0, k1,
-                        coeffs, acc);
+                        gp(d.pl.up), gp(d.dw), d.vstride, z_layout(d), d.ldx, d.nx, nv, i,
+                        i < d.nx, k0, k1, coeffs, acc);
   block_partials<NA, MVT>(acc, nv + 1, red, d.partials2, blk, d.mv_grid);
 }
 
@@ -499,7 +509,7 @@ __device__ __forceinline__ void givens_step(const InstDesc& d, GState* st, GSumm
   sm.k = j + 1;
   const bool brk = !(hn > 1e-300 * (sm.beta > 0.0 ? sm.beta : 1.0));
   sm.breakdown = brk ? 1 : 0;
-  if (est <= rtol * sm.bnorm || brk || j + 1 >= stop_iter) {
+  if (est <= rtol * d.ctl->rscale * sm.bnorm || brk || j + 1 >= stop_iter) {
     sm.done = 1;
     // the cycle stops here: y = R^{-1} g for the cycle end (column j of R is
     // the one just formed, the others were loaded above)
@@ -552,7 +562,12 @@ __global__ __launch_bounds__(FT) void k_finish(const InstDesc* __restrict__ D, i
   sm.relres = sm.bnorm > 0.0 ? beta / sm.bnorm : 0.0;
   sm.breakdown = 0;
   sm.k = 0;
-  sm.done = (sm.relres <= rtol || beta == 0.0) ? 1 : 0;
+  // rtol < 0: the residual of an error estimate; every instance it is asked
+  // for goes on to the preconditioner (no stop threshold)
+  if (rtol < 0.0)
+    sm.done = (d.ctl->est_skip || beta == 0.0) ? 1 : 0;
+  else
+    sm.done = (sm.relres <= rtol * d.ctl->rscale || beta == 0.0) ? 1 : 0;
   publish(host, sm, seq);
 }
 
@@ -633,6 +648,7 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
   __syncthreads();
   const CN_G TZ* __restrict__ Z = gp((const TZ*)d.Z);
   const long long zs = d.vstride;
+  const VecLayout zl = z_layout(d);
   const CN_G double* __restrict__ b = gp(bo + d.off);
   CN_G double* __restrict__ x = gp(xo + d.off);
   CN_G double* __restrict__ v0 = gp(d.V);
@@ -656,6 +672,7 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
   }
   const bool valid = col >= 0 && col < nx;
   const bool own = t < MVT && col < nx;
+  const size_t zcol = valid ? zl.col(col) : 0, zrow = (size_t)zl.row;
   double lo = 0.0, di = 0.0, up = 0.0;
   if (own) {
     lo = gp(d.pl.lo)[col];
@@ -678,9 +695,9 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
 #pragma unroll
         for (int g = 0; g < QG; ++g) {
           const int q = q0 + g;
-          const size_t zq = (size_t)(q < kk ? q : kk - 1) * zs + col + (size_t)kc * ldx;
+          const size_t zq = (size_t)(q < kk ? q : kk - 1) * zs + zcol + (size_t)kc * zrow;
 #pragma unroll
-          for (int r = 0; r < UR_R; ++r) zv[g][r] = Z[zq + (size_t)r * ldx];
+          for (int r = 0; r < UR_R; ++r) zv[g][r] = Z[zq + (size_t)r * zrow];
         }
 #pragma unroll
         for (int g = 0; g < QG; ++g)
@@ -694,7 +711,7 @@ __global__ __launch_bounds__(UR_T) void k_update_residual(const InstDesc* __rest
   auto form1 = [&](int k) -> double {
     double xv = 0.0;
     if (!valid || kk == 0) return xv;
-    const size_t zk = (size_t)k * ldx + col;
+    const size_t zk = (size_t)k * zrow + zcol;
 #pragma unroll 1
     for (int q0 = 0; q0 < KB; q0 += QG) {
       if (q0 < kk) {
@@ -778,10 +795,11 @@ __global__ __launch_bounds__(KT) void k_update(const InstDesc* __restrict__ D,
   const TZ* __restrict__ Z = (const TZ*)d.Z;
   double* __restrict__ x = xb + d.off;
   const long long zstride = d.vstride;
-  // rows of the caller layout (pitch N_x); Z has the internal pitch ldx
+  const VecLayout zl = z_layout(d);
+  // rows of the caller layout (pitch N_x); Z is tile-blocked
   for (int row = wi.y; row < d.nt; row += d.st_grid) {
     for (int i = threadIdx.x; i < d.nx; i += KT) {
-      const size_t e = (size_t)row * d.nx + i, ez = (size_t)row * d.ldx + i;
+      const size_t e = (size_t)row * d.nx + i, ez = zl.col(i) + (size_t)row * zl.row;
       double s = (x_zero & 1) ? 0.0 : x[e];
       int q = 0;
       for (; q + 4 <= k; q += 4) {
@@ -829,6 +847,72 @@ __global__ __launch_bounds__(256) void k_batch_summary(const InstDesc* __restric
     sm.done = s_active[0] == 0 ? 1 : 0;
     publish(host, sm, seq);
   }
+}
+
+// Error estimate of a stopped solve (error-controlled stopping).  With
+// V_0 = r = b - M x and Z_0 = P_alpha^{-1} r / ||r|| (the cycle start with no
+// stop threshold, then the preconditioner of iteration 0), the error
+// e = M^{-1} r is estimated by ||r|| Z_0: P_alpha differs from M only in the
+// alpha-scaled wrap-around block (eq. (3.1)), so P_alpha^{-1} M = I + O(alpha)
+// and the estimate is within a relative O(alpha) of e.  Each workgroup folds
+// max |Z_0| and max |x| over its rows into the instance's state (bit patterns
+// of non-negative float64 values order like unsigned integers).
+template <typename TZ>
+__global__ __launch_bounds__(KT) void k_err_parts(const InstDesc* __restrict__ D,
+                                                  const int2* __restrict__ items,
+                                                  const double* __restrict__ xb) {
+  __shared__ double red[2][KT / 64];
+  const int2 wi = work_item(items, blockIdx.x);
+  const InstDesc& d = D[wi.x];
+  GState* st = d.st;
+  if (st->sum.done) return;  // r = 0: nothing was applied, the estimate is 0
+  const TZ* __restrict__ Z = (const TZ*)d.Z;
+  const double* __restrict__ x = xb + d.off;
+  const VecLayout zl = z_layout(d);
+  double mz = 0.0, mx = 0.0;
+  for (int row = wi.y; row < d.nt; row += d.st_grid) {
+    for (int i = threadIdx.x; i < d.nx; i += KT) {
+      mz = fmax(mz, fabs((double)Z[zl.col(i) + (size_t)row * zl.row]));
+      mx = fmax(mx, fabs(x[(size_t)row * d.nx + i]));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mz = fmax(mz, __shfl_xor(mz, off, 64));
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = mz;
+    red[1][wave] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < KT / 64; ++w) {
+      mz = fmax(mz, red[0][w]);
+      mx = fmax(mx, red[1][w]);
+    }
+    atomicMax(&st->emax[0], (unsigned long long)__double_as_longlong(mz));
+    atomicMax(&st->emax[1], (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+// err = ||r|| max|Z_0| / max|x| (0 when r = 0, -1 when not asked for) into
+// the summary slot; clears the maxima for the next estimate
+__global__ __launch_bounds__(64) void k_err_publish(const InstDesc* __restrict__ D, int slot,
+                                                    int seq) {
+  if (threadIdx.x != 0) return;
+  const InstDesc& d = D[blockIdx.x];
+  GState* st = d.st;
+  GSummary& sm = st->sum;
+  const double mz = __longlong_as_double((long long)st->emax[0]);
+  const double mx = __longlong_as_double((long long)st->emax[1]);
+  // skipped instances publish -1 (no new estimate)
+  double err = d.ctl->est_skip ? -1.0 : 0.0;
+  if (!sm.done) err = mx > 0.0 ? sm.beta * mz / mx : (mz > 0.0 ? INFINITY : 0.0);
+  sm.err = err;
+  st->emax[0] = 0ull;
+  st->emax[1] = 0ull;
+  publish(d.host != nullptr ? d.host + slot : nullptr, sm, seq);
 }
 
 // b = xi + tau f, xi = [(I + (d_0/2) A~) u0; 0; ...]
@@ -969,6 +1053,32 @@ hipError_t launch_cycle_end_zero(const Launch& L, const Items& mv, int kmax,
   }
   hipLaunchKernelGGL((k_finish<1>), dim3(L.ninst), dim3(FT), 0, s, L.D, 0, guard ? 1 : 0, rtol,
                      slot_res, seq_res);
+  return hipGetLastError();
+}
+
+// Start of an error estimate from the residual the last cycle end of a batch
+// left in V_0 (its norm beta and the scale of v_0 in the state): every
+// instance asked for goes on to the preconditioner.
+__global__ __launch_bounds__(256) void k_err_begin(const InstDesc* __restrict__ D, int ninst) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= ninst) return;
+  const InstDesc& d = D[i];
+  GSummary& sm = d.st->sum;
+  sm.done = (d.ctl->est_skip || sm.beta == 0.0 || sm.bnorm == 0.0) ? 1 : 0;
+}
+
+hipError_t launch_err_begin(const Launch& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_err_begin, dim3((L.ninst + 255) / 256), dim3(256), 0, s, L.D, L.ninst);
+  return hipGetLastError();
+}
+
+hipError_t launch_err_estimate(const Launch& L, const Items& stv, const double* x_base, int slot,
+                               int seq, hipStream_t s) {
+  if (L.zf)
+    hipLaunchKernelGGL((k_err_parts<float>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, x_base);
+  else
+    hipLaunchKernelGGL((k_err_parts<double>), dim3(stv.n), dim3(KT), 0, s, L.D, stv.it, x_base);
+  hipLaunchKernelGGL(k_err_publish, dim3(L.ninst), dim3(64), 0, s, L.D, slot, seq);
   return hipGetLastError();
 }
 

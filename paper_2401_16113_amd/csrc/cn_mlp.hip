@@ -19,6 +19,7 @@
 #include <string>
 #include <vector>
 
+#include "cn_internal.hpp"
 #include "cn_warmstart.h"
 
 namespace cn_ws {
@@ -213,7 +214,47 @@ __global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ x, 
 }
 
 // x0(k, i) = bilinear interpolation of scale * coarse, extended by u0 at
-// t = 0 and by the Dirichlet data gl(t), gr(t) at the space ends.
+// t = 0 and by the Dirichlet data gl(t), gr(t) at the space ends, for one
+// instance: cs its CX x CT coarse values, gL/gR its N_t boundary values, u0
+// its N_x initial values.  Contraction into fused multiply-adds is off, so
+// every kernel that calls this gets the same bits for the same inputs.
+__device__ __forceinline__ double interp_value(const float* __restrict__ cs, double sc,
+                                               const double* __restrict__ gL,
+                                               const double* __restrict__ gR,
+                                               const double* __restrict__ u0, int nx, int nt,
+                                               int k, int i) {
+#pragma clang fp contract(off)
+  const int sx = (nx + 1) / CX, st = nt / CT;
+  // space position in coarse units: node c at (i - (sx/2 - 1))/sx = c; the
+  // boundaries sit at -1/2 (left) and CX - 1/2 (right)
+  const double pc = (double)(i - (sx / 2 - 1)) / sx;
+  // value of coarse time row q (q >= 0) at fine column i
+  auto row = [&](int q, int kk) -> double {
+    if (pc < 0.0) {
+      const double w = (pc + 0.5) / 0.5;
+      return (1.0 - w) * gL[kk] + w * sc * cs[q * CX];
+    }
+    if (pc > CX - 1) {
+      const double w = (pc - (CX - 1)) / 0.5;
+      return (1.0 - w) * sc * cs[q * CX + CX - 1] + w * gR[kk];
+    }
+    const int c0 = min((int)pc, CX - 2);
+    const double w = pc - c0;
+    return (1.0 - w) * sc * cs[q * CX + c0] + w * sc * cs[q * CX + c0 + 1];
+  };
+  // time position: node q at fine level st q + st - 1; q = -1 is t = 0 (u0)
+  const double pq = (double)(k + 1) / st - 1.0;
+  const int q0 = (int)floor(pq);
+  const double wt = pq - q0;
+  // fine level of coarse row q (for the boundary data of that row)
+  const int k0 = st * q0 + st - 1;
+  const double v0 = q0 < 0 ? u0[i] : row(q0, k0);
+  double v = v0;
+  if (wt > 0.0 && q0 + 1 < CT) v = (1.0 - wt) * v0 + wt * row(q0 + 1, k0 + st);
+  return v;
+}
+
+// `count` instances of one shape, back to back
 __global__ __launch_bounds__(256) void k_interp(const float* __restrict__ coarse, int count, int nx,
                                                 int nt, const double* __restrict__ u0,
                                                 const double* __restrict__ gl,
@@ -226,37 +267,36 @@ __global__ __launch_bounds__(256) void k_interp(const float* __restrict__ coarse
   const int inst = (int)(e / n);
   const long long r = e % n;
   const int k = (int)(r / nx), i = (int)(r % nx);
-  const int sx = (nx + 1) / CX, st = nt / CT;
-  const float* cs = coarse + (long long)inst * CX * CT;
-  const double sc = scale[inst];
-  // space position in coarse units: node c at (i - (sx/2 - 1))/sx = c; the
-  // boundaries sit at -1/2 (left) and CX - 1/2 (right)
-  const double pc = (double)(i - (sx / 2 - 1)) / sx;
-  // value of coarse time row q (q >= 0) at fine column i
-  auto row = [&](int q, int kk) -> double {
-    const double gL = gl[(long long)inst * nt + kk], gR = gr[(long long)inst * nt + kk];
-    if (pc < 0.0) {
-      const double w = (pc + 0.5) / 0.5;
-      return (1.0 - w) * gL + w * sc * cs[q * CX];
-    }
-    if (pc > CX - 1) {
-      const double w = (pc - (CX - 1)) / 0.5;
-      return (1.0 - w) * sc * cs[q * CX + CX - 1] + w * gR;
-    }
-    const int c0 = min((int)pc, CX - 2);
-    const double w = pc - c0;
-    return (1.0 - w) * sc * cs[q * CX + c0] + w * sc * cs[q * CX + c0 + 1];
-  };
-  // time position: node q at fine level st q + st - 1; q = -1 is t = 0 (u0)
-  const double pq = (double)(k + 1) / st - 1.0;
-  const int q0 = (int)floor(pq);
-  const double wt = pq - q0;
-  // fine level of coarse row q (for the boundary data of that row)
-  const int k0 = st * q0 + st - 1;
-  const double v0 = q0 < 0 ? u0[(long long)inst * nx + i] : row(q0, k0);
-  double v = v0;
-  if (wt > 0.0 && q0 + 1 < CT) v = (1.0 - wt) * v0 + wt * row(q0 + 1, k0 + st);
-  x0[e] = v;
+  x0[e] = interp_value(coarse + (long long)inst * CX * CT, scale[inst], gl + (long long)inst * nt,
+                       gr + (long long)inst * nt, u0 + (long long)inst * nx, nx, nt, k, i);
+}
+
+// The same for a batch of uneven instances: element e of the packed vector
+// belongs to the instance whose offset range holds it (binary search over the
+// offsets); that instance's N_x, N_t, initial condition and boundary data come
+// from the batch layout (see BatchLayout).
+__global__ __launch_bounds__(256) void k_interp_batch(const float* __restrict__ coarse, int count,
+                                                      const long long* __restrict__ lay,
+                                                      const double* __restrict__ u0,
+                                                      const double* __restrict__ gl,
+                                                      const double* __restrict__ gr,
+                                                      const double* __restrict__ scale,
+                                                      double* __restrict__ x0) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= lay[count]) return;
+  int lo = 0, hi = count - 1;  // lay[lo] <= e < lay[hi + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (lay[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  const int inst = lo;
+  const int nx = (int)lay[3 * count + 1 + inst], nt = (int)lay[4 * count + 1 + inst];
+  const long long r = e - lay[inst];
+  const int k = (int)(r / nx), i = (int)(r % nx);
+  const long long go = lay[2 * count + 1 + inst];
+  x0[e] = interp_value(coarse + (long long)inst * CX * CT, scale[inst], gl + go, gr + go,
+                       u0 + lay[count + 1 + inst], nx, nt, k, i);
 }
 
 }  // namespace cn_ws
@@ -571,6 +611,33 @@ cn_status cn_ws_predict(cn_mlp* n, const float* features, int32_t count, int32_t
     if (st != CN_OK) return st;
   }
   return cn_ws_interpolate(coarse, count, nx, nt, u0, gl, gr, scale, x0, n->s);
+}
+
+cn_status cn_ws_predict_batch(cn_mlp* n, const float* features, const cn_batch* b,
+                              const double* u0, const double* gl, const double* gr,
+                              const double* scale, float* coarse, double* x0) {
+  if (n == nullptr || features == nullptr || b == nullptr || u0 == nullptr || gl == nullptr ||
+      gr == nullptr || scale == nullptr || coarse == nullptr || x0 == nullptr)
+    return ws_fail(CN_EINVAL, "NULL argument");
+  if (n->n_out != CX * CT) return ws_fail(CN_EINVAL, "the network must predict 128 x 64 values");
+  cn::BatchLayout lay;
+  if (!cn::batch_layout(b, &lay)) return ws_fail(CN_EINVAL, "batch has no layout");
+  for (int i = 0; i < lay.count; ++i) {
+    const int nx = lay.nx[i], nt = lay.nt[i];
+    if (nt < CT || (nx + 1) % CX != 0 || nt % CT != 0 || (nx + 1) / CX < 2)
+      return ws_fail(CN_EINVAL, "instance " + std::to_string(i) +
+                                    ": need nx + 1 a multiple of 128 (>= 256) and nt a multiple of 64");
+  }
+  for (int c0 = 0; c0 < lay.count; c0 += n->max_batch) {
+    const int B = std::min(n->max_batch, lay.count - c0);
+    const cn_status st = cn_mlp_forward(n, features + (size_t)c0 * n->n_in, B,
+                                        coarse + (size_t)c0 * n->n_out);
+    if (st != CN_OK) return st;
+  }
+  hipLaunchKernelGGL(k_interp_batch, dim3((unsigned)((lay.total + 255) / 256)), dim3(256), 0,
+                     n->s, coarse, lay.count, lay.dev, u0, gl, gr, scale, x0);
+  WS_TRY(hipGetLastError());
+  return CN_OK;
 }
 
 }  // extern "C"

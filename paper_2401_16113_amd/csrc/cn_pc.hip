@@ -158,6 +158,125 @@ __device__ __forceinline__ void reduced_line_strided(
   }
 }
 
+// Block scan of the lanes' maps (in lane order, or reversed for the
+// backward sweep) returning the exclusive prefix of the lane (the maps of
+// the lanes before it) and the block total.  sA/sB: 2W+1 entries.
+template <bool UP, int W>
+__device__ __forceinline__ void block_affine_excl(Cx<double> A, Cx<double> Bv, Cx<double>& Ae,
+                                                  Cx<double>& Be, Cx<double>& At, Cx<double>& Bt,
+                                                  int lane, int wave, Cx<double>* sA,
+                                                  Cx<double>* sB) {
+  const Cx<double> one{1.0, 0.0}, zero{0.0, 0.0};
+  Cx<double> Ai = A, Bi = Bv;
+  block_affine<UP, W>(Ai, Bi, At, Bt, lane, wave, sA, sB);
+  // exclusive = inclusive of the neighbour before it in scan order; the
+  // first lane of a wavefront takes the wavefront's exclusive prefix
+  Ae = UP ? shfl_up_c(Ai, 1) : shfl_down_c(Ai, 1);
+  Be = UP ? shfl_up_c(Bi, 1) : shfl_down_c(Bi, 1);
+  if (UP ? lane == 0 : lane == 63) {
+    Ae = sA[W + wave];
+    Be = sB[W + wave];
+  }
+  (void)one;
+  (void)zero;
+}
+
+// Rounds layout for wide grids (4096 < NS <= 8192): L = 512 lanes, lane
+// t of round r owns the CH = 8 consecutive separators from r L CH + t CH.
+// All operands of a round are requested at once; each round needs one block
+// scan per sweep, and the value carried between rounds is the round's total
+// map applied to the previous carry.  rr stays in registers.
+template <typename R, int RD>
+__device__ __forceinline__ void reduced_line_rounds(
+    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const RedFwd<R>* __restrict__ rf,
+    const Cx<R>* __restrict__ rb, int NS, int t, Cx<double> (*sA)[17], Cx<double> (*sB)[17]) {
+  constexpr int W = 8, L = 64 * W, CH = 8;
+  const int lane = t & 63, wave = t >> 6;
+  const Cx<double> one{1.0, 0.0}, zero{0.0, 0.0};
+  const Cx<R> onef{R(1), R(0)}, zerof{R(0), R(0)};
+  Cx<double> rh[RD][CH];
+  int buf = 0;
+  Cx<double> carry = zero;
+#pragma unroll
+  for (int r = 0; r < RD; ++r) {
+    const int s0 = r * L * CH + t * CH;
+    // operands as loaded (rho_s = p1_s + p2_{s+1} is formed where used)
+    RedFwd<R> q[CH];
+    Cx<R> p1[CH], p2[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int s = s0 + c;
+      q[c] = s < NS ? rf[s] : RedFwd<R>{onef, zerof};
+      p1[c] = s < NS ? f[(size_t)2 * s] : zerof;
+      p2[c] = s < NS ? f[(size_t)2 * s + 3] : zerof;
+    }
+    auto rho = [&](int c) {
+      return Cx<double>{(double)p1[c].x + (double)p2[c].x, (double)p1[c].y + (double)p2[c].y};
+    };
+    Cx<double> A = one, Bv = zero;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const Cx<double> aw = wide(q[c].a);
+      Bv = aw * Bv + rho(c);
+      A = aw * A;
+    }
+    Cx<double> Ae, Be, At, Bt;
+    block_affine_excl<true, W>(A, Bv, Ae, Be, At, Bt, lane, wave, sA[buf], sB[buf]);
+    buf ^= 1;
+    Cx<double> v = Ae * carry + Be;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      v = wide(q[c].a) * v + rho(c);
+      rh[r][c] = wide(q[c].inv) * v;  // rr_s
+    }
+    carry = At * carry + Bt;
+  }
+  carry = zero;
+#pragma unroll
+  for (int r = RD - 1; r >= 0; --r) {
+    const int s0 = r * L * CH + t * CH;
+    Cx<R> ap[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) ap[c] = s0 + c < NS ? rb[s0 + c] : onef;
+    Cx<double> A = one, Bv = zero;
+#pragma unroll
+    for (int c = CH - 1; c >= 0; --c) {
+      const Cx<double> aw = wide(ap[c]);
+      Bv = aw * Bv + rh[r][c];
+      A = aw * A;
+    }
+    Cx<double> Ae, Be, At, Bt;
+    block_affine_excl<false, W>(A, Bv, Ae, Be, At, Bt, lane, wave, sA[buf], sB[buf]);
+    buf ^= 1;
+    Cx<double> S = Ae * carry + Be;
+#pragma unroll
+    for (int c = CH - 1; c >= 0; --c) {
+      S = wide(ap[c]) * S + rh[r][c];
+      const int s = s0 + c;
+      if (s < NS) sep[s] = Cx<R>{(R)S.x, (R)S.y};
+    }
+    carry = At * carry + Bt;
+  }
+}
+
+template <typename R, int RD>
+__global__ __launch_bounds__(512) void k_pc_reduced_rounds(const InstDesc* __restrict__ D,
+                                                           const int2* __restrict__ items,
+                                                           int nitems, int standalone) {
+  __shared__ Cx<double> sA[2][17], sB[2][17];
+  const int item = blockIdx.x;
+  if (item >= nitems) return;
+  const int2 wi = work_item(items, item);
+  const InstDesc& d = D[wi.x];
+  const PcPlan& pl = d.pl;
+  if (!standalone && d.st->sum.done) return;
+  const int j = wi.y;
+  const size_t row = (size_t)j * pl.NS;
+  reduced_line_rounds<R, RD>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 2,
+                             (Cx<R>*)pl.sep + row, (const RedFwd<R>*)pl.recf + row,
+                             (const Cx<R>*)pl.recb + row, pl.NS, threadIdx.x, sA, sB);
+}
+
 template <typename R, int W, int CH>
 __global__ __launch_bounds__(64 * W) void k_pc_reduced_strided(
     const InstDesc* __restrict__ D, const int2* __restrict__ items, int nitems, int standalone) {
@@ -348,7 +467,9 @@ int k2_chunk_class(int ns, int prec) {
     for (int c = 1; c <= cmax; c *= 2)
       if (chunk <= c) return 32 * w + c;
   }
-  // strided blocks of 1024 separators (K2_STRIDED + CH), then streamed
+  // two rounds of 4096 separators (K2_ROUNDS + 2), then strided blocks of 1024
+  // separators (K2_STRIDED + CH), then streamed
+  if (ns <= 2 * 4096) return K2_ROUNDS + 2;
   const int blocks = (ns + 1023) / 1024;
   for (int c = 4; c <= 16; c *= 2)
     if (blocks <= c) return K2_STRIDED + c;
@@ -386,6 +507,17 @@ hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int chunk_clas
     break;
     K2S(1) K2S(2) K2S(4) K2S(8) K2S(16)
 #undef K2S
+#define K2R(RD)                                                                                \
+  case K2_ROUNDS + RD:                                                                         \
+    if (prec)                                                                                  \
+      hipLaunchKernelGGL((k_pc_reduced_rounds<float, RD>), dim3(it.n), dim3(512), 0, s, L.D,  \
+                         it.it, it.n, standalone);                                             \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_pc_reduced_rounds<double, RD>), dim3(it.n), dim3(512), 0, s, L.D, \
+                         it.it, it.n, standalone);                                             \
+    break;
+    K2R(2)
+#undef K2R
 #undef K2
     default:
       return hipErrorInvalidValue;

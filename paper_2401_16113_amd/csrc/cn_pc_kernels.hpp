@@ -25,7 +25,7 @@ namespace cn {
 // ---------------------------------------------------------------------------
 template <typename R, int LOG2N, int BB, int TT>
 __device__ __forceinline__ void pc_forward_tile(
-    int p, const CN_G double* __restrict__ v, const double* scp, const int* stop,
+    int p, const CN_G double* __restrict__ v, const CN_G double* scp, const CN_G int* stop,
     const CN_G double* __restrict__ lo,
     const CN_G double* __restrict__ di, const CN_G double* __restrict__ up,
     const CN_G double* __restrict__ wfw, const Cx<R>* __restrict__ tw,
@@ -40,42 +40,86 @@ __device__ __forceinline__ void pc_forward_tile(
   const int i0 = p * B;
   const int ncols = min(B, nx - i0);
   // step (a): alpha-weighted tile, columns (2s, 2s+1) packed as one complex
-  // sequence.  All of a thread's loads (tile, then twiddles) are issued
-  // before any is consumed.
+  // sequence.  The stop flag and the basis scale are uniform scalar loads,
+  // issued first (they do not wait behind vector loads); then every vector
+  // load of the phase (weights, tile, twiddles, operator rows) is issued
+  // before any is consumed, in the order they are used.
   R* ldsr = reinterpret_cast<R*>(lds);
   {
+    const int stopped = stop != nullptr ? *stop : 0;
+    const double sc = scp != nullptr ? *scp : 1.0;
+    // the alpha weights of the thread's levels: B divides T, so its levels
+    // are k = tid/B + q T/B and w_q = alpha^{k/N_t} = w_0 rho^q with
+    // rho = alpha^{(T/B)/N_t}, formed by recurrence (rounding <= LPT eps
+    // relative) instead of one table load per element
+    static_assert(T % B == 0, "the workgroup size must be a multiple of the tile width");
+    const double w0 = wfw[min(tid / B, N - 1)];
+    const double rho = wfw[T / B < N ? T / B : 0];
     constexpr int LPT = (N * B + T - 1) / T;
     double xv[LPT];
+    {
+      // element (k, b) of the tile at byte offset (k vp + b) 8 from column
+      // i0; thread tid reads column b = tid mod B (unconditionally: columns
+      // past the grid's edge re-read its last column and are masked when
+      // staged) at levels tid/B + q T/B, a uniform step of (T/B) vp 8 bytes
+      // per q.  Offsets stay below N_t vp 8 bytes (below 2^32: checked at
+      // set-up).
+      const BufRd vb(v + i0);
+      const unsigned vo = ((unsigned)(tid / B) * (unsigned)vp + (unsigned)min(tid % B, ncols - 1)) * 8u;
+      const unsigned step = (unsigned)(T / B) * (unsigned)vp * 8u;
 #pragma unroll
-    for (int q = 0; q < LPT; ++q) {
-      const int e = tid + q * T;
-      const int k = e / B, b = e % B;
-      xv[q] = ((N * B) % T == 0 || e < N * B) && b < ncols ? v[(size_t)k * vp + i0 + b] : 0.0;
+      for (int q = 0; q < LPT; ++q) {
+        const int e = tid + q * T;
+        if ((N * B) % T == 0 || e < N * B) xv[q] = vb.f64(vo, (unsigned)q * step);
+      }
     }
-    // the stop flag and the basis scale are read with the tile in flight
-    // (a stopped cycle's loads are simply dropped)
-    if (stop != nullptr && *stop) return;
-    const double sc = scp != nullptr ? *scp : 1.0;
     TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
     if constexpr (Cfg::TWL) tws.fetch(gp(tw));
+    double cov = 0.0;
     if (tid < 3 * B) {
-      const int b = tid / 3, c = tid % 3;
-      R val = R(0);
-      if (b < ncols) val = (R)(c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]));
-      co[tid] = val;
+      const int b = min(tid / 3, ncols - 1), c = tid % 3;
+      cov = c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]);
     }
+    // a stopped cycle's loads are simply dropped
+    if (stopped) return;
+    if (tid < 3 * B) co[tid] = tid / 3 < ncols ? (R)cov : R(0);
+    double w = w0 * sc;
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int e = tid + q * T;
       if ((N * B) % T == 0 || e < N * B) {
         const int k = e / B, b = e % B;
-        ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] = (R)(xv[q] * (wfw[k] * sc));
+        const R val = (R)(xv[q] * w);
+        ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] = b < ncols ? val : R(0);
       }
+      w *= rho;
     }
     if constexpr (Cfg::TWL) tws.store(ltw);
   }
   __syncthreads();
   fft_tile<Cfg, R, LOG2N, false>(lds, ltw, tw, threadIdx.x);
+
+  // the shifts of the thread's frequencies (task u: t = tid + u T; t = 0
+  // solves the real modes 0 and N/2, held as (.x, .y)).  With several tasks
+  // per thread they are requested together after the FFT (one latency for
+  // all of them); with one task, at the task (earlier placement cost the
+  // 16-column, 1024-thread variants register spills).
+  constexpr int NTK = Cfg::NTK;
+  auto shifts = [&](int t, Cx<double>& m, Cx<double>& s2) {
+    if (t == 0) {
+      const int h = N >= 2 ? N / 2 : 0;
+      m = Cx<double>{mu[0].x, mu[h].x};
+      s2 = Cx<double>{il2[0].x, il2[h].x};
+    } else if (Cfg::TASKS % T == 0 || t < Cfg::TASKS) {
+      m = gld(mu + t);
+      s2 = gld(il2 + t);
+    }
+  };
+  Cx<double> tmd[NTK], tsd[NTK];
+  if constexpr (NTK > 1) {
+#pragma unroll
+    for (int u = 0; u < NTK; ++u) shifts(tid + u * T, tmd[u], tsd[u]);
+  }
 
   // step (b), tile-local part.  Per frequency the tile leaves two partial
   // right-hand sides of the separator systems: d + lo y_last for its own
@@ -85,7 +129,11 @@ __device__ __forceinline__ void pc_forward_tile(
   const R lsep = has_sep ? co[3 * (B - 1)] : R(0);
   const R uprev = p > 0 ? (R)up[i0 - 1] : R(0);
   CN_G Cx<R>* ifc = iface + (size_t)p * 2;
-  for (int t = tid; t < Cfg::TASKS; t += T) {
+#pragma unroll
+  for (int u = 0; u < NTK; ++u) {
+    const int t = tid + u * T;
+    if (Cfg::TASKS % T != 0 && t >= Cfg::TASKS) break;
+    if constexpr (NTK == 1) shifts(t, tmd[u], tsd[u]);
     if (t == 0) {
       // j = 0 and j = N/2: real modes, real shifts
       const int nreal = N >= 2 ? 2 : 1;
@@ -93,7 +141,7 @@ __device__ __forceinline__ void pc_forward_tile(
       for (int h = 0; h < 2; ++h) {
         if (h >= nreal) break;
         const int j = h == 0 ? 0 : N / 2;
-        const R m = (R)mu[j].x, s2 = (R)il2[j].x;
+        const R m = (R)(h == 0 ? tmd[u].x : tmd[u].y), s2 = (R)(h == 0 ? tsd[u].x : tsd[u].y);
         R d[B];
 #pragma unroll
         for (int c = 0; c < NSEQ; ++c) {
@@ -115,8 +163,7 @@ __device__ __forceinline__ void pc_forward_tile(
       }
     } else {
       const int j = t;
-      const Cx<double> md = gld(mu + j), sd = gld(il2 + j);
-      const Cx<R> m{(R)md.x, (R)md.y}, s2{(R)sd.x, (R)sd.y};
+      const Cx<R> m{(R)tmd[u].x, (R)tmd[u].y}, s2{(R)tsd[u].x, (R)tsd[u].y};
       Cx<R> d[B];
 #pragma unroll
       for (int c = 0; c < NSEQ; ++c) {
@@ -170,9 +217,12 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
   // inside a solve: input V_j scaled by 1/||v_j||, skipped once the cycle stopped
   const bool in_solve = v_ovr == nullptr;
   const double* v = in_solve ? d.V + (size_t)jv * d.vstride : v_ovr;
-  const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
-  pc_forward_tile<R, LOG2N, BB, TT>(wi.y, gp(v), in_solve ? d.st->vscale + jv : nullptr,
-                                    in_solve ? &d.st->sum.done : nullptr, gp(pl.lo), gp(pl.di),
+  using Cfg = PcCfg<R, LOG2N, BB, TT>;
+  const Cx<R>* tw = Cfg::TWMODE == 3
+                        ? (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw2 : (const Cx<R>*)pl.tw2_f)
+                        : (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f);
+  pc_forward_tile<R, LOG2N, BB, TT>(wi.y, gp(v), in_solve ? gp(d.st->vscale + jv) : nullptr,
+                                    in_solve ? gp(&d.st->sum.done) : nullptr, gp(pl.lo), gp(pl.di),
                                     gp(pl.up), gp(pl.wfw), tw, gp((const Cx<double>*)pl.mu),
                                     gp((const Cx<double>*)pl.il2), gp((Cx<R>*)pl.spec),
                                     gp((Cx<R>*)pl.iface), pl.nx, pitch > 0 ? pitch : d.ldx, pl.P);
@@ -183,7 +233,7 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
 // ---------------------------------------------------------------------------
 template <typename R, int LOG2N, int BB, int TT, typename TZ>
 __device__ __forceinline__ void pc_inverse_tile(
-    int p, const int* stop, const CN_G Cx<R>* __restrict__ spec,
+    int p, const CN_G int* stop, const CN_G Cx<R>* __restrict__ spec,
     const CN_G Cx<R>* __restrict__ sep, const CN_G double* __restrict__ lo,
     const CN_G double* __restrict__ di, const CN_G double* __restrict__ up,
     const CN_G double* __restrict__ winv, const Cx<R>* __restrict__ tw,
@@ -198,6 +248,18 @@ __device__ __forceinline__ void pc_inverse_tile(
   const int i0 = p * B;
   const int ncols = min(B, nx - i0);
   const CN_G Cx<R>* img = spec + (size_t)p * NSEQ * N;
+  constexpr int NTK = Cfg::NTK;
+  const Cx<R> zero{R(0), R(0)};
+  Cx<R> slv[NTK], srv[NTK];
+  Cx<double> tmd[NTK];
+  // the stop flag first, as a uniform scalar load; then every vector load of
+  // the phase is issued before any is consumed (see K1)
+  const int stopped = stop != nullptr ? *stop : 0;
+  // inverse weights alpha^{-k/N_t}/N_t of the thread's levels k = tid/B +
+  // q T/B by recurrence, as in K1: w_q = w_0 rho^q, rho = alpha^{-(T/B)/N_t}
+  static_assert(T % B == 0, "the workgroup size must be a multiple of the tile width");
+  double w = winv[min(tid / B, N - 1)];
+  const double rho = winv[T / B < N ? T / B : 0] * (double)N;
   {
     constexpr int SPT = (NSEQ * N + T - 1) / T;
     Cx<R> iv[SPT];
@@ -206,15 +268,36 @@ __device__ __forceinline__ void pc_inverse_tile(
       const int e = tid + q * T;
       if ((NSEQ * N) % T == 0 || e < NSEQ * N) iv[q] = gld(img + e);
     }
-    if (stop != nullptr && *stop) return;  // read with the image in flight
+    // the separator values of the thread's frequencies and their shifts are
+    // requested with the image (task u: t = tid + u T; t = 0 solves the real
+    // modes 0 and N/2, held as (.x, .y)); indices are clamped to the
+    // separator array (at least one entry per line) and masked where the
+    // tile has no such separator
+    const int sli = max(p - 1, 0), sri = min(p, max(NS - 1, 0));
+#pragma unroll
+    for (int u = 0; u < NTK; ++u) {
+      const int t = tid + u * T;
+      if (t == 0) {
+        const int h = N >= 2 ? N / 2 : 0;
+        const size_t hr = (size_t)h * NS;
+        slv[u] = Cx<R>{sep[sli].x, sep[hr + sli].x};
+        srv[u] = Cx<R>{sep[sri].x, sep[hr + sri].x};
+        tmd[u] = Cx<double>{mu[0].x, mu[h].x};
+      } else if (Cfg::TASKS % T == 0 || t < Cfg::TASKS) {
+        slv[u] = gld(sep + (size_t)t * NS + sli);
+        srv[u] = gld(sep + (size_t)t * NS + sri);
+        tmd[u] = gld(mu + t);
+      }
+    }
     TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
     if constexpr (Cfg::TWL) tws.fetch(gp(tw));
+    double cov = 0.0;
     if (tid < 3 * B) {
-      const int b = tid / 3, c = tid % 3;
-      R val = R(0);
-      if (b < ncols) val = (R)(c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]));
-      co[tid] = val;
+      const int b = min(tid / 3, ncols - 1), c = tid % 3;
+      cov = c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]);
     }
+    if (stopped) return;  // a stopped cycle's loads are simply dropped
+    if (tid < 3 * B) co[tid] = tid / 3 < ncols ? (R)cov : R(0);
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int e = tid + q * T;
@@ -226,16 +309,19 @@ __device__ __forceinline__ void pc_inverse_tile(
   const bool has_sep = p < P - 1;
   const bool has_left = p > 0;
   const int nb = has_sep ? B - 1 : ncols;
-  for (int t = tid; t < Cfg::TASKS; t += T) {
+#pragma unroll
+  for (int u = 0; u < NTK; ++u) {
+    const int t = tid + u * T;
+    if (Cfg::TASKS % T != 0 && t >= Cfg::TASKS) break;
     if (t == 0) {
       const int nreal = N >= 2 ? 2 : 1;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         if (h >= nreal) break;
         const int j = h == 0 ? 0 : N / 2;
-        const R m = (R)mu[j].x;
-        const R sl = has_left ? sep[(size_t)j * NS + p - 1].x : R(0);
-        const R sr = has_sep ? sep[(size_t)j * NS + p].x : R(0);
+        const R m = (R)(h == 0 ? tmd[u].x : tmd[u].y);
+        const R sl = has_left ? (h == 0 ? slv[u].x : slv[u].y) : R(0);
+        const R sr = has_sep ? (h == 0 ? srv[u].x : srv[u].y) : R(0);
         R d[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) d[b] = R(0);
@@ -255,11 +341,8 @@ __device__ __forceinline__ void pc_inverse_tile(
       }
     } else {
       const int j = t;
-      const Cx<double> md = gld(mu + j);
-      const Cx<R> m{(R)md.x, (R)md.y};
-      const Cx<R> zero{R(0), R(0)};
-      const Cx<R> sl = has_left ? gld(sep + (size_t)j * NS + p - 1) : zero;
-      const Cx<R> sr = has_sep ? gld(sep + (size_t)j * NS + p) : zero;
+      const Cx<R> m{(R)tmd[u].x, (R)tmd[u].y};
+      const Cx<R> sl = has_left ? slv[u] : zero, sr = has_sep ? srv[u] : zero;
       Cx<R> d[B];
 #pragma unroll
       for (int b = 0; b < B; ++b) d[b] = zero;
@@ -289,16 +372,21 @@ __device__ __forceinline__ void pc_inverse_tile(
     for (int q = 0; q < LPT; ++q) {
       const int e = tid + q * T;
       const int k = e / B, b = e % B;
+      const double wq = w;
+      w *= rho;
       if (((N * B) % T == 0 || e < N * B) && b < ncols) {
-        const double val = (double)ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] * winv[k];
-        z[(size_t)k * zp + i0 + b] = (TZ)val;
+        const double val = (double)ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] * wq;
+        // zp > 0: row-major with pitch zp; 0: tile-blocked (the tile's B x N_t
+        // block is contiguous: element (k, b) at (p N_t + k) B + b)
+        const size_t zi = zp > 0 ? (size_t)k * zp + i0 + b : (size_t)p * N * B + (size_t)e;
+        z[zi] = (TZ)val;
       }
     }
   }
 }
 
-// z_ovr: output vector instead of Z_j; pitch: its row pitch (0: the internal
-// pitch of Z)
+// z_ovr: output vector instead of Z_j; pitch: its row pitch (row-major), or 0
+// for the tile-blocked layout of Z
 template <typename R, int LOG2N, int BB, int TT, typename TZ>
 __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ D,
                                                    const int2* __restrict__ items, int nitems,
@@ -310,12 +398,15 @@ __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ 
   const InstDesc& d = D[wi.x];
   const PcPlan& pl = d.pl;
   TZ* z = z_ovr != nullptr ? z_ovr : (TZ*)d.Z + (size_t)jv * d.vstride;
-  const Cx<R>* tw = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f;
-  pc_inverse_tile<R, LOG2N, BB, TT, TZ>(wi.y, z_ovr == nullptr ? &d.st->sum.done : nullptr,
+  using Cfg = PcCfg<R, LOG2N, BB, TT>;
+  const Cx<R>* tw = Cfg::TWMODE == 3
+                        ? (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw2 : (const Cx<R>*)pl.tw2_f)
+                        : (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f);
+  pc_inverse_tile<R, LOG2N, BB, TT, TZ>(wi.y, z_ovr == nullptr ? gp(&d.st->sum.done) : nullptr,
                                         gp((const Cx<R>*)pl.spec), gp((const Cx<R>*)pl.sep),
                                         gp(pl.lo), gp(pl.di), gp(pl.up), gp(pl.winv), tw,
                                         gp((const Cx<double>*)pl.mu), gp(z), pl.nx,
-                                        pitch > 0 ? pitch : d.ldx, pl.P, pl.NS);
+                                        pitch > 0 ? pitch : 0, pl.P, pl.NS);
 }
 
 // ---------------------------------------------------------------------------

@@ -23,7 +23,6 @@ namespace cn {
 // into a 256-thread workgroup.
 // ---------------------------------------------------------------------------
 constexpr int K2_THREADS = 256;
-constexpr int K2_STRIDED = 4096;  // variant code offset of the strided layout
 
 __device__ __forceinline__ Cx<double> shfl_up_c(Cx<double> v, int off) {
   return Cx<double>{__shfl_up(v.x, off, 64), __shfl_up(v.y, off, 64)};

@@ -74,17 +74,17 @@ def family_batch(params: np.ndarray, nx: int = W.WS_NX, nt: int = W.WS_NT,
 
 
 def solve_family(fb: FamilyBatch, x0=None, m: int = 20, rtol: float = 1e-8,
-                 pc_prec: str = "fp32", warm: bool = False):
+                 pc_prec: str = "fp32", warm: bool = False, err_tol: float = 0.0):
     """Batched solve of the family batch; returns (x, total, per-instance,
     seconds of the solve call).  warm: x0 holds the initial guess (fallback
-    start)."""
+    start); err_tol > 0: error-controlled stopping."""
     bat = B.Batch(fb.probs, pc_prec=pc_prec)
     b = torch.empty(fb.count * fb.nx * fb.nt, dtype=torch.float64, device=fb.u0.device)
     bat.rhs(fb.u0, fb.f, b)
     x = x0 if x0 is not None else torch.zeros_like(b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tot, per = bat.solve(b, x, m=m, rtol=rtol, use_x0=2 if warm else 0)
+    tot, per = bat.solve(b, x, m=m, rtol=rtol, use_x0=2 if warm else 0, err_tol=err_tol)
     sec = time.perf_counter() - t0
     bat.close()
     return x, tot, per, sec

@@ -107,6 +107,10 @@ def test_ws_grid_calls_reject_bad_arguments(lib):
 
 
 def test_gmres_info_layout():
-    # six 32-bit fields then three doubles, as include/cn_aao.h declares
-    assert ctypes.sizeof(B.CnGmresInfo) == 48
+    # six 32-bit fields then four doubles, as include/cn_aao.h declares
+    assert ctypes.sizeof(B.CnGmresInfo) == 56
     assert B.CnGmresInfo.relres_true.offset == 24
+    assert B.CnGmresInfo.err_est.offset == 48
+    # four 32-bit fields then rtol and err_tol
+    assert ctypes.sizeof(B.CnGmresOpts) == 32
+    assert B.CnGmresOpts.rtol.offset == 16 and B.CnGmresOpts.err_tol.offset == 24

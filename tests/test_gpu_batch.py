@@ -70,32 +70,51 @@ def test_batch_equals_single_solves():
         assert rel_inf(x[bt.offsets[q]:bt.offsets[q + 1]].cpu().numpy(), xq.cpu().numpy()) <= 1e-12
 
 
-def test_batch_uneven_workload_shape():
-    """The uneven-batch recipe (N_x in {255..2047}, N_t in {64..512}) at 64
-    instances: every instance reaches relres 1e-8; a sample matches the oracle."""
-    banner("batch config3 recipe x64")
-    insts = W.config3(count=64, seed=3)
+def test_batch_uneven_workload_every_instance():
+    """The full uneven-batch workload (512 instances, N_x in {255..2047},
+    N_t in {64..512}, float32 preconditioner, GMRES(20) to relres 1e-8):
+    every instance's solution against the oracle's CN time stepping, to the
+    bar for mixed-precision forms (1e-7, relative max-norm).  A residual of
+    1e-8 leaves errors up to ~40x larger on the stiffest instances, so the
+    solve runs with error-controlled stopping at half the bar, and its
+    per-instance error estimates are checked against the measured errors."""
+    banner("batch config3 recipe x512, error-controlled stopping")
+    insts = W.config3()
     bt = batch(insts, pc_prec="fp32")
     b = torch.empty(bt.n, dtype=torch.float64, device="cuda")
     bt.rhs(packed(insts, "u0"), packed(insts, "f"), b)
     x = torch.empty_like(b)
-    tot, per = bt.solve(b, x, m=20, rtol=1e-8)
+    for call in range(2):
+        # the second call starts from the per-instance targets the first one left
+        tot, per = bt.solve(b, x, m=20, rtol=1e-8, err_tol=5e-8)
+        print(f"  call {call}: iterations max {tot.iters}, pc applies {tot.pc_applies}, "
+              f"{tot.seconds * 1e3:.1f} ms, relres max {tot.relres_true:.2e} "
+              f"min {min(p.relres_true for p in per):.2e}, continuation passes "
+              f"{tot.err_passes} ({sum(p.err_passes > 0 for p in per)} instances)", flush=True)
     assert tot.status == B.CN_OK and all(p.relres_true <= 1e-8 for p in per)
+    assert all(0.0 <= p.err_est <= 5e-8 for p in per)
     xs = x.cpu().numpy()
-    ratios = []
-    for q in range(0, 64, 9):
-        inst = insts[q]
+    x2 = torch.empty_like(b)
+    t2, _ = bt.solve(b, x2, m=20, rtol=1e-8)
+    print(f"  residual test alone: iterations max {t2.iters}, {t2.seconds * 1e3:.1f} ms", flush=True)
+    errs, ratios, est = [], [], []
+    for q, inst in enumerate(insts):
         seg = xs[bt.offsets[q]:bt.offsets[q + 1]]
-        rr = oracle_relres(inst, seg)
-        err = rel_inf(seg, exact(inst))
-        print(f"  instance {q}: {inst.nx}x{inst.nt} relres {rr:.2e} err {err:.2e}")
-        # the oracle confirms the residual reached; the error follows from it
-        # through the conditioning of M (error/residual up to ~30 here, where
-        # T ||A|| reaches 1e5), so it is bounded relative to the residual
-        assert rr <= 1e-8 * (1 + 1e-6), (q, rr)
-        assert err <= max(1e-7, 50.0 * rr), (q, err, rr)
-        ratios.append(err / rr)
-    print(f"  error/residual ratios: {np.round(ratios, 1)}")
+        u = O.sequential_cn_banded(inst.a_lo, inst.a_di, inst.a_up, inst.T, inst.nt, inst.u0,
+                                   f=inst.f)
+        errs.append(rel_inf(seg, u))
+        ratios.append(errs[-1] / per[q].relres_true)
+        est.append(per[q].err_est / errs[-1])
+    errs, ratios, est = np.array(errs), np.array(ratios), np.array(est)
+    worst = int(np.argmax(errs))
+    print(f"  max error {errs.max():.2e} (instance {worst}: {insts[worst].nx}x{insts[worst].nt}, "
+          f"relres {per[worst].relres_true:.2e}); error/residual ratio median "
+          f"{np.median(ratios):.1f}, max {ratios.max():.1f}; estimate/error "
+          f"[{est.min():.3f}, {est.max():.3f}]", flush=True)
+    assert errs.max() <= 1e-7
+    # P_alpha^{-1} M = I + O(alpha): the estimate is within a few percent
+    assert 0.8 <= est.min() and est.max() <= 1.25
+    bt.close()
 
 
 def test_batch_converged_instances_and_restarts():

@@ -287,17 +287,12 @@ def test_fallback_start_rejects_a_bad_guess():
     s.close()
 
 
-def _exact_cn(p, nx, nt):
-    inst = W.config4_instance(p, nx, nt)
-    return inst, O.sequential_cn(inst.a_lo, inst.a_di, inst.a_up, inst.T, inst.nt, inst.u0,
-                                 inst.f)
-
-
 def test_learned_warm_start_gains_over_zero_start():
     """Data from plain solves, training on the GPU, then held-out instances
     solved from the network's guess and from zero: the warm start needs
     fewer iterations in total, every instance reaches the true relative
-    residual 1e-8, and sampled solutions match the exact CN solution."""
+    residual 1e-8, and every solution matches the exact CN solution (both
+    forms with error-controlled stopping at half the 1e-7 bar)."""
     banner("learned warm start 2047x512")
     torch.manual_seed(0)
     ptrain = W.config4_params(768, seed=40)
@@ -307,9 +302,9 @@ def test_learned_warm_start_gains_over_zero_start():
     net, hist = WS.train(X, Y, epochs=150, batch=128, lr=2e-3, seed=0)
     assert hist[-1] < 0.05 * hist[0], hist[::25]
     fb = WS.family_batch(ptest)
-    _, tz, pz, _ = WS.solve_family(fb)
+    _, tz, pz, _ = WS.solve_family(fb, err_tol=5e-8)
     x0, coarse = WS.initial_guess(net, fb)
-    xw, tw, pw, _ = WS.solve_family(fb, x0=x0, warm=True)
+    xw, tw, pw, _ = WS.solve_family(fb, x0=x0, warm=True, err_tol=5e-8)
     assert tz.status == B.CN_OK and tw.status == B.CN_OK
     iz = sum(r.iters for r in pz)
     iw = sum(r.iters for r in pw)
@@ -317,12 +312,17 @@ def test_learned_warm_start_gains_over_zero_start():
     print(f"zero start {iz} iterations, warm start {iw}, rejected guesses {rej}", flush=True)
     assert iw < iz and rej < len(pw) // 4
     assert all(r.relres_true <= 1e-8 for r in pw)
+    # every held-out solution against the oracle's CN time stepping, to the
+    # bar for warm-started mixed-precision forms (1e-7, relative max-norm)
     xs = xw.cpu().numpy()
     n = fb.nx * fb.nt
-    for q in (0, 37):
-        inst, u = _exact_cn(ptest[q], fb.nx, fb.nt)
-        err = rel_inf(xs[q * n:(q + 1) * n], u)
-        assert err <= max(1e-7, 50 * pw[q].relres_true), (q, err, pw[q])
+    worst = 0.0
+    for q in range(fb.count):
+        (_, lo, di, up, u0, f_col, _, _), _, _ = W.config4_rows(ptest[q], fb.nx, fb.nt)
+        u = O.sequential_cn_banded(lo, di, up, float(ptest[q][3]), fb.nt, u0, f_col=f_col)
+        worst = max(worst, rel_inf(xs[q * n:(q + 1) * n], u))
+    print(f"max error of the warm-started solutions {worst:.2e}", flush=True)
+    assert worst <= 1e-7
     net.close()
 
 
@@ -351,4 +351,45 @@ def test_predict_equals_forward_then_interpolate():
     assert torch.equal(coarse, c2) and torch.equal(x0, x2)
     with pytest.raises(B.CnError, match="128 x 64"):
         B.Mlp(67, 64, 100, 2).predict(X, nx, nt, u0, gl, gr, scale, coarse, x0)
+    net.close()
+
+
+def test_predict_batch_equals_per_instance_predict():
+    """cn_ws_predict_batch on an uneven batch (N_x in {255, 511, 1023}, N_t in
+    {64, 128, 256}) gives, instance by instance, bit for bit what
+    cn_ws_predict gives on each instance alone."""
+    banner("ws predict over an uneven batch")
+    rng = np.random.default_rng(31)
+    shapes = [(255, 64), (1023, 128), (511, 256), (255, 128), (511, 64)]
+    insts = [W.make_instance(nx, nt, T=1.0, r=0.03, K=1.0,
+                             sigma_fn=lambda x: 0.2 + 0.0 * x, alpha=0.01) for nx, nt in shapes]
+    bt = B.Batch([dict(a_lo=T(i.a_lo), a_di=T(i.a_di), a_up=T(i.a_up), nt=i.nt, T=i.T,
+                       alpha=i.alpha, m_max=4) for i in insts], pc_prec="fp32")
+    count = len(shapes)
+    net = B.Mlp(67, 64, 8192, 2)   # max_batch 2: three chunks
+    net.set_params(torch.as_tensor(WS.init_params(5, 67, 64, 8192), device=dev()))
+    X = f32(rng.standard_normal((count, 67)))
+    u0 = T(np.concatenate([rng.standard_normal(nx) for nx, _ in shapes]))
+    gl = T(np.concatenate([rng.standard_normal(nt) for _, nt in shapes]))
+    gr = T(np.concatenate([rng.standard_normal(nt) for _, nt in shapes]))
+    scale = T(rng.uniform(0.5, 2.0, count))
+    coarse = torch.empty((count, 8192), dtype=torch.float32, device=dev())
+    x0 = torch.full((bt.n,), np.nan, dtype=torch.float64, device=dev())
+    net.predict_batch(X, bt, u0, gl, gr, scale, coarse, x0)
+    uo = go = 0
+    for q, (nx, nt) in enumerate(shapes):
+        c1 = torch.empty((1, 8192), dtype=torch.float32, device=dev())
+        x1 = torch.empty(nx * nt, dtype=torch.float64, device=dev())
+        net.predict(X[q:q + 1].contiguous(), nx, nt, u0[uo:uo + nx], gl[go:go + nt],
+                    gr[go:go + nt], scale[q:q + 1], c1, x1)
+        torch.cuda.synchronize()
+        assert torch.equal(coarse[q:q + 1], c1)
+        assert torch.equal(x0[bt.offsets[q]:bt.offsets[q + 1]], x1), q
+        uo += nx
+        go += nt
+    # an instance whose grid does not fit the coarse grid is refused
+    bad = B.Batch([dict(a_lo=T(insts[0].a_lo), a_di=T(insts[0].a_di), a_up=T(insts[0].a_up),
+                        nt=32, T=1.0, alpha=0.01, m_max=4)], pc_prec="fp32")
+    with pytest.raises(B.CnError, match="multiple of 64"):
+        net.predict_batch(X[:1].contiguous(), bad, u0, gl, gr, scale, coarse, x0)
     net.close()
