@@ -168,6 +168,28 @@ cn_status cn_gmres_solve(cn_aao *h, const double *b, double *x,
 cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
                        int32_t *threads);
 
+/* Preconditioner apply that allocates nothing, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops or
+ * harnesses that forbid hipMalloc).  Computes z = P_alpha^{-1} v as
+ * cn_pc_apply does (FP64 input and output, row pitch N_x, v == z allowed)
+ * for the problem p, without a handle: p's fields as for cn_aao_create
+ * (m_max and flags unused; 0 < alpha < 1), enqueued on p->stream with no
+ * synchronisation.  Every table and work array (operator rows, alpha
+ * weights, twiddles, shifts, interface factors, tile images, interface and
+ * separator values) is built on the device, each call, in a library-owned
+ * array of CN_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs
+ * on holds until the process ends; a problem that needs more (about 13 bytes
+ * per unknown in float32, 25 in float64, plus O(N_t) tables) gets CN_EINVAL.
+ * All calls on one GPU share that array and it keeps the last call's
+ * contents: calls that overlap on one GPU (concurrent streams, threads)
+ * race.  The default transform variant is used (no autotuning), and a
+ * singular shifted system is not reported (it cannot arise for 0 < alpha < 1
+ * when A has no eigenvalue with positive real part).  The first call on each
+ * device looks up the array's address: make one call before capturing a
+ * graph. */
+#define CN_NOALLOC_SCRATCH_BYTES (64u << 20)
+cn_status cn_pc_apply_noalloc(const cn_problem *p, const double *v, double *z);
+
 /* Inspection of the last cycle's Arnoldi process (for tests; synchronises the
  * handle's stream).  The Gram-Schmidt step keeps the Gram matrix of the
  * normalised basis, G_pq = <v_p, v_q>/(||v_p|| ||v_q||), formed from the

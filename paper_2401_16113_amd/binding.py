@@ -74,6 +74,7 @@ def load():
         "cn_aao_cycle": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                         ctypes.POINTER(dbl)]),
         "cn_aao_basis": (ctypes.c_int, [vp, i32, vp]),
+        "cn_pc_apply_noalloc": (ctypes.c_int, [ctypes.POINTER(CnProblem), vp, vp]),
         "cn_rhs": (ctypes.c_int, [vp, vp, vp, vp]),
         "cn_matvec": (ctypes.c_int, [vp, vp, vp]),
         "cn_pc_apply": (ctypes.c_int, [vp, vp, vp]),
@@ -413,6 +414,22 @@ class Mlp:
                                              _ptr(gl), _ptr(gr), _ptr(scale), _f32(coarse),
                                              _ptr(x0)), "cn_ws_predict_batch")
         return x0
+
+
+def pc_apply_noalloc(a_lo, a_di, a_up, nt: int, T: float, alpha: float, v, out,
+                     pc_prec: str = "fp64", d_half=None, stream=None):
+    """z = P_alpha^{-1} v without a handle and without allocation
+    (cn_pc_apply_noalloc): the work arrays live in the library's fixed
+    per-GPU array."""
+    lib = load()
+    if stream is None:
+        stream = torch.cuda.current_stream(a_lo.device)
+    prob = CnProblem(nx=int(a_lo.numel()), nt=int(nt), m_max=1, flags=0, T=float(T),
+                     alpha=float(alpha), a_lo=_ptr(a_lo), a_di=_ptr(a_di), a_up=_ptr(a_up),
+                     d_half=_ptr(d_half), pc_prec=CN_PC_FP32 if pc_prec == "fp32" else CN_PC_FP64,
+                     stream=ctypes.c_void_p(stream.cuda_stream))
+    _check(lib.cn_pc_apply_noalloc(ctypes.byref(prob), _ptr(v), _ptr(out)), "cn_pc_apply_noalloc")
+    return out
 
 
 def ws_restrict(x, count: int, nx: int, nt: int, inv_scale, coarse, stream=None):

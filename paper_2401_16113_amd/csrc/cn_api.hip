@@ -1562,3 +1562,210 @@ cn_status cn_batch_solve(cn_batch* b, const double* bp, double* xp, const cn_gmr
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free preconditioner apply.  Every table and work array of one
+// apply lives in `scratch`, a file-scope device array of
+// CN_NOALLOC_SCRATCH_BYTES (one copy per GPU, held until the process ends,
+// shared by all calls on that GPU).  Host code uses the array only through
+// the device address looked up per device (the symbol itself is a host-side
+// stand-in).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[CN_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char*> g_scratch_ptr;
+
+// Device address of `scratch` on the current device: looked up on the first
+// call on each device (with that device current) and kept.
+static hipError_t scratch_base(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (ptr == nullptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[dev] = (unsigned char*)ptr;
+  *out = (unsigned char*)ptr;
+  return hipSuccess;
+}
+
+// The tables of one apply, computed on the device from the same definitions
+// as the handle's host-side tables (float64 here, long double there):
+// tau A rows with the boundary couplings cleared, alpha^{k/N_t} and
+// alpha^{-k/N_t}/N_t, the twiddles exp(-2 pi i m/N_t) (full and two-level),
+// mu_j = lambda_{1,j}/lambda_{2,j} and 1/lambda_{2,j} with
+// lambda_{1,j} = 1 - alpha^{1/N_t} w^j, lambda_{2,j} = dbar (1 + alpha^{1/N_t} w^j)/2
+// (dbar: the mean time weight, 1 without weights).  Block 0 also writes the
+// instance descriptor and clears the set-up flag.
+__global__ void k_noalloc_tables(const double* __restrict__ a_lo, const double* __restrict__ a_di,
+                                 const double* __restrict__ a_up, const double* __restrict__ dw,
+                                 int nx, int nt, double tau, double alpha, InstDesc desc,
+                                 InstDesc* dst, int* err) {
+  __shared__ double red[256];
+  const PcPlan& pl = desc.pl;
+  const int t = threadIdx.x;
+  double s = 0.0;
+  if (dw != nullptr)
+    for (int k = t; k < nt; k += 256) s += dw[k];
+  red[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  const double dbar = dw != nullptr ? red[0] / nt : 1.0;
+  const int gid = blockIdx.x * 256 + t, gs = gridDim.x * 256;
+  if (gid == 0) {
+    *dst = desc;
+    *err = 0;
+  }
+  for (int i = gid; i < nx; i += gs) {
+    pl.lo[i] = i == 0 ? 0.0 : tau * a_lo[i];
+    pl.di[i] = tau * a_di[i];
+    pl.up[i] = i == nx - 1 ? 0.0 : tau * a_up[i];
+  }
+  const double la = log(alpha);
+  const int wsl = nt < 64 ? nt : 64, wsh = nt / wsl;
+  for (int k = gid; k < nt; k += gs) {
+    pl.wfw[k] = exp(la * k / nt);
+    pl.winv[k] = exp(-la * k / nt) / nt;
+    double sn, cs;
+    sincospi(-2.0 * k / nt, &sn, &cs);
+    pl.tw[k] = Cx<double>{cs, sn};
+    pl.tw_f[k] = Cx<float>{(float)cs, (float)sn};
+  }
+  for (int e = gid; e < wsl + wsh; e += gs) {
+    const int k = e < wsl ? e : (e - wsl) * wsl;
+    double sn, cs;
+    sincospi(-2.0 * k / nt, &sn, &cs);
+    pl.tw2[e] = Cx<double>{cs, sn};
+    pl.tw2_f[e] = Cx<float>{(float)cs, (float)sn};
+  }
+  const double a1 = exp(la / nt);
+  for (int j = gid; j < pl.F; j += gs) {
+    double wr = 1.0, wi = 0.0;
+    if (2 * j == nt) {
+      wr = -1.0;
+    } else if (j != 0) {
+      sincospi(-2.0 * j / nt, &wi, &wr);
+    }
+    const double l1r = 1.0 - a1 * wr, l1i = -a1 * wi;
+    const double l2r = 0.5 * dbar * (1.0 + a1 * wr), l2i = 0.5 * dbar * a1 * wi;
+    const double den = l2r * l2r + l2i * l2i;
+    pl.mu[j] = Cx<double>{(l1r * l2r + l1i * l2i) / den, (l1i * l2r - l1r * l2i) / den};
+    pl.il2[j] = Cx<double>{l2r / den, -l2i / den};
+  }
+}
+
+extern "C" {
+
+cn_status cn_pc_apply_noalloc(const cn_problem* p, const double* v, double* z) {
+  if (p == nullptr || v == nullptr || z == nullptr) return fail(CN_EINVAL, "NULL argument");
+  if (p->nx < 1) return fail(CN_EINVAL, "nx must be >= 1");
+  if (p->nt < 1 || p->nt > 8192 || (p->nt & (p->nt - 1)) != 0)
+    return fail(CN_EINVAL, "nt must be a power of two in [1, 8192]");
+  if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(CN_EINVAL, "T must be finite and > 0");
+  if (!(p->alpha > 0.0) || !(p->alpha < 1.0)) return fail(CN_EINVAL, "alpha must satisfy 0 < alpha < 1");
+  if (p->pc_prec != CN_PC_FP64 && p->pc_prec != CN_PC_FP32)
+    return fail(CN_EINVAL, "pc_prec must be CN_PC_FP64 or CN_PC_FP32");
+  if (p->a_lo == nullptr || p->a_di == nullptr || p->a_up == nullptr)
+    return fail(CN_EINVAL, "A diagonals must be device pointers");
+  const int nx = p->nx, nt = p->nt;
+  const int prec = p->pc_prec == CN_PC_FP32 ? 1 : 0;
+  const size_t rsz = prec ? sizeof(float) : sizeof(double);
+  int log2n = 0;
+  while ((1 << log2n) < nt) ++log2n;
+  int B = 0, T = 0;
+  if (!pc_candidate(prec, log2n, 0, &B, &T)) return fail(CN_EINVAL, "no transform variant");
+  const int F = nt / 2 + 1, P = (nx + B - 1) / B, NS = P - 1;
+  const size_t ns1 = (size_t)std::max(NS, 1);
+  const int wsl = std::min(nt, 64), wsh = nt / wsl;
+  // layout of the scratch array (256-byte aligned pieces)
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t o_desc = take(sizeof(InstDesc));
+  const size_t o_lo = take(nx * sizeof(double)), o_di = take(nx * sizeof(double)),
+               o_up = take(nx * sizeof(double));
+  const size_t o_wfw = take(nt * sizeof(double)), o_winv = take(nt * sizeof(double));
+  const size_t o_tw = take(nt * sizeof(Cx<double>)), o_twf = take(nt * sizeof(Cx<float>));
+  const size_t o_tw2 = take((wsl + wsh) * sizeof(Cx<double>)),
+               o_tw2f = take((wsl + wsh) * sizeof(Cx<float>));
+  const size_t o_mu = take(F * sizeof(Cx<double>)), o_il2 = take(F * sizeof(Cx<double>));
+  const size_t o_spec = take((size_t)P * B * nt * rsz);
+  const size_t o_iface = take((size_t)F * P * 2 * 2 * rsz);
+  const size_t o_sep = take((size_t)F * ns1 * 2 * rsz);
+  const size_t o_recf = take((size_t)F * ns1 * 2 * 2 * rsz), o_recb = take((size_t)F * ns1 * 2 * rsz);
+  const size_t o_tmp = take((size_t)F * ns1 * sizeof(Cx<double>));
+  const size_t o_spk = take((size_t)F * P * 4 * sizeof(Cx<double>));
+  const size_t o_err = take(sizeof(int));
+  if (off > (size_t)CN_NOALLOC_SCRATCH_BYTES)
+    return fail(CN_EINVAL, "problem needs " + std::to_string(off) + " bytes of scratch, more than " +
+                               std::to_string((size_t)CN_NOALLOC_SCRATCH_BYTES));
+  unsigned char* base = nullptr;
+  HIP_TRY(scratch_base(&base));
+  PcPlan pl;
+  pl.nx = nx;
+  pl.nt = nt;
+  pl.log2n = log2n;
+  pl.F = F;
+  pl.prec = prec;
+  pl.B = B;
+  pl.P = P;
+  pl.NS = NS;
+  pl.T = T;
+  pl.cand = 0;
+  pl.alpha = p->alpha;
+  pl.lo = (double*)(base + o_lo);
+  pl.di = (double*)(base + o_di);
+  pl.up = (double*)(base + o_up);
+  pl.wfw = (double*)(base + o_wfw);
+  pl.winv = (double*)(base + o_winv);
+  pl.tw = (Cx<double>*)(base + o_tw);
+  pl.tw_f = (Cx<float>*)(base + o_twf);
+  pl.tw2 = (Cx<double>*)(base + o_tw2);
+  pl.tw2_f = (Cx<float>*)(base + o_tw2f);
+  pl.mu = (Cx<double>*)(base + o_mu);
+  pl.il2 = (Cx<double>*)(base + o_il2);
+  pl.spec = base + o_spec;
+  pl.iface = base + o_iface;
+  pl.sep = base + o_sep;
+  pl.recf = base + o_recf;
+  pl.recb = base + o_recb;
+  pl.red_tmp = (Cx<double>*)(base + o_tmp);
+  InstDesc desc{};
+  desc.pl = pl;
+  desc.nx = nx;
+  desc.nt = nt;
+  desc.n = (long long)nx * nt;
+  desc.ldx = (nx + 15) / 16 * 16;
+  desc.nin = (long long)nt * desc.ldx;
+  desc.zf = 0;
+  InstDesc* d_desc = (InstDesc*)(base + o_desc);
+  int* err = (int*)(base + o_err);
+  hipStream_t s = (hipStream_t)p->stream;
+  const int grid = (int)std::min<long long>(1024, (std::max(nx, nt) + 255) / 256);
+  hipLaunchKernelGGL(k_noalloc_tables, dim3(grid), dim3(256), 0, s, p->a_lo, p->a_di, p->a_up,
+                     p->d_half, nx, nt, p->T / nt, p->alpha, desc, d_desc, err);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(pc_setup(pl, (Cx<double>*)(base + o_spk), err, s));
+  const Launch L{d_desc, 1, 0};
+  const Items ipc{nullptr, P}, ik2{nullptr, NS > 0 ? F : 0};
+  HIP_TRY(pc_forward(prec, log2n, 0, L, ipc, 0, v, nx, s));
+  HIP_TRY(pc_reduced(prec, L, ik2, k2_chunk_class(NS, prec), 0, 1, s));
+  HIP_TRY(pc_inverse(prec, log2n, 0, L, ipc, 0, z, 0, nx, s));
+  return CN_OK;
+}
+
+}  // extern "C"
