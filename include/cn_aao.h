@@ -163,10 +163,11 @@ cn_status cn_gmres_solve(cn_aao *h, const double *b, double *x,
                          const cn_gmres_opts *opts, cn_gmres_info *info);
 
 /* Sizes chosen at creation (for tests and tooling): tile width of the
- * partitioned step-(b) solve, number of tiles and workgroup size of the
- * transform kernels.  Any pointer may be NULL. */
+ * partitioned step-(b) solve, number of tiles, workgroup size of the
+ * transform kernels and workgroups per tile of the inverse transform (1 or
+ * 2: each inverts half of the tile's columns).  Any pointer may be NULL. */
 cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
-                       int32_t *threads);
+                       int32_t *threads, int32_t *inverse_split);
 
 /* Preconditioner apply that allocates nothing, for callers that cannot
  * allocate device memory (code under HIP graph capture, serving loops or

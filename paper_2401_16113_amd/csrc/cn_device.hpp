@@ -236,19 +236,28 @@ struct PcCfg {
 // default.  A candidate is compiled for 64 <= N_t <= 4096 when its tile
 // image fits the LDS, every thread owns at least one element and the
 // tile-solve registers fit the VGPR budget of its workgroup size.
-constexpr int kNumCand = 9;
-constexpr int kCandB[kNumCand] = {0, 16, 16, 16, 8, 8, 8, 4, 4};
-constexpr int kCandT[kNumCand] = {0, 256, 512, 1024, 256, 512, 1024, 256, 512};
+// S: workgroups per tile of K3.  With S = 2 each workgroup inverts half of
+// the tile's sequences (the interface correction, which couples all B
+// columns, is formed by both), so K3 needs half the LDS per workgroup and
+// runs twice as many workgroups per CU; K1 is the same as for S = 1.
+constexpr int kNumCand = 13;
+constexpr int kCandB[kNumCand] = {0, 16, 16, 16, 8, 8, 8, 4, 4, 16, 16, 8, 8};
+constexpr int kCandT[kNumCand] = {0, 256, 512, 1024, 256, 512, 1024, 256, 512, 256, 512, 256, 512};
+constexpr int kCandS[kNumCand] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2};
 
 template <typename R, int LOG2N, int CI>
 struct PcCand {
   static constexpr int B = CI == 0 ? PcDefault<R, LOG2N>::B : kCandB[CI];
   static constexpr int T = CI == 0 ? PcDefault<R, LOG2N>::T : kCandT[CI];
+  static constexpr int S = kCandS[CI];
   using Cfg = PcCfg<R, LOG2N, B, T>;
-  static constexpr bool dup = CI != 0 && B == PcDefault<R, LOG2N>::B && T == PcDefault<R, LOG2N>::T;
+  using CfgF = PcCfg<R, LOG2N, B / S, T>;  // K3's part of a tile
+  static constexpr bool dup =
+      CI != 0 && S == 1 && B == PcDefault<R, LOG2N>::B && T == PcDefault<R, LOG2N>::T;
   static constexpr bool ok =
       CI == 0 || (!dup && LOG2N >= 6 && LOG2N <= 12 && Cfg::LDS_BYTES <= kLdsCap &&
-                  Cfg::ELEMS >= T && (T < 1024 || B * (int)sizeof(R) <= 64));
+                  Cfg::ELEMS >= T && (T < 1024 || B * (int)sizeof(R) <= 64) &&
+                  (S == 1 || (B >= 8 && CfgF::ELEMS >= T)));
 };
 
 // threadIdx.x through an empty asm: index arithmetic derived from it cannot be

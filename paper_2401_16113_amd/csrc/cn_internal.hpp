@@ -18,7 +18,8 @@ struct PcPlan {
   int nx = 0, nt = 0, log2n = 0, F = 0;  // F = nt/2 + 1 frequency lines kept
   int prec = 0;                           // 0: float64, 1: float32
   int B = 0, P = 0, NS = 0, T = 0;        // tile cols, tiles, separators, threads
-  int cand = 0;                           // compiled (B, T) variant (0 = default)
+  int S = 1;                              // K3 workgroups per tile
+  int cand = 0;                           // compiled (B, T, S) variant (0 = default)
   double alpha = 0, dbar = 1;
   // device tables
   double *lo = nullptr, *di = nullptr, *up = nullptr;   // tau*A rows
@@ -107,9 +108,10 @@ struct InstDesc {
   GState* st;             // solver state
   GSummary* host;         // the instance's summary slot in pinned host memory
   int zf;                 // Z stored in float32
-  int zlog;               // Z is tile-blocked with tile width 2^zlog (the
+  int zlog;               // Z is tile-blocked with block width 2^zlog (the
                           // transform tile width): element (k, i) of Z_j at
-                          // ((i >> zlog) N_t + k) 2^zlog + (i mod 2^zlog)
+                          // ((i >> zlog) N_t + k) 2^zlog + (i mod 2^zlog);
+                          // -1: row-major with pitch ldx
   const StopCtl* ctl;     // per-solve stopping controls of the instance
 };
 
@@ -128,7 +130,7 @@ struct VecLayout {
 };
 __device__ __forceinline__ VecLayout row_major(int pitch, int nt) { return VecLayout{pitch, -1, nt}; }
 __device__ __forceinline__ VecLayout z_layout(const InstDesc& d) {
-  return VecLayout{1 << d.zlog, d.zlog, d.nt};
+  return d.zlog < 0 ? VecLayout{d.ldx, -1, d.nt} : VecLayout{1 << d.zlog, d.zlog, d.nt};
 }
 
 // Launch context shared by the kernels of one handle or batch.
@@ -167,7 +169,7 @@ hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int chunk_clas
 hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
                       void* z, int zf, int pitch, hipStream_t s);
 // (B, T) of compiled candidate `ci`; false if that candidate is not compiled
-bool pc_candidate(int prec, int log2n, int ci, int* B, int* T);
+bool pc_candidate(int prec, int log2n, int ci, int* B, int* T, int* S = nullptr);
 // Krylov launchers (cn_krylov.hip)
 constexpr int KT = 512;     // threads per workgroup of the streaming Krylov kernels
 constexpr int KGRID = 512;  // most workgroups of a streaming pass (= partial sums

@@ -436,10 +436,13 @@ hipError_t pc_inverse_f64(int, int, const Launch&, const Items&, int, void*, int
                           hipStream_t);
 hipError_t pc_inverse_f32(int, int, const Launch&, const Items&, int, void*, int, int,
                           hipStream_t);
-bool pc_candidate_f64(int log2n, int ci, int* B, int* T);
-bool pc_candidate_f32(int log2n, int ci, int* B, int* T);
-bool pc_candidate(int prec, int log2n, int ci, int* B, int* T) {
-  return prec ? pc_candidate_f32(log2n, ci, B, T) : pc_candidate_f64(log2n, ci, B, T);
+bool pc_candidate_f64(int log2n, int ci, int* B, int* T, int* S);
+bool pc_candidate_f32(int log2n, int ci, int* B, int* T, int* S);
+bool pc_candidate(int prec, int log2n, int ci, int* B, int* T, int* S) {
+  int s = 1;
+  const bool ok = prec ? pc_candidate_f32(log2n, ci, B, T, &s) : pc_candidate_f64(log2n, ci, B, T, &s);
+  if (S != nullptr) *S = s;
+  return ok;
 }
 
 hipError_t pc_forward(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,

@@ -231,23 +231,29 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
 // ---------------------------------------------------------------------------
 // K3
 // ---------------------------------------------------------------------------
-template <typename R, int LOG2N, int BB, int TT, typename TZ>
+// Workgroup hf of the SPL that serve tile p inverts the tile's sequences
+// [hf NSEQ/SPL, (hf+1) NSEQ/SPL) (columns [hf B/SPL, (hf+1) B/SPL)); each
+// forms the interface correction of the whole tile (it couples all B
+// columns) and applies it to its own sequences.
+template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL>
 __device__ __forceinline__ void pc_inverse_tile(
-    int p, const CN_G int* stop, const CN_G Cx<R>* __restrict__ spec,
+    int p, int hf, const CN_G int* stop, const CN_G Cx<R>* __restrict__ spec,
     const CN_G Cx<R>* __restrict__ sep, const CN_G double* __restrict__ lo,
     const CN_G double* __restrict__ di, const CN_G double* __restrict__ up,
     const CN_G double* __restrict__ winv, const Cx<R>* __restrict__ tw,
     const CN_G Cx<double>* __restrict__ mu, CN_G TZ* __restrict__ z, int nx, int zp, int P,
     int NS) {
-  using Cfg = PcCfg<R, LOG2N, BB, TT>;
+  using Cfg = PcCfg<R, LOG2N, BB, TT>;          // the tile (interface correction)
+  using CfgF = PcCfg<R, LOG2N, BB / SPL, TT>;   // the part this workgroup inverts
   constexpr int N = Cfg::N, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
-  __shared__ Cx<R> lds[Cfg::LDS_ELEMS];
-  __shared__ Cx<R> ltw[Cfg::TWN];
+  constexpr int BF = CfgF::B, NSF = CfgF::NSEQ;
+  __shared__ Cx<R> lds[CfgF::LDS_ELEMS];
+  __shared__ Cx<R> ltw[CfgF::TWN];
   __shared__ R co[3 * B];
   const int tid = threadIdx.x;
   const int i0 = p * B;
   const int ncols = min(B, nx - i0);
-  const CN_G Cx<R>* img = spec + (size_t)p * NSEQ * N;
+  const CN_G Cx<R>* img = spec + ((size_t)p * NSEQ + (size_t)hf * NSF) * N;
   constexpr int NTK = Cfg::NTK;
   const Cx<R> zero{R(0), R(0)};
   Cx<R> slv[NTK], srv[NTK];
@@ -255,18 +261,18 @@ __device__ __forceinline__ void pc_inverse_tile(
   // the stop flag first, as a uniform scalar load; then every vector load of
   // the phase is issued before any is consumed (see K1)
   const int stopped = stop != nullptr ? *stop : 0;
-  // inverse weights alpha^{-k/N_t}/N_t of the thread's levels k = tid/B +
-  // q T/B by recurrence, as in K1: w_q = w_0 rho^q, rho = alpha^{-(T/B)/N_t}
-  static_assert(T % B == 0, "the workgroup size must be a multiple of the tile width");
-  double w = winv[min(tid / B, N - 1)];
-  const double rho = winv[T / B < N ? T / B : 0] * (double)N;
+  // inverse weights alpha^{-k/N_t}/N_t of the thread's levels k = tid/BF +
+  // q T/BF by recurrence, as in K1: w_q = w_0 rho^q, rho = alpha^{-(T/BF)/N_t}
+  static_assert(T % BF == 0, "the workgroup size must be a multiple of the part width");
+  double w = winv[min(tid / BF, N - 1)];
+  const double rho = winv[T / BF < N ? T / BF : 0] * (double)N;
   {
-    constexpr int SPT = (NSEQ * N + T - 1) / T;
+    constexpr int SPT = (NSF * N + T - 1) / T;
     Cx<R> iv[SPT];
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int e = tid + q * T;
-      if ((NSEQ * N) % T == 0 || e < NSEQ * N) iv[q] = gld(img + e);
+      if ((NSF * N) % T == 0 || e < NSF * N) iv[q] = gld(img + e);
     }
     // the separator values of the thread's frequencies and their shifts are
     // requested with the image (task u: t = tid + u T; t = 0 solves the real
@@ -289,8 +295,8 @@ __device__ __forceinline__ void pc_inverse_tile(
         tmd[u] = gld(mu + t);
       }
     }
-    TwStage<R, Cfg::TWN, T, Cfg::TWPT> tws;
-    if constexpr (Cfg::TWL) tws.fetch(gp(tw));
+    TwStage<R, CfgF::TWN, T, CfgF::TWPT> tws;
+    if constexpr (CfgF::TWL) tws.fetch(gp(tw));
     double cov = 0.0;
     if (tid < 3 * B) {
       const int b = min(tid / 3, ncols - 1), c = tid % 3;
@@ -301,9 +307,9 @@ __device__ __forceinline__ void pc_inverse_tile(
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int e = tid + q * T;
-      if ((NSEQ * N) % T == 0 || e < NSEQ * N) lds[lidx<N>(e / N, e % N)] = iv[q];
+      if ((NSF * N) % T == 0 || e < NSF * N) lds[lidx<N>(e / N, e % N)] = iv[q];
     }
-    if constexpr (Cfg::TWL) tws.store(ltw);
+    if constexpr (CfgF::TWL) tws.store(ltw);
   }
   __syncthreads();
   const bool has_sep = p < P - 1;
@@ -330,13 +336,17 @@ __device__ __forceinline__ void pc_inverse_tile(
         for (int b = 0; b < B; ++b)
           if (b == nb - 1) d[b] = d[b] + co[3 * b + 2] * sr;
         tile_solve<R, R, B>(d, m, co, nb);
+        // sequence c of the tile (columns 2c, 2c+1) is local sequence c - hf NSF
+        // (the loop runs over the whole tile, so d is indexed by constants)
 #pragma unroll
         for (int c = 0; c < NSEQ; ++c) {
-          const Cx<R> yv = lds[lidx<N>(c, j)];
+          if (c / NSF != hf) continue;
+          const int cl = c - hf * NSF;
+          const Cx<R> yv = lds[lidx<N>(cl, j)];
           R xa = yv.x + d[2 * c], xb = yv.y + d[2 * c + 1];
           if (2 * c >= nb) xa = (2 * c == B - 1 && has_sep) ? sr : R(0);
           if (2 * c + 1 >= nb) xb = (2 * c + 1 == B - 1 && has_sep) ? sr : R(0);
-          lds[lidx<N>(c, j)] = Cx<R>{xa, xb};
+          lds[lidx<N>(cl, j)] = Cx<R>{xa, xb};
         }
       }
     } else {
@@ -353,32 +363,38 @@ __device__ __forceinline__ void pc_inverse_tile(
       tile_solve<R, Cx<R>, B>(d, m, co, nb);
 #pragma unroll
       for (int c = 0; c < NSEQ; ++c) {
-        Cx<R> xa = lds[lidx<N>(c, j)] + d[2 * c];
-        Cx<R> xb = lds[lidx<N>(c, N - j)] + d[2 * c + 1];
+        if (c / NSF != hf) continue;
+        const int cl = c - hf * NSF;
+        Cx<R> xa = lds[lidx<N>(cl, j)] + d[2 * c];
+        Cx<R> xb = lds[lidx<N>(cl, N - j)] + d[2 * c + 1];
         if (2 * c >= nb) xa = (2 * c == B - 1 && has_sep) ? sr : zero;
         if (2 * c + 1 >= nb) xb = (2 * c + 1 == B - 1 && has_sep) ? sr : zero;
         // Z'_j = X_{2c} + i X_{2c+1}; Z'_{N-j} = conj(X_{2c}) + i conj(X_{2c+1})
-        lds[lidx<N>(c, j)] = Cx<R>{xa.x - xb.y, xa.y + xb.x};
-        lds[lidx<N>(c, N - j)] = Cx<R>{xa.x + xb.y, xb.x - xa.y};
+        lds[lidx<N>(cl, j)] = Cx<R>{xa.x - xb.y, xa.y + xb.x};
+        lds[lidx<N>(cl, N - j)] = Cx<R>{xa.x + xb.y, xb.x - xa.y};
       }
     }
   }
   __syncthreads();
-  fft_tile<Cfg, R, LOG2N, true>(lds, ltw, tw, threadIdx.x);
+  fft_tile<CfgF, R, LOG2N, true>(lds, ltw, tw, threadIdx.x);
   const R* ldsr = reinterpret_cast<const R*>(lds);
   {
-    constexpr int LPT = (N * B + T - 1) / T;
+    constexpr int LPT = (N * BF + T - 1) / T;
+    const int c0 = hf * BF;  // first column of the part within the tile
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int e = tid + q * T;
-      const int k = e / B, b = e % B;
+      const int k = e / BF, b = e % BF;
       const double wq = w;
       w *= rho;
-      if (((N * B) % T == 0 || e < N * B) && b < ncols) {
+      if (((N * BF) % T == 0 || e < N * BF) && c0 + b < ncols) {
         const double val = (double)ldsr[2 * lidx<N>(b >> 1, k) + (b & 1)] * wq;
         // zp > 0: row-major with pitch zp; 0: tile-blocked (the tile's B x N_t
-        // block is contiguous: element (k, b) at (p N_t + k) B + b)
-        const size_t zi = zp > 0 ? (size_t)k * zp + i0 + b : (size_t)p * N * B + (size_t)e;
+        // block is contiguous: element (k, c) at (p N_t + k) B + c; the SPL
+        // parts of a tile fill the rows of one block, and the Krylov kernels
+        // read blocks of the full tile width much faster than narrower ones)
+        const size_t zi = zp > 0 ? (size_t)k * zp + i0 + c0 + b
+                                 : ((size_t)p * N + k) * B + c0 + b;
         z[zi] = (TZ)val;
       }
     }
@@ -386,27 +402,31 @@ __device__ __forceinline__ void pc_inverse_tile(
 }
 
 // z_ovr: output vector instead of Z_j; pitch: its row pitch (row-major), or 0
-// for the tile-blocked layout of Z
-template <typename R, int LOG2N, int BB, int TT, typename TZ>
+// for the tile-blocked layout of Z.  SPL workgroups per tile item: nitems
+// counts tiles, the grid covers SPL nitems parts (the parts of one tile are
+// consecutive, so they share an XCD).
+template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL>
 __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ D,
                                                    const int2* __restrict__ items, int nitems,
                                                    int nitems_pad, int jv, TZ* __restrict__ z_ovr,
                                                    int pitch) {
   const int itx = xcd_tile(blockIdx.x, nitems_pad);
-  if (itx >= nitems) return;
-  const int2 wi = work_item(items, itx);
+  if (itx >= nitems * SPL) return;
+  const int2 wi = work_item(items, itx / SPL);
+  const int hf = itx % SPL;
   const InstDesc& d = D[wi.x];
   const PcPlan& pl = d.pl;
   TZ* z = z_ovr != nullptr ? z_ovr : (TZ*)d.Z + (size_t)jv * d.vstride;
-  using Cfg = PcCfg<R, LOG2N, BB, TT>;
-  const Cx<R>* tw = Cfg::TWMODE == 3
+  using CfgF = PcCfg<R, LOG2N, BB / SPL, TT>;
+  const Cx<R>* tw = CfgF::TWMODE == 3
                         ? (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw2 : (const Cx<R>*)pl.tw2_f)
                         : (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f);
-  pc_inverse_tile<R, LOG2N, BB, TT, TZ>(wi.y, z_ovr == nullptr ? gp(&d.st->sum.done) : nullptr,
+  pc_inverse_tile<R, LOG2N, BB, TT, TZ, SPL>(wi.y, hf, z_ovr == nullptr ? gp(&d.st->sum.done) : nullptr,
                                         gp((const Cx<R>*)pl.spec), gp((const Cx<R>*)pl.sep),
                                         gp(pl.lo), gp(pl.di), gp(pl.up), gp(pl.winv), tw,
                                         gp((const Cx<double>*)pl.mu), gp(z), pl.nx,
-                                        pitch > 0 ? pitch : 0, pl.P, pl.NS);
+                                        pitch > 0 ? pitch : (z_ovr == nullptr && d.zlog < 0 ? d.ldx : 0),
+                                        pl.P, pl.NS);
 }
 
 // ---------------------------------------------------------------------------
@@ -437,13 +457,13 @@ static hipError_t launch_inv_c(const Launch& Lc, const Items& it, int j, void* z
     return hipErrorInvalidValue;
   } else {
     if (it.n <= 0) return hipSuccess;
-    const int nwg = pad8(it.n);
+    const int nwg = pad8(it.n * C::S);
     if (zf)
-      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, float>), dim3(nwg), dim3(C::T), 0, s,
-                         Lc.D, it.it, it.n, nwg, j, (float*)z, pitch);
+      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, float, C::S>), dim3(nwg), dim3(C::T), 0,
+                         s, Lc.D, it.it, it.n, nwg, j, (float*)z, pitch);
     else
-      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, double>), dim3(nwg), dim3(C::T), 0, s,
-                         Lc.D, it.it, it.n, nwg, j, (double*)z, pitch);
+      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, double, C::S>), dim3(nwg), dim3(C::T), 0,
+                         s, Lc.D, it.it, it.n, nwg, j, (double*)z, pitch);
     return hipGetLastError();
   }
 }
@@ -471,16 +491,17 @@ static hipError_t inv_cand(int ci, const Launch& Lc, const Items& it, int j, voi
 }
 
 template <typename R, int L, int CI = 0>
-static bool cand_info(int ci, int* B, int* T) {
+static bool cand_info(int ci, int* B, int* T, int* S) {
   if constexpr (CI >= kNumCand) {
     return false;
   } else {
     if (ci == CI) {
       *B = PcCand<R, L, CI>::B;
       *T = PcCand<R, L, CI>::T;
+      *S = PcCand<R, L, CI>::S;
       return PcCand<R, L, CI>::ok;
     }
-    return cand_info<R, L, CI + 1>(ci, B, T);
+    return cand_info<R, L, CI + 1>(ci, B, T, S);
   }
 }
 
@@ -502,7 +523,7 @@ static bool cand_info(int ci, int* B, int* T) {
     }                                                                                         \
     return hipErrorInvalidValue;                                                              \
   }                                                                                           \
-  bool pc_candidate_##SUF(int log2n, int ci, int* B, int* T) {                                \
+  bool pc_candidate_##SUF(int log2n, int ci, int* B, int* T, int* S) {                        \
     switch (log2n) {                                                                          \
       CN_LOG2N_CASES(CN_INFO_CASE_##SUF)                                                      \
     }                                                                                         \

@@ -234,3 +234,85 @@ def config5(nx: int = 65535, nt: int = 4096, seed: int = 5) -> Instance:
 
 def random_vector(n: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(n)
+
+
+# ---------------------------------------------------------------------------
+# 2D drift-diffusion operators on a tensor grid (synthetic stand-ins for the
+# 2D operators of Sec. 5; none of the paper's model parameters are used)
+# ---------------------------------------------------------------------------
+
+# stencil entry q of grid point i multiplies the unknown at (iy + dy, ix + dx),
+# q = 3 (dy + 1) + (dx + 1); unknown i = iy N_x + ix (x fastest)
+STENCIL_OFFSETS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+@dataclass
+class Instance2D:
+    nx: int
+    ny: int
+    nt: int
+    T: float
+    alpha: float
+    st: np.ndarray        # (9, N_x N_y) stencil coefficients of A
+    u0: np.ndarray        # (N_x N_y,) initial condition
+    f: np.ndarray         # (N_t, N_x N_y) source blocks f^{k+1/2}
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nt
+
+    @property
+    def npts(self) -> int:
+        return self.nx * self.ny
+
+
+def drift_diffusion_2d_stencil(nx: int, ny: int, a, b, c, d, e, r):
+    """Nine-point central-difference stencil of
+        A u = a u_xx + b u_yy + c u_xy + d u_x + e u_y - r u
+    on the interior nodes of the unit square (h_x = 1/(N_x+1),
+    h_y = 1/(N_y+1)), homogeneous Dirichlet data outside; a..r are functions
+    of (x, y) evaluated at the nodes (or constants)."""
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    X, Y = np.meshgrid(np.arange(1, nx + 1) * hx, np.arange(1, ny + 1) * hy)
+    ev = lambda g: np.broadcast_to(np.asarray(g(X, Y) if callable(g) else g, dtype=np.float64),
+                                   X.shape).reshape(-1)
+    A_, B_, C_, D_, E_, R_ = (ev(g) for g in (a, b, c, d, e, r))
+    st = np.zeros((9, nx * ny))
+    q = {o: k for k, o in enumerate(STENCIL_OFFSETS)}
+    st[q[(0, -1)]] = A_ / hx ** 2 - D_ / (2 * hx)
+    st[q[(0, 1)]] = A_ / hx ** 2 + D_ / (2 * hx)
+    st[q[(-1, 0)]] = B_ / hy ** 2 - E_ / (2 * hy)
+    st[q[(1, 0)]] = B_ / hy ** 2 + E_ / (2 * hy)
+    st[q[(0, 0)]] = -2 * A_ / hx ** 2 - 2 * B_ / hy ** 2 - R_
+    cm = C_ / (4 * hx * hy)
+    st[q[(1, 1)]] = cm
+    st[q[(-1, -1)]] = cm
+    st[q[(1, -1)]] = -cm
+    st[q[(-1, 1)]] = -cm
+    return st
+
+
+def drift_diffusion_2d(nx: int, ny: int, nt: int, T: float = 0.5, alpha: float = 0.01,
+                       seed: int = 21, mixed: float = 0.0) -> Instance2D:
+    """Seeded variable-coefficient drift-diffusion-reaction operator (not
+    separable: every coefficient depends on x and y), a smooth bump as the
+    initial condition and a small smooth source.  `mixed` scales a mixed
+    derivative term c = mixed sqrt(a b).  The cell Peclet numbers stay below
+    1, so with mixed = 0 the stencil is an M-matrix pattern (weakly
+    diagonally dominant rows)."""
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(0.8, 1.2, size=8)
+    a = lambda x, y: 0.20 * p[0] * (1.0 + 0.3 * np.sin(np.pi * x) * np.cos(np.pi * y))
+    b = lambda x, y: 0.10 * p[1] * (1.0 + 0.3 * np.cos(2 * np.pi * x * y))
+    d = lambda x, y: 0.3 * p[2] * np.cos(np.pi * y) * (1.0 - x)
+    e = lambda x, y: 0.2 * p[3] * np.sin(np.pi * x) - 0.1 * p[4]
+    r = 0.05 * p[5]
+    c = lambda x, y: mixed * np.sqrt(a(x, y) * b(x, y))
+    st = drift_diffusion_2d_stencil(nx, ny, a, b, c, d, e, r)
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    X, Y = np.meshgrid(np.arange(1, nx + 1) * hx, np.arange(1, ny + 1) * hy)
+    u0 = (np.exp(-40 * ((X - 0.4 * p[6]) ** 2 + (Y - 0.5) ** 2))).reshape(-1)
+    tk = (np.arange(nt) + 0.5) * (T / nt)
+    f = 0.1 * p[7] * np.outer(np.exp(-tk), (np.sin(np.pi * X) * np.sin(np.pi * Y)).reshape(-1))
+    return Instance2D(nx, ny, nt, T, alpha, st, u0, f, name=f"dd2d-{nx}x{ny}x{nt}")

@@ -339,31 +339,42 @@ def test_aliasing_rejected():
 # every compiled (tile width, workgroup size) variant of the transform kernels
 # ---------------------------------------------------------------------------
 
-VARIANTS = [(16, 256), (16, 512), (16, 1024), (8, 256), (8, 512), (8, 1024), (4, 256),
-            (4, 512)]
+# (tile columns, threads, inverse-transform workgroups per tile)
+VARIANTS = [(16, 256, 1), (16, 512, 1), (16, 1024, 1), (8, 256, 1), (8, 512, 1), (8, 1024, 1),
+            (4, 256, 1), (4, 512, 1), (16, 256, 2), (16, 512, 2), (8, 256, 2), (8, 512, 2)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("nx,nt", [(300, 64), (1000, 512), (257, 1024), (255, 4096)])
 def test_pc_apply_every_variant(nx, nt, prec, monkeypatch):
-    """The autotuner may pick any compiled variant: each one must match."""
+    """The autotuner may pick any compiled variant: each one must match,
+    in the standalone apply (row-major output) and inside a solve (Z stored
+    blocked by the columns one inverse-transform workgroup writes)."""
     inst = localvol(nx, nt) if nx >= 255 else W.config1(nx=nx, nt=nt)
     v = W.random_vector(inst.n, 11)
     ref = O.pc_apply(*oracle_args(inst), inst.alpha, v)
+    u = O.sequential_cn(*oracle_args(inst), inst.u0, inst.f)
     ran = 0
-    for bcols, thr in VARIANTS:
-        monkeypatch.setenv("CN_PC_TILE", f"{bcols},{thr}")
+    for bcols, thr, split in VARIANTS:
+        monkeypatch.setenv("CN_PC_TILE", f"{bcols},{thr},{split}")
         try:
             s = solver(inst, pc_prec=prec)
         except B.CnError as e:
             assert e.status == B.CN_EINVAL and "not a compiled variant" in str(e)
             continue
-        banner(f"pc_apply variant {prec} B={bcols} T={thr} nx={nx} nt={nt}")
-        assert s.query()["tile_cols"] == bcols and s.query()["threads"] == thr
+        banner(f"pc_apply variant {prec} B={bcols} T={thr} S={split} nx={nx} nt={nt}")
+        q = s.query()
+        assert (q["tile_cols"], q["threads"], q["inverse_split"]) == (bcols, thr, split)
         z = torch.empty(inst.n, dtype=torch.float64, device="cuda")
         s.pc_apply(T(v), z)
         err = rel_inf(z.cpu().numpy(), ref)
-        assert err <= pc_tol(inst.alpha, prec, nt), (bcols, thr, err)
+        assert err <= pc_tol(inst.alpha, prec, nt), (bcols, thr, split, err)
+        b = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+        s.rhs(T(inst.u0), T(inst.f.reshape(-1)), b)
+        x = torch.empty_like(b)
+        r = s.solve(b, x, m=20, rtol=1e-10)
+        assert r.status == B.CN_OK and r.relres_true <= 1e-10
+        assert rel_inf(x.cpu().numpy(), u) <= 1e-8, (bcols, thr, split)
         s.close()
         ran += 1
     assert ran >= 1
