@@ -433,6 +433,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the constant-volatility, batch, warm-start and production forms")
+    ap.add_argument("--forms", default="",
+                    help="comma-separated subset of the forms to run (constant_vol, batch_uneven, "
+                         "warm_start, production); default all")
     ap.add_argument("--ws-train", type=int, default=20000,
                     help="training instances of the warm-start network")
     ap.add_argument("--ws-heldout", type=int, default=1024,
@@ -515,28 +518,35 @@ def main():
     checks = {}
     if not args.no_forms:
         forms = {}
-        log("[bench] form: constant volatility 127x64")
-        forms["constant_vol"], checks["constant_vol"] = form_constant_vol(B, W, torch, reps=20)
-        log("[bench] form: uneven batch of 512 instances")
-        forms["batch_uneven"], checks["batch_uneven"] = form_batch_uneven(B, W, torch, reps=5)
-        log(f"[bench] batch: {forms['batch_uneven']['ms_per_solve']:.2f} ms, "
-            f"{forms['batch_uneven']['unknowns_per_s']:.3e} unknowns/s")
-        log(f"[bench] form: warm start ({args.ws_train} training solves, "
-            f"{args.ws_heldout} held-out)")
-        forms["warm_start"], checks["warm_start"] = form_warm_start(
-            B, W, torch, args.ws_train, args.ws_heldout, args.ws_epochs, reps=3)
-        ws = forms["warm_start"]
-        log(f"[bench] warm start: plain {ws['plain_fp64']['unknowns_per_s']:.3e}, batched "
-            f"{ws['batched_fp32']['unknowns_per_s']:.3e}, batched+warm "
-            f"{ws['batched_fp32_warm']['unknowns_per_s']:.3e} unknowns/s; iterations "
-            f"{ws['plain_fp64']['mean_iters']:.2f} / {ws['batched_fp32']['mean_iters']:.2f} / "
-            f"{ws['batched_fp32_warm']['mean_iters']:.2f}")
-        out["batched_fp32_warm_vs_plain"] = ws["speedup_vs_plain"]["batched_fp32_warm"]
-        log("[bench] form: production shape 65535x4096")
-        forms["production"], checks["production"] = form_production(B, W, torch, reps=3)
-        pr = forms["production"]
-        log(f"[bench] production: {pr['ms_per_solve']:.2f} ms, {pr['unknowns_per_s']:.3e} unknowns/s, "
-            f"{pr['iters']} iters, preconditioner apply {pr['pc_apply']['GBps']:.0f} GB/s")
+        want = set(args.forms.split(",")) if args.forms else None
+        run = lambda name: want is None or name in want
+        if run("constant_vol"):
+            log("[bench] form: constant volatility 127x64")
+            forms["constant_vol"], checks["constant_vol"] = form_constant_vol(B, W, torch, reps=20)
+        if run("batch_uneven"):
+            log("[bench] form: uneven batch of 512 instances")
+            forms["batch_uneven"], checks["batch_uneven"] = form_batch_uneven(B, W, torch, reps=5)
+            log(f"[bench] batch: {forms['batch_uneven']['ms_per_solve']:.2f} ms, "
+                f"{forms['batch_uneven']['unknowns_per_s']:.3e} unknowns/s")
+        if run("warm_start"):
+            log(f"[bench] form: warm start ({args.ws_train} training solves, "
+                f"{args.ws_heldout} held-out)")
+            forms["warm_start"], checks["warm_start"] = form_warm_start(
+                B, W, torch, args.ws_train, args.ws_heldout, args.ws_epochs, reps=3)
+            ws = forms["warm_start"]
+            log(f"[bench] warm start: plain {ws['plain_fp64']['unknowns_per_s']:.3e}, batched "
+                f"{ws['batched_fp32']['unknowns_per_s']:.3e}, batched+warm "
+                f"{ws['batched_fp32_warm']['unknowns_per_s']:.3e} unknowns/s; iterations "
+                f"{ws['plain_fp64']['mean_iters']:.2f} / {ws['batched_fp32']['mean_iters']:.2f} / "
+                f"{ws['batched_fp32_warm']['mean_iters']:.2f}")
+            out["batched_fp32_warm_vs_plain"] = ws["speedup_vs_plain"]["batched_fp32_warm"]
+        if run("production"):
+            log("[bench] form: production shape 65535x4096")
+            forms["production"], checks["production"] = form_production(B, W, torch, reps=3)
+            pr = forms["production"]
+            log(f"[bench] production: {pr['ms_per_solve']:.2f} ms, {pr['unknowns_per_s']:.3e} "
+                f"unknowns/s, {pr['iters']} iters, preconditioner apply "
+                f"{pr['pc_apply']['GBps']:.0f} GB/s")
         out["forms"] = forms
     if args.calibrate_copy:
         log("[bench] calibration: 5 device copies of 256 MiB")

@@ -37,6 +37,14 @@ class CnProblem(ctypes.Structure):
     ]
 
 
+class Cn2dProblem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nt", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("T", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("stencil", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+    ]
+
+
 class CnGmresOpts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("flags", ctypes.c_int32),
@@ -108,6 +116,12 @@ def load():
         "cn_ws_predict": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "cn_ws_predict_batch": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "cn_ws_last_error": (ctypes.c_char_p, []),
+        "cn2d_create": (ctypes.c_int, [ctypes.POINTER(Cn2dProblem), ctypes.POINTER(vp)]),
+        "cn2d_destroy": (ctypes.c_int, [vp]),
+        "cn2d_matvec": (ctypes.c_int, [vp, vp, vp]),
+        "cn2d_rhs": (ctypes.c_int, [vp, vp, vp, vp]),
+        "cn2d_pc_apply": (ctypes.c_int, [vp, vp, vp]),
+        "cn2d_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -120,7 +134,8 @@ def load():
 class CnError(RuntimeError):
     def __init__(self, status: int, where: str):
         lib = load()
-        last = lib.cn_ws_last_error if where.startswith(("cn_mlp", "cn_ws")) else lib.cn_last_error
+        last = (lib.cn_ws_last_error if where.startswith(("cn_mlp", "cn_ws"))
+                else lib.cn2d_last_error if where.startswith("cn2d") else lib.cn_last_error)
         msg = last().decode()
         super().__init__(f"{where}: {lib.cn_status_string(status).decode()} ({status}): {msg}")
         self.status = status
@@ -447,3 +462,49 @@ def ws_interpolate(coarse, count: int, nx: int, nt: int, u0, gl, gr, scale, x0, 
     _check(lib.cn_ws_interpolate(_f32(coarse), count, nx, nt, _ptr(u0), _ptr(gl), _ptr(gr),
                                  _ptr(scale), _ptr(x0), s), "cn_ws_interpolate")
     return x0
+
+
+class Solver2D:
+    """All-at-once CN system of a 2D nine-point stencil operator and its
+    alpha-circulant preconditioner (wraps a cn2d handle, cn_aao2d.h).
+    stencil: float64 CUDA tensor of 9 * nx * ny coefficients (entry q of grid
+    point i = iy nx + ix multiplies the unknown at (iy + q//3 - 1,
+    ix + q%3 - 1))."""
+
+    def __init__(self, stencil, nx: int, ny: int, nt: int, T: float, alpha: float, stream=None):
+        lib = load()
+        self._lib = lib
+        if stream is None:
+            stream = torch.cuda.current_stream(stencil.device)
+        self._keep = stencil
+        prob = Cn2dProblem(nx=int(nx), ny=int(ny), nt=int(nt), flags=0, T=float(T),
+                           alpha=float(alpha), stencil=_ptr(stencil),
+                           stream=ctypes.c_void_p(stream.cuda_stream))
+        h = ctypes.c_void_p()
+        _check(lib.cn2d_create(ctypes.byref(prob), ctypes.byref(h)), "cn2d_create")
+        self._h = h
+        self.nx, self.ny, self.nt = int(nx), int(ny), int(nt)
+        self.n = self.nx * self.ny * self.nt
+
+    def matvec(self, x, y):
+        _check(self._lib.cn2d_matvec(self._h, _ptr(x), _ptr(y)), "cn2d_matvec")
+        return y
+
+    def rhs(self, u0, f, b):
+        _check(self._lib.cn2d_rhs(self._h, _ptr(u0), _ptr(f), _ptr(b)), "cn2d_rhs")
+        return b
+
+    def pc_apply(self, v, z):
+        _check(self._lib.cn2d_pc_apply(self._h, _ptr(v), _ptr(z)), "cn2d_pc_apply")
+        return z
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cn2d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

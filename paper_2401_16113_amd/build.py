@@ -14,7 +14,7 @@ OUT = os.path.join(PKG, "libcn_aao.so")
 OBJ = os.path.join(ROOT, "_build")
 
 SOURCES = ["cn_api.hip", "cn_krylov.hip", "cn_pc.hip", "cn_pc_f64.hip", "cn_pc_f32.hip",
-           "cn_mlp.hip"]
+           "cn_mlp.hip", "cn_2d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

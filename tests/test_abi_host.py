@@ -114,3 +114,21 @@ def test_gmres_info_layout():
     # four 32-bit fields then rtol and err_tol
     assert ctypes.sizeof(B.CnGmresOpts) == 32
     assert B.CnGmresOpts.rtol.offset == 16 and B.CnGmresOpts.err_tol.offset == 24
+
+
+def test_cn2d_create_rejects_bad_arguments(lib):
+    """Validation of cn2d_create happens before any device call."""
+    vp = ctypes.c_void_p
+    h = vp()
+    good = dict(nx=8, ny=8, nt=8, flags=0, T=0.5, alpha=0.01, stencil=4096, stream=None)
+    assert lib.cn2d_create(None, ctypes.byref(h)) == B.CN_EINVAL
+    for bad in (dict(nx=0), dict(nx=128), dict(ny=0), dict(nx=100, ny=100), dict(nt=12),
+                dict(nt=2048), dict(T=0.0), dict(alpha=1.0), dict(alpha=0.0), dict(flags=1),
+                dict(stencil=None)):
+        args = dict(good)
+        args.update(bad)
+        prob = B.Cn2dProblem(**args)
+        assert lib.cn2d_create(ctypes.byref(prob), ctypes.byref(h)) == B.CN_EINVAL
+        assert h.value is None
+    assert lib.cn2d_destroy(None) == B.CN_EINVAL
+    assert lib.cn2d_pc_apply(None, None, None) == B.CN_EINVAL
