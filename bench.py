@@ -55,7 +55,11 @@ KERNEL_SOURCES = ["paper_2401_16113_amd/csrc/cn_device.hpp",
                   "paper_2401_16113_amd/csrc/cn_pc_reduced.hpp",
                   "paper_2401_16113_amd/csrc/cn_pc.hip",
                   "paper_2401_16113_amd/csrc/cn_krylov.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_localvol_4095x1024_fp32pc.txt")
+# hardware-counter traffic of the headline's float64 apply and of the
+# production form's float32 apply (variant 8 x 512, two inverse workgroups)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_localvol_4095x1024_fp64pc.txt")
+TRAFFIC_FILE_PROD = os.path.join(ROOT, "profiles", "traffic_localvol_65535x4096_fp32pc.txt")
+TRAFFIC_PROD_VARIANT = {"tile_cols": 8, "threads": 512, "inverse_split": 2}
 
 
 def kernel_source_hash():
@@ -66,13 +70,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel):
+def stored_traffic(kernel, path=None):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE scaled by a copy of known size), or None when the
     summary is missing or the kernel sources changed since it was taken."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path or TRAFFIC_FILE) as fh:
             for line in fh:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
@@ -100,8 +104,8 @@ def apply_roofline(us, n, prec):
             "GBps": round(ach, 1), "frac_of_peak": round(ach / HBM_PEAK_GBS, 4)}
 
 
-def stored_traffic_sum(kernels):
-    vals = [stored_traffic(k) for k in kernels]
+def stored_traffic_sum(kernels, path=None):
+    vals = [stored_traffic(k, path) for k in kernels]
     return None if any(v is None for v in vals) else float(sum(vals))
 
 
@@ -343,6 +347,9 @@ def form_production(B, W, torch, reps):
            "kernels_step1": {k: {"us": v["ms"] * 1e3, "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
                              for k, v in prof.items()},
            "pc_apply": apply_roofline(pc_us, inst.n, "fp32")}
+    q = out["pc_variant"]
+    same = all(q.get(k) == v for k, v in TRAFFIC_PROD_VARIANT.items())
+    out["pc_apply"]["traffic"] = stored_traffic_sum(PC_KERNELS, TRAFFIC_FILE_PROD) if same else None
     x_host = x.cpu().numpy()
     s.close()
     return out, (inst, f_col, x_host)
