@@ -136,6 +136,14 @@ typedef struct {
  * (captured on first use per iteration index, restart length and rtol, and
  * kept with the batch); this flag launches the same kernels one by one. */
 #define CN_SOLVE_NO_GRAPHS 1
+/* By default cn_batch_solve captures the first K inner iterations of a cycle
+ * as one graph, K = the first cycle's iteration count of the batch's last
+ * solve (2 <= K <= m), and waits once for the summary of iteration K-1;
+ * iterations queued after convergence return at entry, and a cycle that
+ * needs more continues one graph per iteration.  This flag keeps one graph
+ * per iteration throughout.  Ignored with CN_SOLVE_NO_GRAPHS and by
+ * cn_gmres_solve. */
+#define CN_SOLVE_ITERATION_GRAPHS 2
 
 typedef struct {
     int32_t iters;          /* inner iterations (= preconditioned matvecs)    */

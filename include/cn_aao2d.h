@@ -55,7 +55,8 @@ extern "C" {
 typedef struct {
     int32_t nx, ny;          /* grid: N_x in [1, 127], N_y >= 1, N_x N_y <= 8192 */
     int32_t nt;              /* time steps: power of two in [1, 1024]         */
-    int32_t flags;           /* 0                                             */
+    int32_t m_max;           /* largest GMRES restart length, 0..64 (0: no     */
+                             /* solver workspace)                             */
     double T;                /* final time, > 0 (tau = T / N_t)               */
     double alpha;            /* 0 < alpha < 1                                 */
     const double *stencil;   /* device, 9 N_x N_y coefficients of A           */
@@ -80,6 +81,18 @@ cn_status cn2d_rhs(cn2d *h, const double *u0, const double *f, double *b);
 /* z = P_alpha^{-1} v by the three steps of eq. (3.2) in complex128; v == z
  * allowed. */
 cn_status cn2d_pc_apply(cn2d *h, const double *v, double *z);
+
+/* GMRES for M u = b (right-preconditioned flexible GMRES(m) with P_alpha,
+ * Sec. 5's solver, as cn_gmres_solve): classical Gram-Schmidt applied twice
+ * in two passes of dots and updates, the Hessenberg column, Givens rotations
+ * and the triangular solve on the device; the host waits once per inner
+ * iteration for the residual estimate.  opts->m <= m_max; use_x0 0 (x is
+ * zeroed) or 1; flags and err_tol must be 0.  x: initial guess / solution.
+ * info (may be NULL): iterations, restarts, products, relres_true from the
+ * recomputed residual.  CN_NOT_CONVERGED when max_iters is spent.
+ * Workspace (at create, m_max > 0): (2 m_max + 2) N_t N_x N_y doubles. */
+cn_status cn2d_gmres_solve(cn2d *h, const double *b, double *x, const cn_gmres_opts *opts,
+                           cn_gmres_info *info);
 
 /* Thread-local message of the last failed cn2d_* call on this thread. */
 const char *cn2d_last_error(void);

@@ -24,6 +24,7 @@ CN_ESINGULAR = -4
 
 CN_PC_FP64 = 0
 CN_SOLVE_NO_GRAPHS = 1
+CN_SOLVE_ITERATION_GRAPHS = 2
 CN_PC_FP32 = 1
 CN_FLAG_ALLOW_ALPHA_ONE = 1
 
@@ -40,7 +41,7 @@ class CnProblem(ctypes.Structure):
 class Cn2dProblem(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nt", ctypes.c_int32),
-        ("flags", ctypes.c_int32), ("T", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("m_max", ctypes.c_int32), ("T", ctypes.c_double), ("alpha", ctypes.c_double),
         ("stencil", ctypes.c_void_p), ("stream", ctypes.c_void_p),
     ]
 
@@ -121,6 +122,8 @@ def load():
         "cn2d_matvec": (ctypes.c_int, [vp, vp, vp]),
         "cn2d_rhs": (ctypes.c_int, [vp, vp, vp, vp]),
         "cn2d_pc_apply": (ctypes.c_int, [vp, vp, vp]),
+        "cn2d_gmres_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(CnGmresOpts),
+                                            ctypes.POINTER(CnGmresInfo)]),
         "cn2d_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -332,13 +335,16 @@ class Batch:
         return out
 
     def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
-              use_x0: int = 0, graphs: bool = True, err_tol: float = 0.0):
+              use_x0: int = 0, graphs: bool = True, err_tol: float = 0.0,
+              cycle_graphs: bool = True):
         """use_x0: 0 zero start, 1 x holds the guess, 2 guess with fallback
         to zero; graphs: launch each inner iteration as a captured graph;
-        err_tol > 0: error-controlled stopping per instance."""
+        cycle_graphs: the first iterations of a cycle as one graph (as many
+        as the last solve's first cycle took); err_tol > 0: error-controlled
+        stopping per instance."""
+        flags = (0 if graphs else CN_SOLVE_NO_GRAPHS) | (0 if cycle_graphs else CN_SOLVE_ITERATION_GRAPHS)
         opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=int(use_x0),
-                           flags=0 if graphs else CN_SOLVE_NO_GRAPHS, rtol=float(rtol),
-                           err_tol=float(err_tol))
+                           flags=flags, rtol=float(rtol), err_tol=float(err_tol))
         infos = (CnGmresInfo * self.count)()
         total = CnGmresInfo()
         st = _check(self._lib.cn_batch_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(opts), infos,
@@ -471,13 +477,14 @@ class Solver2D:
     point i = iy nx + ix multiplies the unknown at (iy + q//3 - 1,
     ix + q%3 - 1))."""
 
-    def __init__(self, stencil, nx: int, ny: int, nt: int, T: float, alpha: float, stream=None):
+    def __init__(self, stencil, nx: int, ny: int, nt: int, T: float, alpha: float,
+                 m_max: int = 0, stream=None):
         lib = load()
         self._lib = lib
         if stream is None:
             stream = torch.cuda.current_stream(stencil.device)
         self._keep = stencil
-        prob = Cn2dProblem(nx=int(nx), ny=int(ny), nt=int(nt), flags=0, T=float(T),
+        prob = Cn2dProblem(nx=int(nx), ny=int(ny), nt=int(nt), m_max=int(m_max), T=float(T),
                            alpha=float(alpha), stencil=_ptr(stencil),
                            stream=ctypes.c_void_p(stream.cuda_stream))
         h = ctypes.c_void_p()
@@ -497,6 +504,18 @@ class Solver2D:
     def pc_apply(self, v, z):
         _check(self._lib.cn2d_pc_apply(self._h, _ptr(v), _ptr(z)), "cn2d_pc_apply")
         return z
+
+    def solve(self, b, x, m: int = 20, rtol: float = 1e-8, max_iters: int = 1000,
+              use_x0: bool = False) -> SolveResult:
+        """Flexible GMRES(m) with P_alpha (cn2d_gmres_solve)."""
+        opts = CnGmresOpts(m=int(m), max_iters=int(max_iters), use_x0=int(use_x0), flags=0,
+                           rtol=float(rtol), err_tol=0.0)
+        info = CnGmresInfo()
+        st = _check(self._lib.cn2d_gmres_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(opts),
+                                               ctypes.byref(info)), "cn2d_gmres_solve",
+                    (CN_OK, CN_NOT_CONVERGED))
+        return SolveResult(st, info.iters, info.restarts, info.matvecs, info.pc_applies,
+                           info.relres_true, info.relres_est, info.seconds)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -322,6 +323,129 @@ __global__ __launch_bounds__(BANDT) void k2d_band(const Cx<double>* __restrict__
   for (int i = t; i < npts; i += BANDT) s[i] = y[i] * sc;
 }
 
+// ---------------------------------------------------------------------------
+// GMRES for the 2D system: right-preconditioned flexible GMRES(m) with
+// classical Gram-Schmidt applied twice (two passes of dots and updates), the
+// Hessenberg column, Givens rotations and y on the device (one thread); the
+// host waits once per inner iteration for the residual estimate.
+// ---------------------------------------------------------------------------
+constexpr int KB = 256;     // threads per block of the streaming kernels
+constexpr int NBLK = 512;   // blocks of a dot pass (partial sums per dot)
+
+struct GmState {
+  double H[(MMAX + 1) * MMAX];  // column j at H[j (MMAX+1)]
+  double cs[MMAX], sn[MMAX];
+  double g[MMAX + 1];
+  double y[MMAX];
+  double h[NVMAX], h2[NVMAX];   // the two Gram-Schmidt passes
+  double nrm2, bsq;             // ||w||^2 after both passes, ||b||^2
+  double bnorm, scale;          // ||b||, 1/||v|| of the vector being normalised
+  double unit;                  // 1.0 (the coefficient of r = b - 1 * (M x))
+};
+
+struct GmSummary {
+  double relres;  // ||r|| / ||b|| at a cycle start, or the estimate after an iteration
+  double hnext;   // h_{j+1,j}
+};
+
+// partials[q NBLK + blk] = <V_q, w> over the block's slice, q < gridDim.y
+__global__ __launch_bounds__(KB) void k2d_dots(const double* __restrict__ V, long long stride,
+                                               const double* __restrict__ w, long long n,
+                                               double* __restrict__ part) {
+  __shared__ double red[KB / 64];
+  const int q = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
+  const double* v = V + (size_t)q * stride;
+  double acc = 0.0;
+  for (long long i = (long long)blk * KB + t; i < n; i += (long long)NBLK * KB) acc += v[i] * w[i];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((t & 63) == 0) red[t >> 6] = acc;
+  __syncthreads();
+  if (t == 0) {
+    double s = 0.0;
+    for (int u = 0; u < KB / 64; ++u) s += red[u];
+    part[(size_t)q * NBLK + blk] = s;
+  }
+}
+
+// out[q] = sum of the NBLK partials of dot q, in a fixed order
+__global__ __launch_bounds__(64) void k2d_sum(const double* __restrict__ part, int nv,
+                                              double* __restrict__ out) {
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  if (q >= nv) return;
+  double s = 0.0;
+  for (int b = 0; b < NBLK; ++b) s += part[(size_t)q * NBLK + b];
+  out[q] = s;
+}
+
+// out = base + sign * sum_q c[q] V_q (c on the device; base may be out)
+__global__ __launch_bounds__(KB) void k2d_combine(double* __restrict__ out, const double* base,
+                                                  const double* __restrict__ V, long long stride,
+                                                  int nv, const double* __restrict__ c,
+                                                  double sign, long long n) {
+  const long long i = (long long)blockIdx.x * KB + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < nv; ++q) s += c[q] * V[(size_t)q * stride + i];
+  out[i] = (base != nullptr ? base[i] : 0.0) + sign * s;
+}
+
+// v = w * (*scale)
+__global__ __launch_bounds__(KB) void k2d_scale(double* __restrict__ v, const double* __restrict__ w,
+                                                const double* __restrict__ scale, long long n) {
+  const long long i = (long long)blockIdx.x * KB + threadIdx.x;
+  if (i < n) v[i] = w[i] * *scale;
+}
+
+// cycle start: beta = sqrt(nrm2), g = beta e_1, scale = 1/beta, relres
+__global__ void k2d_gm_start(GmState* st, GmSummary* sum) {
+  if (threadIdx.x != 0) return;
+  const double beta = sqrt(st->nrm2);
+  st->bnorm = sqrt(st->bsq);
+  for (int q = 0; q <= MMAX; ++q) st->g[q] = 0.0;
+  st->g[0] = beta;
+  st->scale = beta > 0.0 ? 1.0 / beta : 0.0;
+  sum->relres = st->bnorm > 0.0 ? beta / st->bnorm : 0.0;
+  sum->hnext = beta;
+}
+
+// column j of the Hessenberg matrix (h + h2, ||w||), the earlier rotations
+// applied to it, the new rotation, g and the residual estimate
+__global__ void k2d_gm_column(GmState* st, int j, GmSummary* sum) {
+  if (threadIdx.x != 0) return;
+  double* col = st->H + (size_t)j * (MMAX + 1);
+  for (int q = 0; q <= j; ++q) col[q] = st->h[q] + st->h2[q];
+  const double hn = sqrt(st->nrm2);
+  col[j + 1] = hn;
+  for (int q = 0; q < j; ++q) {
+    const double a = col[q], b = col[q + 1];
+    col[q] = st->cs[q] * a + st->sn[q] * b;
+    col[q + 1] = -st->sn[q] * a + st->cs[q] * b;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double r = hypot(a, b);
+  const double c = r > 0.0 ? a / r : 1.0, sn = r > 0.0 ? b / r : 0.0;
+  st->cs[j] = c;
+  st->sn[j] = sn;
+  col[j] = r;
+  col[j + 1] = 0.0;
+  st->g[j + 1] = -sn * st->g[j];
+  st->g[j] = c * st->g[j];
+  st->scale = hn > 0.0 ? 1.0 / hn : 0.0;
+  sum->relres = st->bnorm > 0.0 ? fabs(st->g[j + 1]) / st->bnorm : 0.0;
+  sum->hnext = hn;
+}
+
+// y = R^{-1} g over the first k columns
+__global__ void k2d_gm_y(GmState* st, int k) {
+  if (threadIdx.x != 0) return;
+  for (int q = k - 1; q >= 0; --q) {
+    double s = st->g[q];
+    for (int r = q + 1; r < k; ++r) s -= st->H[(size_t)r * (MMAX + 1) + q] * st->y[r];
+    const double d = st->H[(size_t)q * (MMAX + 1) + q];
+    st->y[q] = d != 0.0 ? s / d : 0.0;
+  }
+}
+
 }  // namespace cn_twod
 
 using namespace cn_twod;
@@ -335,6 +459,13 @@ struct cn2d {
   double *st = nullptr, *wfw = nullptr, *winv = nullptr;
   Cx<double> *tw = nullptr, *tw2 = nullptr, *mu = nullptr, *il2 = nullptr;
   Cx<double> *Lc = nullptr, *Uc = nullptr, *dinv = nullptr, *S = nullptr;
+  // GMRES workspace (m_max > 0): basis V (m_max + 1 vectors), Z (m_max), w,
+  // dot partials, the device state and the host-mapped summary
+  int m_max = 0;
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *part = nullptr;
+  GmState* gs = nullptr;
+  GmSummary* hsum = nullptr;
+  GmSummary* hsum_dev = nullptr;
   std::vector<void*> allocs;
 };
 
@@ -347,6 +478,7 @@ static void release2d(cn2d* h) {
   if (h == nullptr) return;
   (void)hipStreamSynchronize(h->stream);
   for (void* q : h->allocs) (void)hipFree(q);
+  if (h->hsum != nullptr) (void)hipHostFree(h->hsum);
   delete h;
 }
 
@@ -417,7 +549,7 @@ cn_status cn2d_create(const cn2d_problem* p, cn2d** out) {
     return fail2d(CN_EINVAL, "nt must be a power of two in [1, 1024]");
   if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail2d(CN_EINVAL, "T must be finite and > 0");
   if (!(p->alpha > 0.0 && p->alpha < 1.0)) return fail2d(CN_EINVAL, "alpha must satisfy 0 < alpha < 1");
-  if (p->flags != 0) return fail2d(CN_EINVAL, "flags must be 0");
+  if (p->m_max < 0 || p->m_max > MMAX) return fail2d(CN_EINVAL, "m_max must be in [0, 64]");
   cn2d* h = new cn2d();
   h->nx = p->nx;
   h->ny = p->ny;
@@ -430,13 +562,16 @@ cn_status cn2d_create(const cn2d_problem* p, cn2d** out) {
   h->tau = p->T / p->nt;
   h->alpha = p->alpha;
   h->stream = (hipStream_t)p->stream;
+  h->m_max = p->m_max;
   const int nt = h->nt, F = h->F, npts = h->npts, pb = h->p;
+  const size_t nvec = (size_t)nt * npts;
   const size_t band = (size_t)F * npts * pb * sizeof(Cx<double>);
   const size_t gband = (size_t)F * npts * (2 * pb + 1) * sizeof(Cx<double>);
   {
     size_t freeb = 0, totalb = 0;
     TRY2(hipMemGetInfo(&freeb, &totalb));
-    const size_t need = 2 * band + gband + 2 * (size_t)F * npts * sizeof(Cx<double>);
+    const size_t need = 2 * band + gband + 2 * (size_t)F * npts * sizeof(Cx<double>) +
+                        (size_t)(2 * h->m_max + 2) * nvec * sizeof(double);
     if (need > freeb) {
       release2d(h);
       return fail2d(CN_ENOMEM, "band factors need " + std::to_string(need) + " bytes");
@@ -486,6 +621,20 @@ cn_status cn2d_create(const cn2d_problem* p, cn2d** out) {
   TRY2(alloc2d(h, &h->Uc, band));
   TRY2(alloc2d(h, &h->dinv, (size_t)F * npts * sizeof(Cx<double>)));
   TRY2(alloc2d(h, &h->S, (size_t)F * npts * sizeof(Cx<double>)));
+  if (h->m_max > 0) {
+    TRY2(alloc2d(h, &h->V, (size_t)(h->m_max + 1) * nvec * sizeof(double)));
+    TRY2(alloc2d(h, &h->Z, (size_t)h->m_max * nvec * sizeof(double)));
+    TRY2(alloc2d(h, &h->w, nvec * sizeof(double)));
+    TRY2(alloc2d(h, &h->part, (size_t)NVMAX * NBLK * sizeof(double)));
+    TRY2(alloc2d(h, &h->gs, sizeof(GmState)));
+    {
+      GmState g0{};
+      g0.unit = 1.0;
+      TRY2(hipMemcpy(h->gs, &g0, sizeof(GmState), hipMemcpyHostToDevice));
+    }
+    TRY2(hipHostMalloc((void**)&h->hsum, sizeof(GmSummary), hipHostMallocCoherent | hipHostMallocMapped));
+    TRY2(hipHostGetDevicePointer((void**)&h->hsum_dev, h->hsum, 0));
+  }
   // the band of every frequency during the factorisation (freed after)
   Cx<double>* G = nullptr;
   int* err = nullptr;
@@ -570,3 +719,124 @@ cn_status cn2d_pc_apply(cn2d* h, const double* v, double* z) {
 }
 
 }  // extern "C"
+
+// dots of V_0..V_{nv-1} with w into out[0..nv) (device)
+static hipError_t dots2d(cn2d* h, const double* V, int nv, const double* w, double* out) {
+  const long long n = (long long)h->nt * h->npts;
+  hipLaunchKernelGGL(k2d_dots, dim3(NBLK, nv), dim3(KB), 0, h->stream, V, n, w, n, h->part);
+  hipLaunchKernelGGL(k2d_sum, dim3((nv + 63) / 64), dim3(64), 0, h->stream, h->part, nv, out);
+  return hipGetLastError();
+}
+
+static hipError_t combine2d(cn2d* h, double* out, const double* base, const double* V, int nv,
+                            const double* c, double sign) {
+  const long long n = (long long)h->nt * h->npts;
+  hipLaunchKernelGGL(k2d_combine, dim3((unsigned)((n + KB - 1) / KB)), dim3(KB), 0, h->stream, out,
+                     base, V, n, nv, c, sign, n);
+  return hipGetLastError();
+}
+
+// r = b - M x into V_0 (x = 0: r = b), ||r||^2 and the cycle start
+static hipError_t restart2d(cn2d* h, const double* b, const double* x, bool x_zero) {
+  const long long n = (long long)h->nt * h->npts;
+  hipError_t e = hipSuccess;
+  if (x_zero) {
+    e = hipMemcpyAsync(h->V, b, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+  } else {
+    hipLaunchKernelGGL(k2d_matvec<0>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, h->st,
+                       h->nx, h->ny, h->nt, h->tau, x, nullptr, h->w);
+    e = hipGetLastError();
+    // V_0 = b - w
+    if (e == hipSuccess) e = combine2d(h, h->V, b, h->w, 1, &h->gs->unit, -1.0);
+  }
+  if (e == hipSuccess) e = dots2d(h, h->V, 1, h->V, &h->gs->nrm2);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k2d_gm_start, dim3(1), dim3(1), 0, h->stream, h->gs, h->hsum_dev);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+extern "C" cn_status cn2d_gmres_solve(cn2d* h, const double* b, double* x, const cn_gmres_opts* opts,
+                                      cn_gmres_info* info) {
+  if (h == nullptr || b == nullptr || x == nullptr || opts == nullptr)
+    return fail2d(CN_EINVAL, "NULL argument");
+  if (h->m_max < 1) return fail2d(CN_EINVAL, "the handle has no solver workspace (m_max = 0)");
+  if (opts->m < 1 || opts->m > h->m_max) return fail2d(CN_EINVAL, "opts->m must be in [1, m_max]");
+  if (opts->max_iters < 1) return fail2d(CN_EINVAL, "opts->max_iters must be >= 1");
+  if (opts->use_x0 < 0 || opts->use_x0 > 1) return fail2d(CN_EINVAL, "opts->use_x0 must be 0 or 1");
+  if (opts->flags != 0 || opts->err_tol != 0.0)
+    return fail2d(CN_EINVAL, "flags and err_tol are not supported for 2D operators");
+  if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
+    return fail2d(CN_EINVAL, "opts->rtol must be finite and >= 0");
+  const long long n = (long long)h->nt * h->npts;
+  if (b < x + n && x < b + n) return fail2d(CN_EINVAL, "b and x overlap");
+  const auto wall0 = std::chrono::steady_clock::now();
+  hipStream_t s = h->stream;
+  GmState* gs = h->gs;
+  const double rtol = opts->rtol;
+  cn_gmres_info in{};
+  in.err_est = -1.0;
+#define CK(expr)                                                        \
+  do {                                                                  \
+    const hipError_t e_ = (expr);                                       \
+    if (e_ != hipSuccess) return fail2d(CN_EHIP, hipGetErrorString(e_)); \
+  } while (0)
+  CK(dots2d(h, b, 1, b, &gs->bsq));
+  bool x_zero = opts->use_x0 == 0;
+  if (x_zero) CK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  CK(restart2d(h, b, x, x_zero));
+  in.matvecs = x_zero ? 0 : 1;
+  CK(hipStreamSynchronize(s));
+  double relres = h->hsum->relres;
+  int done = 0;
+  while (!(relres <= rtol) && done < opts->max_iters) {
+    hipLaunchKernelGGL(k2d_scale, dim3((unsigned)((n + KB - 1) / KB)), dim3(KB), 0, s, h->V, h->V,
+                       &gs->scale, n);
+    CK(hipGetLastError());
+    const int m_eff = std::min(opts->m, opts->max_iters - done);
+    int k = 0;
+    for (int j = 0; j < m_eff; ++j) {
+      double* vj = h->V + (size_t)j * n;
+      double* zj = h->Z + (size_t)j * n;
+      const cn_status ps = cn2d_pc_apply(h, vj, zj);
+      if (ps != CN_OK) return ps;
+      hipLaunchKernelGGL(k2d_matvec<0>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->st,
+                         h->nx, h->ny, h->nt, h->tau, zj, nullptr, h->w);
+      CK(hipGetLastError());
+      // two passes of classical Gram-Schmidt against V_0..V_j
+      CK(dots2d(h, h->V, j + 1, h->w, gs->h));
+      CK(combine2d(h, h->w, h->w, h->V, j + 1, gs->h, -1.0));
+      CK(dots2d(h, h->V, j + 1, h->w, gs->h2));
+      CK(combine2d(h, h->w, h->w, h->V, j + 1, gs->h2, -1.0));
+      CK(dots2d(h, h->w, 1, h->w, &gs->nrm2));
+      hipLaunchKernelGGL(k2d_gm_column, dim3(1), dim3(1), 0, s, gs, j, h->hsum_dev);
+      CK(hipGetLastError());
+      hipLaunchKernelGGL(k2d_scale, dim3((unsigned)((n + KB - 1) / KB)), dim3(KB), 0, s,
+                         h->V + (size_t)(j + 1) * n, h->w, &gs->scale, n);
+      CK(hipGetLastError());
+      CK(hipStreamSynchronize(s));
+      k = j + 1;
+      ++in.iters;
+      ++in.pc_applies;
+      ++in.matvecs;
+      in.relres_est = h->hsum->relres;
+      if (in.relres_est <= rtol || h->hsum->hnext == 0.0) break;
+    }
+    done += k;
+    // x += Z y, then the true residual
+    hipLaunchKernelGGL(k2d_gm_y, dim3(1), dim3(1), 0, s, gs, k);
+    CK(hipGetLastError());
+    CK(combine2d(h, x, x, h->Z, k, gs->y, 1.0));
+    CK(restart2d(h, b, x, false));
+    ++in.matvecs;
+    CK(hipStreamSynchronize(s));
+    relres = h->hsum->relres;
+    if (!(relres <= rtol)) ++in.restarts;
+  }
+#undef CK
+  in.relres_true = relres;
+  in.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  if (info != nullptr) *info = in;
+  return relres <= rtol ? CN_OK : CN_NOT_CONVERGED;
+}

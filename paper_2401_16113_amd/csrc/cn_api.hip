@@ -761,8 +761,12 @@ struct SolveCtx {
   StopCtl* ctl_last = nullptr;
   std::vector<double>* rt = nullptr;
   double* rt_for = nullptr;  // the (rtol, err_tol) the targets were made for
-  // batch: captured inner iterations (null: launch kernel by kernel)
+  // batch: captured inner iterations (null: launch kernel by kernel); with
+  // cycle_graphs the first *cycle_k iterations of a cycle as one graph
+  // (*cycle_k: the last solve's first-cycle iteration count)
   struct GraphCache* graphs = nullptr;
+  bool cycle_graphs = false;
+  int* cycle_k = nullptr;
 };
 
 // One captured graph per inner-iteration index j of a batch: the transform
@@ -811,10 +815,15 @@ static cn_status batch_publish(SolveCtx& c, int slot, int* seq) {
 
 // Launch the captured graph of inner iteration j (capturing it on first use):
 // the same launches as enqueue_iteration + batch_publish on slot j & 1.
-static cn_status launch_iteration_graph(SolveCtx& c, int j, int stop_iter, double rtol) {
+// With `cycle` = K > 0, the graph holds inner iterations 0..K-1 of a cycle,
+// each followed by its batch summary (key j = -K): the host then waits once,
+// for the summary of iteration K-1, instead of once per iteration.
+static cn_status launch_iteration_graph(SolveCtx& c, int j, int stop_iter, double rtol,
+                                        int cycle = 0) {
   GraphCache& gc = *c.graphs;
+  const int key = cycle > 0 ? -cycle : j;
   for (const GraphCache::Entry& e : gc.entries)
-    if (e.j == j && e.stop_iter == stop_iter && e.rtol == rtol) {
+    if (e.j == key && e.stop_iter == stop_iter && e.rtol == rtol) {
       HIP_TRY(hipGraphLaunch(e.x, c.s));
       return CN_OK;
     }
@@ -822,8 +831,12 @@ static cn_status launch_iteration_graph(SolveCtx& c, int j, int stop_iter, doubl
   SolveCtx cc = c;
   cc.s = gc.cap;
   HIP_TRY(hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal));
-  hipError_t e = enqueue_iteration(cc, j, stop_iter, rtol, j & 1, 0);
-  if (e == hipSuccess) e = launch_batch_summary(cc.L, cc.dcounter, cc.bh_dev + (j & 1), gc.cap);
+  hipError_t e = hipSuccess;
+  const int j0 = cycle > 0 ? 0 : j, j1 = cycle > 0 ? cycle : j + 1;
+  for (int jj = j0; jj < j1 && e == hipSuccess; ++jj) {
+    e = enqueue_iteration(cc, jj, stop_iter, rtol, jj & 1, 0);
+    if (e == hipSuccess) e = launch_batch_summary(cc.L, cc.dcounter, cc.bh_dev + (jj & 1), gc.cap);
+  }
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(gc.cap, &g);
   if (e == hipSuccess) e = e2;
@@ -833,7 +846,7 @@ static cn_status launch_iteration_graph(SolveCtx& c, int j, int stop_iter, doubl
     if (g != nullptr) (void)hipGraphDestroy(g);
     return fail(CN_EHIP, std::string("iteration graph: ") + hipGetErrorString(e));
   }
-  gc.entries.push_back(GraphCache::Entry{j, stop_iter, rtol, g, x});
+  gc.entries.push_back(GraphCache::Entry{key, stop_iter, rtol, g, x});
   HIP_TRY(hipGraphLaunch(x, c.s));
   return CN_OK;
 }
@@ -872,6 +885,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
                           opts->use_x0 == 2 ? 2 : 1));
   bool x_zero = !opts->use_x0;
   int done_iters = 0;
+  int first_cycle_k = -1;
   int seqs[MMAX];
   double ests[MMAX];
   GSummary it{};
@@ -886,6 +900,22 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
       spec = false;
       seqs[j] = c.batched ? 0 : ++(*c.seqc);
       enq = j + 1;
+      const int K = c.cycle_k != nullptr ? *c.cycle_k : 0;
+      if (j == 0 && c.graphs != nullptr && c.cycle_graphs && K >= 2 && K <= m_eff) {
+        // the first K iterations (as many as the last solve's first cycle
+        // took) as one graph, and one wait for the summary of the last;
+        // iterations queued after convergence return at entry
+        CN_TRY(launch_iteration_graph(c, 0, m_eff, rtol, K));
+        *c.bseq += K;
+        seqs[K - 1] = *c.bseq;
+        enq = K;
+        CN_TRY(wait_slot(c.s, c.bh + ((K - 1) & 1), seqs[K - 1], &it));
+        for (int q = 0; q < K; ++q) ests[q] = it.est;
+        known = K;
+        if (it.done) break;
+        j = K - 1;
+        continue;
+      }
       if (c.graphs != nullptr) {
         CN_TRY(launch_iteration_graph(c, j, m_eff, rtol));
         seqs[j] = ++(*c.bseq);
@@ -989,6 +1019,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
       kmax = std::max(kmax, k);
       if (!(cur[i].relres <= rtol * fac[i])) all_conv = false;
     }
+    if (first_cycle_k < 0) first_cycle_k = kmax;
     done_iters += kmax;
     if (kmax == 0 || all_conv || done_iters >= opts->max_iters) break;
     if (r_unstored) {
@@ -1009,6 +1040,7 @@ static cn_status run_solve(SolveCtx& c, const double* b, double* x, const cn_gmr
     }
   }
   HIP_TRY(hipStreamSynchronize(c.s));
+  if (c.cycle_k != nullptr && first_cycle_k > 0) *c.cycle_k = first_cycle_k;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
   bool ok = true;
   for (int i = 0; i < ninst; ++i) {
@@ -1089,6 +1121,8 @@ static cn_status solve_driver(SolveCtx& c, const double* b, double* x, const cn_
     std::vector<double> err(ninst, 0.0);
     cn_gmres_opts o2 = *opts;
     o2.use_x0 = 1;
+    // continuations neither use nor record the first-cycle iteration count
+    c.cycle_k = nullptr;
     for (int round = 0;; ++round) {
       CN_TRY(estimate_errors(c, b, x, &err));
       bool above = false;
@@ -1201,6 +1235,7 @@ struct cn_batch {
   std::vector<StopCtl> last_ctl;   // last uploaded
   std::vector<double> rt;          // remembered rtol targets (SolveCtx::rt)
   double rt_for[2] = {0.0, 0.0};
+  int cycle_k = 0;                 // first-cycle iterations of the last solve
 };
 
 static void batch_release(cn_batch* b) {
@@ -1299,7 +1334,8 @@ cn_status cn_gmres_solve(cn_aao* h, const double* b, double* x, const cn_gmres_o
   if (opts->m < 1 || opts->m > h->m_max) return fail(CN_EINVAL, "opts->m must be in [1, m_max]");
   if (opts->max_iters < 1) return fail(CN_EINVAL, "opts->max_iters must be >= 1");
   if (opts->use_x0 < 0 || opts->use_x0 > 2) return fail(CN_EINVAL, "opts->use_x0 must be 0, 1 or 2");
-  if (opts->flags & ~CN_SOLVE_NO_GRAPHS) return fail(CN_EINVAL, "unknown bits in opts->flags");
+  if (opts->flags & ~(CN_SOLVE_NO_GRAPHS | CN_SOLVE_ITERATION_GRAPHS))
+    return fail(CN_EINVAL, "unknown bits in opts->flags");
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
   if (!(opts->err_tol >= 0.0) || !std::isfinite(opts->err_tol))
@@ -1533,7 +1569,8 @@ cn_status cn_batch_solve(cn_batch* b, const double* bp, double* xp, const cn_gmr
     return fail(CN_EINVAL, "opts->m must be in [1, smallest m_max of the batch]");
   if (opts->max_iters < 1) return fail(CN_EINVAL, "opts->max_iters must be >= 1");
   if (opts->use_x0 < 0 || opts->use_x0 > 2) return fail(CN_EINVAL, "opts->use_x0 must be 0, 1 or 2");
-  if (opts->flags & ~CN_SOLVE_NO_GRAPHS) return fail(CN_EINVAL, "unknown bits in opts->flags");
+  if (opts->flags & ~(CN_SOLVE_NO_GRAPHS | CN_SOLVE_ITERATION_GRAPHS))
+    return fail(CN_EINVAL, "unknown bits in opts->flags");
   if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol))
     return fail(CN_EINVAL, "opts->rtol must be finite and >= 0");
   if (!(opts->err_tol >= 0.0) || !std::isfinite(opts->err_tol))
@@ -1554,6 +1591,8 @@ cn_status cn_batch_solve(cn_batch* b, const double* bp, double* xp, const cn_gmr
   c.dcounter = b->dcounter;
   c.bseq = &b->bseq;
   if (!(opts->flags & CN_SOLVE_NO_GRAPHS)) c.graphs = &b->graphs;
+  c.cycle_graphs = (opts->flags & CN_SOLVE_ITERATION_GRAPHS) == 0;
+  c.cycle_k = &b->cycle_k;
   for (size_t i = 0; i < b->inst.size(); ++i) {
     c.inst_host.push_back(b->inst[i]->hsum);
     c.off.push_back(b->off[i]);

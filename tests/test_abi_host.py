@@ -120,10 +120,10 @@ def test_cn2d_create_rejects_bad_arguments(lib):
     """Validation of cn2d_create happens before any device call."""
     vp = ctypes.c_void_p
     h = vp()
-    good = dict(nx=8, ny=8, nt=8, flags=0, T=0.5, alpha=0.01, stencil=4096, stream=None)
+    good = dict(nx=8, ny=8, nt=8, m_max=0, T=0.5, alpha=0.01, stencil=4096, stream=None)
     assert lib.cn2d_create(None, ctypes.byref(h)) == B.CN_EINVAL
     for bad in (dict(nx=0), dict(nx=128), dict(ny=0), dict(nx=100, ny=100), dict(nt=12),
-                dict(nt=2048), dict(T=0.0), dict(alpha=1.0), dict(alpha=0.0), dict(flags=1),
+                dict(nt=2048), dict(T=0.0), dict(alpha=1.0), dict(alpha=0.0), dict(m_max=65),
                 dict(stencil=None)):
         args = dict(good)
         args.update(bad)

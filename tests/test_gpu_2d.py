@@ -8,6 +8,7 @@ import pytest
 import torch
 
 from oracle import cn2d_oracle as O2
+from oracle import cn_oracle as O1
 from paper_2401_16113_amd import binding as B
 from paper_2401_16113_amd import workloads as W
 from gpu_helpers import T, banner, rel_inf
@@ -93,3 +94,36 @@ def test_create_rejects_bad_problems():
         with pytest.raises(B.CnError) as ei:
             B.Solver2D(st, **args)
         assert ei.value.status == B.CN_EINVAL
+
+
+@pytest.mark.parametrize("nx,ny,nt,mixed", [(31, 17, 32, 0.0), (63, 63, 64, 0.0), (37, 23, 128, 0.2)])
+def test_gmres_solve_matches_cn_time_stepping(nx, ny, nt, mixed):
+    """Flexible GMRES(20) with P_alpha on the 2D system to relres 1e-10
+    against the oracle's CN time stepping (the exact M^{-1} b), and its
+    iteration count against the oracle's right-preconditioned GMRES."""
+    banner(f"2d gmres {nx}x{ny}x{nt} mixed={mixed}")
+    inst = W.drift_diffusion_2d(nx, ny, nt, mixed=mixed)
+    A = O2.stencil_matrix(inst.st, nx, ny)
+    s = B.Solver2D(T(inst.st.reshape(-1)), nx, ny, nt, inst.T, inst.alpha, m_max=20)
+    b = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+    s.rhs(T(inst.u0), T(inst.f.reshape(-1)), b)
+    x = torch.full_like(b, 3.0)      # ignored: zero start
+    r = s.solve(b, x, m=20, rtol=1e-10)
+    u = O2.sequential_cn(A, inst.T, nt, inst.u0, inst.f)
+    err = rel_inf(x.cpu().numpy(), u)
+    bh = O2.aao_rhs(A, inst.T, nt, inst.u0, inst.f)
+    ref = O1.gmres_right(lambda v: O2.aao_matvec(A, inst.T, nt, v),
+                         lambda v: O2.pc_apply(A, inst.T, nt, inst.alpha, v), bh, m=20, rtol=1e-10)
+    print(f"  iterations {r.iters} (oracle {ref.iters}), relres {r.relres_true:.2e}, "
+          f"error {err:.2e}", flush=True)
+    assert r.status == B.CN_OK and r.relres_true <= 1e-10
+    assert err <= 1e-8
+    assert abs(r.iters - ref.iters) <= 1
+    # restarts (m = 2) and a warm start from the solution
+    x2 = torch.empty_like(b)
+    r2 = s.solve(b, x2, m=2, rtol=1e-10)
+    assert r2.status == B.CN_OK and r2.restarts >= 1
+    assert rel_inf(x2.cpu().numpy(), u) <= 1e-8
+    r3 = s.solve(b, x, m=20, rtol=1e-8, use_x0=True)
+    assert r3.status == B.CN_OK and r3.iters == 0
+    s.close()

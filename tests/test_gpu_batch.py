@@ -150,8 +150,8 @@ def test_batch_rejects_bad_calls():
 
 
 def test_graph_replays_match_kernel_by_kernel_launches():
-    """Captured iteration graphs against the same kernels launched one by
-    one: several solves replaying the graphs, with eager work and
+    """Captured iteration graphs (one per inner iteration) against the same
+    kernels launched one by one: several solves replaying the graphs, with eager work and
     synchronisation between them, each bit-identical to the eager result;
     new keys (restart length, rtol) capture new graphs."""
     banner("batch iteration graphs")
@@ -170,7 +170,7 @@ def test_graph_replays_match_kernel_by_kernel_launches():
             y.copy_(b).mul_(2.0)                  # unrelated torch work
             torch.cuda.synchronize()
             x = torch.full_like(b, 7.0)           # ignored: zero start
-            tot, per = bt.solve(b, x, m=m, rtol=rtol)
+            tot, per = bt.solve(b, x, m=m, rtol=rtol, cycle_graphs=False)
             assert tot.status == B.CN_OK
             assert [r.iters for r in per] == [r.iters for r in per_ref]
             assert [r.restarts for r in per] == [r.restarts for r in per_ref]
@@ -179,4 +179,33 @@ def test_graph_replays_match_kernel_by_kernel_launches():
     x0 = x_ref.clone()
     tot, per = bt.solve(b, x0, m=20, rtol=1e-10, use_x0=2)
     assert tot.status == B.CN_OK and all(r.x0_rejected == 0 for r in per)
+    bt.close()
+
+
+def test_cycle_graphs_match_kernel_by_kernel_launches():
+    """The first iterations of a cycle captured as one graph (as many as the
+    previous solve's first cycle took): replays, with eager work between
+    them, give bit for bit the kernel-by-kernel result, also when a cycle
+    needs more iterations than the graph holds (a tighter rtol after a
+    looser one) and with restarts (m = 2)."""
+    banner("batch cycle graphs")
+    insts = small_uneven(count=8, seed=9)
+    bt = batch(insts, pc_prec="fp32")
+    u0, f = packed(insts, "u0"), packed(insts, "f")
+    b = torch.empty(bt.n, dtype=torch.float64, device="cuda")
+    bt.rhs(u0, f, b)
+    for m, rtol in ((20, 1e-6), (20, 1e-10), (20, 1e-10), (2, 1e-10), (20, 1e-6)):
+        x_ref = torch.empty_like(b)
+        tot_ref, per_ref = bt.solve(b, x_ref, m=m, rtol=rtol, graphs=False)
+        assert tot_ref.status == B.CN_OK
+        for rep in range(3):
+            bt.rhs(u0, f, b)                      # eager kernels between replays
+            y = torch.empty_like(b)
+            y.copy_(b).mul_(2.0)                  # unrelated torch work
+            torch.cuda.synchronize()
+            x = torch.full_like(b, 7.0)
+            tot, per = bt.solve(b, x, m=m, rtol=rtol, cycle_graphs=True)
+            assert tot.status == B.CN_OK
+            assert [r.iters for r in per] == [r.iters for r in per_ref]
+            assert torch.equal(x, x_ref), (m, rtol, rep)
     bt.close()
