@@ -14,7 +14,7 @@ alpha sweep (0.001, 0.01, 0.05, both precisions) are timed the same way.
 `roofline` is the preconditioner apply (K1 + K2 + K3 of one inner
 iteration, HIP-event timing on the solver's stream) at the algorithmic
 48 B (float64) per unknown against the 8 TB/s HBM peak; the longest single
-launch (the Gram-Schmidt update) is reported beside it.  The production
+launch of that iteration is reported beside it.  The production
 forms on their own workloads ("forms"):
   constant_vol -- the 127 x 64 constant-volatility put, float64, GMRES(20)
                   to 1e-12 (latency-bound);
