@@ -26,6 +26,8 @@ forms on their own workloads ("forms"):
                   and from the learned initial guess (network trained here on
                   20000 plain solves; inference and interpolation inside the
                   timed region);
+  drift_diffusion_2d -- a 2D variable-coefficient operator with a mixed
+                  derivative, 127 x 63 grid, 256 steps, float64, GMRES(20);
   production   -- the 65535 x 4096 local-volatility put (2.7e8 unknowns),
                   float32 preconditioner, GMRES(20), with per-kernel rates.
 The cpu_baseline leg times the CPU oracle on the host and reports every
@@ -179,6 +181,42 @@ def form_constant_vol(B, W, torch, reps):
     out = {"nx": inst.nx, "nt": inst.nt, "unknowns": inst.n, "rtol": inst.rtol,
            "ms_per_solve": sec * 1e3, "device_ms_per_solve": r.seconds * 1e3,
            "unknowns_per_s": inst.n / sec, "iters": r.iters, "relres": r.relres_true}
+    x_host = x.cpu().numpy()
+    s.close()
+    return out, (inst, x_host)
+
+
+def form_drift_diffusion_2d(B, W, torch, reps):
+    """A 2D operator (Sec. 5's setting): seeded variable-coefficient
+    drift-diffusion with a mixed derivative on a 127 x 63 grid, 256 steps
+    (2,048,256 unknowns), float64, flexible GMRES(20) to 1e-8.  Reports the
+    set-up (the band factors of the 129 shifted systems), one preconditioner
+    apply and the whole solve."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    inst = W.drift_diffusion_2d(127, 63, 256, T=0.5, alpha=0.01, seed=21, mixed=0.2)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = B.Solver2D(t(inst.st.reshape(-1)), inst.nx, inst.ny, inst.nt, inst.T, inst.alpha,
+                   m_max=20)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    n = inst.nx * inst.ny * inst.nt
+    b = torch.empty(n, dtype=torch.float64, device=dev)
+    s.rhs(t(inst.u0), t(inst.f.reshape(-1)), b)
+    x = torch.empty_like(b)
+    z = torch.empty_like(b)
+    for _ in range(2):
+        s.solve(b, x, m=20, rtol=RTOL)
+        s.pc_apply(b, z)
+    sec_pc, _ = timed(lambda: s.pc_apply(b, z), 10, torch)
+    sec, r = timed(lambda: s.solve(b, x, m=20, rtol=RTOL), reps, torch)
+    if r.status != B.CN_OK:
+        raise RuntimeError(f"2D solve did not converge: {r}")
+    out = {"nx": inst.nx, "ny": inst.ny, "nt": inst.nt, "unknowns": n, "mixed_derivative": 0.2,
+           "create_s": create_s, "pc_apply_ms": sec_pc * 1e3, "ms_per_solve": sec * 1e3,
+           "unknowns_per_s": n / sec, "iters": r.iters, "relres": r.relres_true}
     x_host = x.cpu().numpy()
     s.close()
     return out, (inst, x_host)
@@ -409,6 +447,11 @@ def cpu_baseline(inst, x_gpu, checks):
             for k in ws:
                 ws[k] = max(ws[k], rel_err(smp[k][q * n1:(q + 1) * n1], uq))
         extra["warm_start_sample"] = {"instances": int(len(params)), **ws}
+    if "drift_diffusion_2d" in checks:
+        from oracle import cn2d_oracle as O2
+        di, xd = checks["drift_diffusion_2d"]
+        A2 = O2.stencil_matrix(di.st, di.nx, di.ny)
+        extra["drift_diffusion_2d"] = rel_err(xd, O2.sequential_cn(A2, di.T, di.nt, di.u0, di.f))
     if "production" in checks:
         pi, f_col, xp = checks["production"]
         up_ = O.sequential_cn_banded(pi.a_lo, pi.a_di, pi.a_up, pi.T, pi.nt, pi.u0, f_col=f_col)
@@ -442,7 +485,7 @@ def main():
                     help="skip the constant-volatility, batch, warm-start and production forms")
     ap.add_argument("--forms", default="",
                     help="comma-separated subset of the forms to run (constant_vol, batch_uneven, "
-                         "warm_start, production); default all")
+                         "warm_start, drift_diffusion_2d, production); default all")
     ap.add_argument("--ws-train", type=int, default=20000,
                     help="training instances of the warm-start network")
     ap.add_argument("--ws-heldout", type=int, default=1024,
@@ -547,6 +590,13 @@ def main():
                 f"{ws['plain_fp64']['mean_iters']:.2f} / {ws['batched_fp32']['mean_iters']:.2f} / "
                 f"{ws['batched_fp32_warm']['mean_iters']:.2f}")
             out["batched_fp32_warm_vs_plain"] = ws["speedup_vs_plain"]["batched_fp32_warm"]
+        if run("drift_diffusion_2d"):
+            log("[bench] form: 2D drift-diffusion 127x63x256")
+            forms["drift_diffusion_2d"], checks["drift_diffusion_2d"] = form_drift_diffusion_2d(
+                B, W, torch, reps=5)
+            d2 = forms["drift_diffusion_2d"]
+            log(f"[bench] 2D: {d2['ms_per_solve']:.2f} ms, {d2['unknowns_per_s']:.3e} unknowns/s, "
+                f"{d2['iters']} iters, apply {d2['pc_apply_ms']:.3f} ms, set-up {d2['create_s']:.2f} s")
         if run("production"):
             log("[bench] form: production shape 65535x4096")
             forms["production"], checks["production"] = form_production(B, W, torch, reps=3)
