@@ -87,7 +87,8 @@ cn_status cn2d_pc_apply(cn2d *h, const double *v, double *z);
  * in two passes of dots and updates, the Hessenberg column, Givens rotations
  * and the triangular solve on the device; the host waits once per inner
  * iteration for the residual estimate.  opts->m <= m_max; use_x0 0 (x is
- * zeroed) or 1; flags and err_tol must be 0.  x: initial guess / solution.
+ * zeroed) or 1; flags and err_tol must be 0.  x: initial guess / solution
+ * (b = 0 gives x = 0 at once).
  * info (may be NULL): iterations, restarts, products, relres_true from the
  * recomputed residual.  CN_NOT_CONVERGED when max_iters is spent.
  * Workspace (at create, m_max > 0): (2 m_max + 2) N_t N_x N_y doubles. */

@@ -346,6 +346,7 @@ struct GmState {
 struct GmSummary {
   double relres;  // ||r|| / ||b|| at a cycle start, or the estimate after an iteration
   double hnext;   // h_{j+1,j}
+  double bnorm;   // ||b|| (cycle start)
 };
 
 // partials[q NBLK + blk] = <V_q, w> over the block's slice, q < gridDim.y
@@ -406,6 +407,7 @@ __global__ void k2d_gm_start(GmState* st, GmSummary* sum) {
   st->scale = beta > 0.0 ? 1.0 / beta : 0.0;
   sum->relres = st->bnorm > 0.0 ? beta / st->bnorm : 0.0;
   sum->hnext = beta;
+  sum->bnorm = st->bnorm;
 }
 
 // column j of the Hessenberg matrix (h + h2, ||w||), the earlier rotations
@@ -789,6 +791,12 @@ extern "C" cn_status cn2d_gmres_solve(cn2d* h, const double* b, double* x, const
   in.matvecs = x_zero ? 0 : 1;
   CK(hipStreamSynchronize(s));
   double relres = h->hsum->relres;
+  if (h->hsum->bnorm == 0.0) {
+    // b = 0: the solution is x = 0, whatever the guess
+    if (!x_zero) CK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    CK(hipStreamSynchronize(s));
+    relres = 0.0;
+  }
   int done = 0;
   while (!(relres <= rtol) && done < opts->max_iters) {
     hipLaunchKernelGGL(k2d_scale, dim3((unsigned)((n + KB - 1) / KB)), dim3(KB), 0, s, h->V, h->V,

@@ -126,4 +126,8 @@ def test_gmres_solve_matches_cn_time_stepping(nx, ny, nt, mixed):
     assert rel_inf(x2.cpu().numpy(), u) <= 1e-8
     r3 = s.solve(b, x, m=20, rtol=1e-8, use_x0=True)
     assert r3.status == B.CN_OK and r3.iters == 0
+    # b = 0: x = 0 whatever the guess
+    z0 = torch.zeros_like(b)
+    r4 = s.solve(z0, x, m=20, rtol=1e-8, use_x0=True)
+    assert r4.status == B.CN_OK and r4.iters == 0 and float(x.abs().max()) == 0.0
     s.close()
