@@ -30,7 +30,7 @@ constexpr int kMaxNx = 127;
 constexpr int kMaxPts = 8192;
 constexpr int kMaxLog2N = 10;
 constexpr int BANDT = 64;       // one wavefront per frequency line of the substitution
-constexpr int PF = 8;           // rows of band coefficients requested ahead
+constexpr int PF = 32;          // rows of band coefficients requested ahead (about a memory latency of rows)
 constexpr int FACT = 256;       // threads per frequency of the factorisation
 
 __device__ __forceinline__ Cx<double> czero() { return Cx<double>{0.0, 0.0}; }
