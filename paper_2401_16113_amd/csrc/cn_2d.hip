@@ -30,7 +30,6 @@ constexpr int kMaxNx = 127;
 constexpr int kMaxPts = 8192;
 constexpr int kMaxLog2N = 10;
 constexpr int BANDT = 64;       // one wavefront per frequency line of the substitution
-constexpr int PF = 32;          // rows of band coefficients requested ahead (about a memory latency of rows)
 constexpr int FACT = 256;       // threads per frequency of the factorisation
 
 __device__ __forceinline__ Cx<double> czero() { return Cx<double>{0.0, 0.0}; }
@@ -231,16 +230,35 @@ __global__ __launch_bounds__(FACT) void k2d_factor(const double* __restrict__ st
 }
 
 // Step (b): one wavefront per frequency j, S[j] <- (1/lambda_2) (L U)^{-1} S[j].
-// Row k of a sweep needs entry k final, which the row before wrote; the
-// sweeps therefore run row by row, each lane updating band entries t,
-// t + 64, ...; coefficient rows are requested PF rows ahead.  P64: the
-// half-bandwidth in units of 64 lanes (1 or 2).
+// Blocked substitution: a step takes RB consecutive rows of a sweep.  Lane u
+// of the wavefront (u < RB + p, in NCH chunks of 64 lanes) holds row k0 + u
+// of the forward sweep (k0 - u of the backward one); for r = 0..RB-1 the
+// final value of the step's row r is broadcast from lane r and every lane
+// subtracts its coefficient times it.  The coefficient of (u, r) is entry
+// u - r - 1 of the factor column of row r (stored by column, see
+// k2d_factor; zero outside the band), so a chunk's lanes read consecutive
+// entries.  The rows cost one LDS read and one write per step instead of per
+// row; the coefficients of the next NB steps are in flight.
+constexpr int RB = 8;  // rows per step
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ Cx<double> lane_value(Cx<double> v, int lane) {
+  return Cx<double>{lane_value(v.x, lane), lane_value(v.y, lane)};
+}
+
 template <int P64>
 __global__ __launch_bounds__(BANDT) void k2d_band(const Cx<double>* __restrict__ Lc,
                                                   const Cx<double>* __restrict__ Uc,
                                                   const Cx<double>* __restrict__ dinv,
                                                   const Cx<double>* __restrict__ il2, int npts, int p,
                                                   Cx<double>* __restrict__ S) {
+  constexpr int NCH = (RB + 64 * P64 + 63) / 64;  // lane chunks: RB + p rows
+  constexpr int NB = P64 == 1 ? 3 : 2;            // steps of coefficients in flight
   extern __shared__ Cx<double> y[];
   const int j = blockIdx.x, t = threadIdx.x;
   Cx<double>* s = S + (size_t)j * npts;
@@ -249,72 +267,99 @@ __global__ __launch_bounds__(BANDT) void k2d_band(const Cx<double>* __restrict__
   const Cx<double>* di = dinv + (size_t)j * npts;
   for (int i = t; i < npts; i += BANDT) y[i] = s[i];
   __syncthreads();
-  auto coef = [&](const Cx<double>* base, int k, int r) -> Cx<double> {
-    const int tt = t + r * BANDT;
-    return (k >= 0 && k < npts && tt < p) ? base[(size_t)k * p + tt] : czero();
+  // coefficient of lane u for the step row r whose factor column is col
+  auto coef = [&](const Cx<double>* base, int col, int u, int r) -> Cx<double> {
+    const int e = u - r - 1;
+    return (col >= 0 && col < npts && e >= 0 && e < p) ? base[(size_t)col * p + e] : czero();
   };
-  // forward: y[k+1+t] -= L[k+1+t][k] y[k]
+  // forward: unit lower L, column k holds L[k+1+e][k]
   {
-    Cx<double> cb[PF][P64];
+    Cx<double> cb[NB][RB][NCH];
 #pragma unroll
-    for (int q = 0; q < PF; ++q)
+    for (int q = 0; q < NB; ++q)
 #pragma unroll
-      for (int r = 0; r < P64; ++r) cb[q][r] = coef(L, q, r);
-    for (int k0 = 0; k0 < npts; k0 += PF) {
+      for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        const int k = k0 + q;
-        Cx<double> c[P64];
+        for (int c = 0; c < NCH; ++c) cb[q][r][c] = coef(L, q * RB + r, t + 64 * c, r);
+    for (int kb = 0; kb < npts; kb += NB * RB) {
 #pragma unroll
-        for (int r = 0; r < P64; ++r) {
-          c[r] = cb[q][r];
-          cb[q][r] = coef(L, k + PF, r);
-        }
-        if (k < npts) {
-          const Cx<double> yk = y[k];
+      for (int q = 0; q < NB; ++q) {
+        const int k0 = kb + q * RB;
+        if (k0 < npts) {
+          Cx<double> yu[NCH];
 #pragma unroll
-          for (int r = 0; r < P64; ++r) {
-            const int i = k + 1 + t + r * BANDT;
-            if (t + r * BANDT < p && i < npts) y[i] = y[i] - c[r] * yk;
+          for (int c = 0; c < NCH; ++c) {
+            const int u = t + 64 * c, i = k0 + u;
+            yu[c] = (u < RB + p && i < npts) ? y[i] : czero();
+          }
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+            if (k0 + r < npts) {
+              const Cx<double> yr = lane_value(yu[0], r);
+#pragma unroll
+              for (int c = 0; c < NCH; ++c) yu[c] = yu[c] - cb[q][r][c] * yr;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const int u = t + 64 * c, i = k0 + u;
+            if (u < RB + p && i < npts) y[i] = yu[c];
           }
         }
+        // the coefficients of the step NB ahead
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) cb[q][r][c] = coef(L, k0 + NB * RB + r, t + 64 * c, r);
         __syncthreads();
       }
     }
   }
-  // backward: y[k] *= 1/U[k][k]; y[k-1-t] -= U[k-1-t][k] y[k]
+  // backward: row k scaled by 1/U[k][k]; column k holds U[k-1-e][k]
   {
-    Cx<double> cb[PF][P64];
-    Cx<double> db[PF];
+    Cx<double> cb[NB][RB][NCH];
+    Cx<double> db[NB];  // lane r < RB: 1/U of the step's row r
 #pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      const int k = npts - 1 - q;
+    for (int q = 0; q < NB; ++q) {
+      const int k0 = npts - 1 - q * RB;
 #pragma unroll
-      for (int r = 0; r < P64; ++r) cb[q][r] = coef(U, k, r);
-      db[q] = k >= 0 ? di[k] : czero();
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) cb[q][r][c] = coef(U, k0 - r, t + 64 * c, r);
+      db[q] = (t < RB && k0 - t >= 0) ? di[k0 - t] : czero();
     }
-    for (int k0 = npts - 1; k0 >= 0; k0 -= PF) {
+    for (int kb = npts - 1; kb >= 0; kb -= NB * RB) {
 #pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        const int k = k0 - q;
-        Cx<double> c[P64];
+      for (int q = 0; q < NB; ++q) {
+        const int k0 = kb - q * RB;
+        if (k0 >= 0) {
+          Cx<double> yu[NCH];
 #pragma unroll
-        for (int r = 0; r < P64; ++r) {
-          c[r] = cb[q][r];
-          cb[q][r] = coef(U, k - PF, r);
-        }
-        const Cx<double> dk = db[q];
-        db[q] = k - PF >= 0 ? di[k - PF] : czero();
-        if (k >= 0) {
-          const Cx<double> yk = y[k] * dk;
-          __syncthreads();  // every lane has read y[k] before lane 0 rewrites it
-          if (t == 0) y[k] = yk;
+          for (int c = 0; c < NCH; ++c) {
+            const int u = t + 64 * c, i = k0 - u;
+            yu[c] = (u < RB + p && i >= 0) ? y[i] : czero();
+          }
 #pragma unroll
-          for (int r = 0; r < P64; ++r) {
-            const int i = k - 1 - t - r * BANDT;
-            if (t + r * BANDT < p && i >= 0) y[i] = y[i] - c[r] * yk;
+          for (int r = 0; r < RB; ++r) {
+            if (k0 - r >= 0) {
+              if (t == r) yu[0] = yu[0] * db[q];
+              const Cx<double> yr = lane_value(yu[0], r);
+#pragma unroll
+              for (int c = 0; c < NCH; ++c) yu[c] = yu[c] - cb[q][r][c] * yr;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const int u = t + 64 * c, i = k0 - u;
+            if (u < RB + p && i >= 0) y[i] = yu[c];
           }
         }
+        const int kn = k0 - NB * RB;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) cb[q][r][c] = coef(U, kn - r, t + 64 * c, r);
+        db[q] = (t < RB && kn - t >= 0) ? di[kn - t] : czero();
         __syncthreads();
       }
     }
