@@ -20,6 +20,8 @@
 // fence writes back and invalidates the XCD's L2).
 #include <math.h>
 
+#include <type_traits>
+
 #include "cn_internal.hpp"
 
 namespace cn {
@@ -112,7 +114,24 @@ __device__ __forceinline__ void publish(GSummary* host, const GSummary& sm, int 
 // vectors are parameters so that __restrict__ holds (y is never one of the
 // vectors read), which lets the loads of later levels be issued before the
 // store of the current one.
-template <typename TX, int MODE, int NV, int NA>
+// Neighbour z or x at a grid edge: loaded unconditionally from a valid address
+// and dropped by a select when the vector is float32 (the conversion to
+// float64 inside a lane-dependent branch made the compiler wait for every load
+// in flight before leaving the branch, at every level), and behind the branch
+// when it is float64 (no conversion; measured faster).
+template <typename TX>
+__device__ __forceinline__ double edge_load(const CN_G TX* p, size_t e, bool keep) {
+  if constexpr (std::is_same<TX, float>::value) {
+    const double v = (double)p[e];
+    return keep ? v : 0.0;
+  } else {
+    return keep ? (double)p[e] : 0.0;
+  }
+}
+
+// DW: the instance has time weights d_k (a compile-time choice, so that the
+// level loop is one basic block and later levels' loads can be issued ahead)
+template <typename TX, int MODE, int NV, int NA, bool DW>
 __device__ __forceinline__ void matvec_column(const CN_G TX* __restrict__ x,
                                               const CN_G double* __restrict__ b,
                                               CN_G double* __restrict__ y,
@@ -125,15 +144,19 @@ __device__ __forceinline__ void matvec_column(const CN_G TX* __restrict__ x,
                                               int k0, int k1, double (&acc)[NA]) {
   const double lo = plo[i], di = pdi[i], up = pup[i];
   const bool hl = i > 0, hr = i < nx - 1;
-  // x's columns i-1, i, i+1 (layout xl); b and y are row-major (pitches px, py)
+  // x's columns i-1, i, i+1 (layout xl); b and y are row-major (pitches px, py);
+  // at the grid's edges the missing neighbour's offset is 0 (a valid address,
+  // see edge_load)
   const size_t xm = hl ? xl.col(i - 1) : 0, xc = xl.col(i), xp = hr ? xl.col(i + 1) : 0;
   const size_t xrow = (size_t)xl.row;
   double pm = 0.0, pc = 0.0, pp = 0.0;  // previous level at i-1, i, i+1
-  if (k0 > 0 && x != nullptr) {
+  // MODE 2 reads z_j, never null (no branch in the level loop)
+  const bool have_x = MODE == 2 || x != nullptr;
+  if (k0 > 0 && have_x) {
     const size_t o = (size_t)(k0 - 1) * xrow;
     pc = (double)x[o + xc];
-    if (hl) pm = (double)x[o + xm];
-    if (hr) pp = (double)x[o + xp];
+    pm = edge_load(x, o + xm, hl);
+    pp = edge_load(x, o + xp, hr);
   }
   size_t vo[NV];
 #pragma unroll
@@ -143,12 +166,12 @@ __device__ __forceinline__ void matvec_column(const CN_G TX* __restrict__ x,
   for (int k = k0; k < k1; ++k) {
     double cm = 0.0, cc = 0.0, cp = 0.0;
     const size_t off = (size_t)k * px, offy = (size_t)k * py, offx = (size_t)k * xrow;
-    if (x != nullptr) {
+    if (have_x) {
       cc = (double)x[offx + xc];
-      if (hl) cm = (double)x[offx + xm];
-      if (hr) cp = (double)x[offx + xp];
+      cm = edge_load(x, offx + xm, hl);
+      cp = edge_load(x, offx + xp, hr);
     }
-    const double w = dw != nullptr ? dw[k] : 1.0;
+    const double w = DW ? dw[k] : 1.0;
     // (M x)^k = (x^k - x^{k-1}) - (w/2) A~ (x^k + x^{k-1})
     const double sm = cm + pm, s0 = cc + pc, sp = cp + pp;
     const double ax = lo * sm + di * s0 + up * sp;
@@ -213,10 +236,16 @@ __global__ __launch_bounds__(MVT) void k_matvec(const InstDesc* __restrict__ D,
   double acc[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = 0.0;
-  if (i < nx)
-    matvec_column<TX, MODE, NV, NA>(gp(x), gp(b), gp(y), gp(d.V), gp(d.pl.lo), gp(d.pl.di),
-                                    gp(d.pl.up), gp(d.dw), d.vstride, xl, px, py, nx, nv, i, k0,
-                                    k1, acc);
+  if (i < nx) {
+    if (d.dw != nullptr)
+      matvec_column<TX, MODE, NV, NA, true>(gp(x), gp(b), gp(y), gp(d.V), gp(d.pl.lo),
+                                            gp(d.pl.di), gp(d.pl.up), gp(d.dw), d.vstride, xl, px,
+                                            py, nx, nv, i, k0, k1, acc);
+    else
+      matvec_column<TX, MODE, NV, NA, false>(gp(x), gp(b), gp(y), gp(d.V), gp(d.pl.lo),
+                                             gp(d.pl.di), gp(d.pl.up), gp(d.dw), d.vstride, xl,
+                                             px, py, nx, nv, i, k0, k1, acc);
+  }
   if (MODE == 0) return;
   block_partials<NA, MVT>(acc, MODE == 1 ? 2 : nv, red, d.partials, blk, d.mv_grid);
 }
@@ -246,8 +275,11 @@ __device__ __forceinline__ void update_coeffs(const double* __restrict__ partial
     const int p = threadIdx.x;
     const double* g = st->gram + (size_t)p * NVMAX;
     double h2 = 0.0;
-    for (int q = 0; q < nv; ++q)
-      if (q != p) h2 -= g[q] * sh[q];
+    // every entry loaded (no branch around the loads), the diagonal skipped
+    for (int q = 0; q < nv; ++q) {
+      const double gq = g[q];
+      if (q != p) h2 -= gq * sh[q];
+    }
     const double h1 = sh[p], s = st->vscale[p];
     sc[p] = (h1 + h2) * s;
     if (keep) {
@@ -272,7 +304,7 @@ __device__ __forceinline__ void update_coeffs(const double* __restrict__ partial
 // after the column's first levels have been requested: the barriers wait for
 // LDS only, so those loads are in flight during the reduction instead of
 // starting after it.
-template <typename TX, int NV, typename Coeffs>
+template <typename TX, int NV, bool DW, typename Coeffs>
 __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
                                               const CN_G double* __restrict__ V,
                                               CN_G double* __restrict__ vout,
@@ -297,7 +329,7 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
   };
   double lo = 0.0, di = 0.0, up = 0.0;
   double pm = 0.0, pc = 0.0, pp = 0.0;  // z at the previous level, i-1, i, i+1
-  // z's columns i-1, i, i+1 in its (tile-blocked) layout
+  // z's columns i-1, i, i+1 in its (tile-blocked) layout (edges: edge_load)
   const size_t zm = act && hl ? zl.col(i - 1) : 0, zc = act ? zl.col(i) : 0,
                zp = act && hr ? zl.col(i + 1) : 0;
   const size_t zrow = (size_t)zl.row;
@@ -312,8 +344,8 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
     if (k0 > 0) {
       const size_t o = (size_t)(k0 - 1) * zrow;
       pc = (double)z[o + zc];
-      if (hl) pm = (double)z[o + zm];
-      if (hr) pp = (double)z[o + zp];
+      pm = edge_load(z, o + zm, hl);
+      pp = edge_load(z, o + zp, hr);
     }
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
@@ -321,11 +353,11 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
       const int k = min(k0 + u, k1 - 1);
       const size_t off = (size_t)k * ldx, oz = (size_t)k * zrow;
       fc[u] = (double)z[oz + zc];
-      fm[u] = hl ? (double)z[oz + zm] : 0.0;
-      fp[u] = hr ? (double)z[oz + zp] : 0.0;
+      fm[u] = edge_load(z, oz + zm, hl);
+      fp[u] = edge_load(z, oz + zp, hr);
 #pragma unroll
       for (int q = 0; q < NV; ++q) fv[u][q] = V[voff(q) + off + i];
-      fw[u] = dw != nullptr ? dw[k] : 1.0;
+      fw[u] = DW ? dw[k] : 1.0;
     }
   }
   const double* c = coeffs();
@@ -354,12 +386,11 @@ __device__ __forceinline__ void update_column(const CN_G TX* __restrict__ z,
   for (int k = k0 + PF; k < k1; ++k) {
     const size_t off = (size_t)k * ldx, oz = (size_t)k * zrow;
     const double cc = (double)z[oz + zc];
-    const double cm = hl ? (double)z[oz + zm] : 0.0;
-    const double cp = hr ? (double)z[oz + zp] : 0.0;
+    const double cm = edge_load(z, oz + zm, hl), cp = edge_load(z, oz + zp, hr);
     double vq[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) vq[q] = V[voff(q) + off + i];
-    const double w = dw != nullptr ? dw[k] : 1.0;
+    const double w = DW ? dw[k] : 1.0;
     level(k, cc, cm, cp, vq, w);
   }
 }
@@ -392,10 +423,18 @@ __global__ __launch_bounds__(MVT) void k_cgs_update(const InstDesc* __restrict__
     __syncthreads();
     return sc;
   };
-  update_column<TX, NV>(gp((const TX*)d.Z + (size_t)j * d.vstride), gp(d.V),
-                        gp(d.V + (size_t)(j + 1) * d.vstride), gp(d.pl.lo), gp(d.pl.di),
-                        gp(d.pl.up), gp(d.dw), d.vstride, z_layout(d), d.ldx, d.nx, nv, i,
-                        i < d.nx, k0, k1, coeffs, acc);
+  // d.dw is the same for every thread of the workgroup (the coefficient
+  // reduction's barriers are reached by all of them either way)
+  if (d.dw != nullptr)
+    update_column<TX, NV, true>(gp((const TX*)d.Z + (size_t)j * d.vstride), gp(d.V),
+                                gp(d.V + (size_t)(j + 1) * d.vstride), gp(d.pl.lo), gp(d.pl.di),
+                                gp(d.pl.up), gp(d.dw), d.vstride, z_layout(d), d.ldx, d.nx, nv,
+                                i, i < d.nx, k0, k1, coeffs, acc);
+  else
+    update_column<TX, NV, false>(gp((const TX*)d.Z + (size_t)j * d.vstride), gp(d.V),
+                                 gp(d.V + (size_t)(j + 1) * d.vstride), gp(d.pl.lo), gp(d.pl.di),
+                                 gp(d.pl.up), gp(d.dw), d.vstride, z_layout(d), d.ldx, d.nx, nv,
+                                 i, i < d.nx, k0, k1, coeffs, acc);
   block_partials<NA, MVT>(acc, nv + 1, red, d.partials2, blk, d.mv_grid);
 }
 
