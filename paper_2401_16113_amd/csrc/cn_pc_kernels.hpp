@@ -279,21 +279,24 @@ __device__ __forceinline__ void pc_inverse_tile(
     // modes 0 and N/2, held as (.x, .y)); indices are clamped to the
     // separator array (at least one entry per line) and masked where the
     // tile has no such separator
+    // Every thread loads its line and line N/2 (the same address across the
+    // workgroup) and selects: a load whose value is assembled under the
+    // lane-dependent t == 0 branch made the compiler wait there for every
+    // load in flight, the tile image included.
     const int sli = max(p - 1, 0), sri = min(p, max(NS - 1, 0));
+    const int h = N >= 2 ? N / 2 : 0;
+    const size_t hr = (size_t)h * NS;
 #pragma unroll
     for (int u = 0; u < NTK; ++u) {
       const int t = tid + u * T;
-      if (t == 0) {
-        const int h = N >= 2 ? N / 2 : 0;
-        const size_t hr = (size_t)h * NS;
-        slv[u] = Cx<R>{sep[sli].x, sep[hr + sli].x};
-        srv[u] = Cx<R>{sep[sri].x, sep[hr + sri].x};
-        tmd[u] = Cx<double>{mu[0].x, mu[h].x};
-      } else if (Cfg::TASKS % T == 0 || t < Cfg::TASKS) {
-        slv[u] = gld(sep + (size_t)t * NS + sli);
-        srv[u] = gld(sep + (size_t)t * NS + sri);
-        tmd[u] = gld(mu + t);
-      }
+      const int tt = (Cfg::TASKS % T == 0 || t < Cfg::TASKS) ? t : 0;
+      const Cx<R> la = gld(sep + (size_t)tt * NS + sli), lb = gld(sep + hr + sli);
+      const Cx<R> ra = gld(sep + (size_t)tt * NS + sri), rb = gld(sep + hr + sri);
+      const Cx<double> ma = gld(mu + tt), mb = gld(mu + h);
+      const bool real = t == 0;
+      slv[u] = real ? Cx<R>{la.x, lb.x} : la;
+      srv[u] = real ? Cx<R>{ra.x, rb.x} : ra;
+      tmd[u] = real ? Cx<double>{ma.x, mb.x} : ma;
     }
     TwStage<R, CfgF::TWN, T, CfgF::TWPT> tws;
     if constexpr (CfgF::TWL) tws.fetch(gp(tw));
