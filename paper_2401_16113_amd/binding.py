@@ -79,7 +79,8 @@ def load():
         "cn_aao_create": (ctypes.c_int, [ctypes.POINTER(CnProblem), ctypes.POINTER(vp)]),
         "cn_aao_destroy": (ctypes.c_int, [vp]),
         "cn_aao_query": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                        ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+                                        ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(i32)]),
         "cn_aao_cycle": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                         ctypes.POINTER(dbl)]),
         "cn_aao_basis": (ctypes.c_int, [vp, i32, vp]),
@@ -217,11 +218,11 @@ class Solver:
             pass
 
     def query(self):
-        b, p, t, sp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        b, p, t, sp, fs = (ctypes.c_int32() for _ in range(5))
         _check(self._lib.cn_aao_query(self._h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(t),
-                                      ctypes.byref(sp)), "cn_aao_query")
+                                      ctypes.byref(sp), ctypes.byref(fs)), "cn_aao_query")
         return {"tile_cols": b.value, "tiles": p.value, "threads": t.value,
-                "inverse_split": sp.value}
+                "inverse_split": sp.value, "forward_split": fs.value}
 
     def cycle(self, k: int):
         """The Arnoldi record of the last cycle, which ran k inner

@@ -84,13 +84,17 @@ static int tune_lookup(const TuneKey& k, const std::vector<int>& cands) {
   int found = -1;
   char line[512], ftag[128], fdev[256];
   while (fgets(line, sizeof line, f) != nullptr) {
-    int pr = -1, l2 = -1, nx = -1, B = 0, T = 0, S = 0;
-    if (sscanf(line, "%127s %255s %d %d %d %d %d %d", ftag, fdev, &pr, &l2, &nx, &B, &T, &S) != 8)
+    int pr = -1, l2 = -1, nx = -1, B = 0, T = 0, S = 0, FS = 1;
+    // (a line without the ninth field, the K1 split, means 1)
+    if (sscanf(line, "%127s %255s %d %d %d %d %d %d %d", ftag, fdev, &pr, &l2, &nx, &B, &T, &S,
+               &FS) < 8)
       continue;
     if (tag != ftag || dev != fdev || pr != k.prec || l2 != k.log2n || nx != k.nx) continue;
     for (int ci : cands) {
-      int cb = 0, ct = 0, cs = 0;
-      if (pc_candidate(k.prec, k.log2n, ci, &cb, &ct, &cs) && cb == B && ct == T && cs == S) found = ci;
+      int cb = 0, ct = 0, cs = 0, cf = 0;
+      if (pc_candidate(k.prec, k.log2n, ci, &cb, &ct, &cs, &cf) && cb == B && ct == T && cs == S &&
+          cf == FS)
+        found = ci;
     }
   }
   fclose(f);
@@ -102,16 +106,16 @@ static void tune_store(const TuneKey& k, int ci) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[k] = ci;
   const std::string path = tune_path(), dev = tune_device();
-  int B = 0, T = 0, S = 0;
-  if (path.empty() || dev.empty() || !pc_candidate(k.prec, k.log2n, ci, &B, &T, &S)) return;
+  int B = 0, T = 0, S = 0, FS = 1;
+  if (path.empty() || dev.empty() || !pc_candidate(k.prec, k.log2n, ci, &B, &T, &S, &FS)) return;
   // create the directory levels of the default location (failures only
   // mean that nothing is kept)
   for (size_t p = path.find('/', 1); p != std::string::npos; p = path.find('/', p + 1))
     (void)mkdir(path.substr(0, p).c_str(), 0755);
   FILE* f = fopen(path.c_str(), "a");
   if (f == nullptr) return;
-  fprintf(f, "%s %s %d %d %d %d %d %d\n", tune_tag().c_str(), dev.c_str(), k.prec, k.log2n, k.nx, B,
-          T, S);
+  fprintf(f, "%s %s %d %d %d %d %d %d %d\n", tune_tag().c_str(), dev.c_str(), k.prec, k.log2n, k.nx,
+          B, T, S, FS);
   fclose(f);
 }
 
@@ -454,17 +458,18 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
     if (pc_candidate(pl.prec, pl.log2n, ci, &B, &T)) cands.push_back(ci);
   }
   {
-    // CN_PC_TILE="B,T" or "B,T,S" forces a variant (S: K3 workgroups per
-    // tile, 1 if not given); CN_AUTOTUNE=0 keeps the default
+    // CN_PC_TILE="B,T", "B,T,S" or "B,T,S,F" forces a variant (S: K3
+    // workgroups per tile, F = 2: K1 by frequency parity; 1 if not given);
+    // CN_AUTOTUNE=0 keeps the default
     const char* force = getenv("CN_PC_TILE");
     const char* at = getenv("CN_AUTOTUNE");
-    int fb = 0, ft = 0, fs = 1;
-    if (force != nullptr && sscanf(force, "%d,%d,%d", &fb, &ft, &fs) >= 2) {
+    int fb = 0, ft = 0, fs = 1, ff = 1;
+    if (force != nullptr && sscanf(force, "%d,%d,%d,%d", &fb, &ft, &fs, &ff) >= 2) {
       std::vector<int> keep;
       for (int ci : cands) {
-        int B = 0, T = 0, S = 0;
-        pc_candidate(pl.prec, pl.log2n, ci, &B, &T, &S);
-        if (B == fb && T == ft && S == fs) keep.push_back(ci);
+        int B = 0, T = 0, S = 0, FS = 0;
+        pc_candidate(pl.prec, pl.log2n, ci, &B, &T, &S, &FS);
+        if (B == fb && T == ft && S == fs && FS == ff) keep.push_back(ci);
       }
       if (keep.empty()) {
         fail(CN_EINVAL, std::string("CN_PC_TILE=") + force + " is not a compiled variant");
@@ -639,12 +644,13 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
     };
     // set up the interface factors and launch context of candidate ci
     auto setup = [&](int ci, int* singular) -> hipError_t {
-      int B = 0, T = 0, S = 1;
-      pc_candidate(pl.prec, pl.log2n, ci, &B, &T, &S);
+      int B = 0, T = 0, S = 1, FS = 1;
+      pc_candidate(pl.prec, pl.log2n, ci, &B, &T, &S, &FS);
       pl.cand = ci;
       pl.B = B;
       pl.T = T;
       pl.S = S;
+      pl.FS = FS;
       pl.P = (nx + B - 1) / B;
       pl.NS = pl.P - 1;
       hipError_t e = hipMemsetAsync(err, 0, sizeof(int), h->stream);
@@ -1265,12 +1271,13 @@ cn_status cn_aao_destroy(cn_aao* h) {
 }
 
 cn_status cn_aao_query(const cn_aao* h, int32_t* tile_cols, int32_t* tiles, int32_t* threads,
-                       int32_t* inverse_split) {
+                       int32_t* inverse_split, int32_t* forward_split) {
   if (h == nullptr) return fail(CN_EINVAL, "handle is NULL");
   if (tile_cols != nullptr) *tile_cols = h->pl.B;
   if (tiles != nullptr) *tiles = h->pl.P;
   if (threads != nullptr) *threads = h->pl.T;
   if (inverse_split != nullptr) *inverse_split = h->pl.S;
+  if (forward_split != nullptr) *forward_split = h->pl.FS;
   return CN_OK;
 }
 

@@ -240,24 +240,38 @@ struct PcCfg {
 // the tile's sequences (the interface correction, which couples all B
 // columns, is formed by both), so K3 needs half the LDS per workgroup and
 // runs twice as many workgroups per CU; K1 is the same as for S = 1.
-constexpr int kNumCand = 13;
-constexpr int kCandB[kNumCand] = {0, 16, 16, 16, 8, 8, 8, 4, 4, 16, 16, 8, 8};
-constexpr int kCandT[kNumCand] = {0, 256, 512, 1024, 256, 512, 1024, 256, 512, 256, 512, 256, 512};
-constexpr int kCandS[kNumCand] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2};
+// F = 2 (float32 only): K1 transforms and solves the tile one frequency
+// parity at a time (two length-N_t/2 FFTs after one radix-2 decimation-in-
+// frequency step, the odd half held in registers meanwhile), in half the
+// LDS and at most 128 registers, so two workgroups share a CU and one's
+// loads overlap the other's transforms; the tile image is stored by parity
+// and K3 reads it so.
+constexpr int kNumCand = 15;
+constexpr int kCandB[kNumCand] = {0, 16, 16, 16, 8, 8, 8, 4, 4, 16, 16, 8, 8, 8, 8};
+constexpr int kCandT[kNumCand] = {0, 256, 512, 1024, 256, 512, 1024, 256, 512, 256, 512, 256, 512, 512, 512};
+constexpr int kCandS[kNumCand] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 1, 2};
+constexpr int kCandF[kNumCand] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2};
 
 template <typename R, int LOG2N, int CI>
 struct PcCand {
   static constexpr int B = CI == 0 ? PcDefault<R, LOG2N>::B : kCandB[CI];
   static constexpr int T = CI == 0 ? PcDefault<R, LOG2N>::T : kCandT[CI];
   static constexpr int S = kCandS[CI];
+  static constexpr int F = kCandF[CI];
   using Cfg = PcCfg<R, LOG2N, B, T>;
   using CfgF = PcCfg<R, LOG2N, B / S, T>;  // K3's part of a tile
+  using CfgH = PcCfg<R, (LOG2N > 0 ? LOG2N - 1 : 0), B, T>;  // K1's half with F = 2
+  static constexpr int HALF_LDS = CfgH::LDS_ELEMS * 2 * (int)sizeof(R) +
+                                  Split2<(1 << LOG2N)>::SIZE * 2 * (int)sizeof(R) +
+                                  3 * B * (int)sizeof(R);
   static constexpr bool dup =
       CI != 0 && S == 1 && B == PcDefault<R, LOG2N>::B && T == PcDefault<R, LOG2N>::T;
   static constexpr bool ok =
       CI == 0 || (!dup && LOG2N >= 6 && LOG2N <= 12 && Cfg::LDS_BYTES <= kLdsCap &&
                   Cfg::ELEMS >= T && (T < 1024 || B * (int)sizeof(R) <= 64) &&
-                  (S == 1 || (B >= 8 && CfgF::ELEMS >= T)));
+                  (S == 1 || (B >= 8 && CfgF::ELEMS >= T)) &&
+                  (F == 1 || (sizeof(R) == 4 && T == 512 && LOG2N >= 7 && 2 * HALF_LDS <= kLdsCap &&
+                              CfgH::ELEMS >= T && ((1 << LOG2N) / 2) % (T / B) == 0)));
 };
 
 // threadIdx.x through an empty asm: index arithmetic derived from it cannot be
@@ -371,6 +385,14 @@ struct TwTab2 {
   }
 };
 
+// Twiddle of the length-N/2 transform, w_{N/2}^m = w_N^{2m}, from the
+// two-level table of length N.
+template <typename R, int N>
+struct TwTab2Half {
+  const Cx<R>* t;
+  __device__ __forceinline__ Cx<R> operator()(int m) const { return TwTab2<R, N>{t}(2 * m); }
+};
+
 template <typename R, int LOG2N, int NSEQ, int T, bool INV, int MAXLOG, int DONE, typename TW>
 __device__ __forceinline__ void fft_run(Cx<R>* lds, const TW& tw, int tid) {
   if constexpr (DONE < LOG2N) {
@@ -378,6 +400,50 @@ __device__ __forceinline__ void fft_run(Cx<R>* lds, const TW& tw, int tid) {
     fft_pass<R, (1 << LOG2N), NSEQ, T, INV, LR, (1 << DONE)>(lds, tw, tid);
     fft_run<R, LOG2N, NSEQ, T, INV, MAXLOG, DONE + LR>(lds, tw, tid);
   }
+}
+
+// Forward transform of length NH = N/2 whose input, when `pre` is set, is
+// first multiplied elementwise by w_N^e (e = 0..NH-1): the odd-frequency
+// half of a length-N transform split by decimation in frequency.  The
+// multiplication is folded into the first pass, which reads every element
+// once; all twiddles come from the two-level table of length N in LDS.
+template <typename R, int LOG2N, int NSEQ, int T, int MAXLOG>
+__device__ __forceinline__ void fft_half(Cx<R>* lds, const Cx<R>* ltw, int tid, bool pre) {
+  constexpr int N = 1 << LOG2N, LOGH = LOG2N - 1, NH = N / 2;
+  constexpr int LR = (LOGH % MAXLOG) != 0 ? (LOGH % MAXLOG) : MAXLOG;
+  constexpr int RAD = 1 << LR;
+  constexpr int NQ = NH / RAD;
+  constexpr int NB = NSEQ * NQ;
+  constexpr int PER = (NB + T - 1) / T;
+  const TwTab2<R, N> twf{ltw};
+  Cx<R> u[PER][RAD];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * T;
+    if (NB % T == 0 || b < NB) {
+      const int s = b / NQ, i = b % NQ;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) u[q][r] = lds[lidx<NH>(s, i + r * NQ)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * T;
+    if (NB % T == 0 || b < NB) {
+      const int s = b / NQ, i = b % NQ;
+      if (pre) {
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) u[q][r] = u[q][r] * twf(i + r * NQ);
+      }
+      Dft<R, RAD, false>::run(u[q]);
+      // first pass (P = 1): output j = i RAD + r
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) lds[lidx<NH>(s, i * RAD + r)] = u[q][r];
+    }
+  }
+  __syncthreads();
+  fft_run<R, LOGH, NSEQ, T, false, MAXLOG, LR>(lds, TwTab2Half<R, N>{ltw}, tid);
 }
 
 // FFT with the twiddles from the LDS table staged as Cfg says.

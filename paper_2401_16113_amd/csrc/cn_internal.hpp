@@ -19,7 +19,8 @@ struct PcPlan {
   int prec = 0;                           // 0: float64, 1: float32
   int B = 0, P = 0, NS = 0, T = 0;        // tile cols, tiles, separators, threads
   int S = 1;                              // K3 workgroups per tile
-  int cand = 0;                           // compiled (B, T, S) variant (0 = default)
+  int FS = 1;                             // 2: K1 by frequency parity (half the LDS)
+  int cand = 0;                           // compiled (B, T, S, FS) variant (0 = default)
   double alpha = 0, dbar = 1;
   // device tables
   double *lo = nullptr, *di = nullptr, *up = nullptr;   // tau*A rows
@@ -169,7 +170,8 @@ hipError_t pc_reduced(int prec, const Launch& L, const Items& it, int chunk_clas
 hipError_t pc_inverse(int prec, int log2n, int cand, const Launch& L, const Items& it, int j,
                       void* z, int zf, int pitch, hipStream_t s);
 // (B, T) of compiled candidate `ci`; false if that candidate is not compiled
-bool pc_candidate(int prec, int log2n, int ci, int* B, int* T, int* S = nullptr);
+bool pc_candidate(int prec, int log2n, int ci, int* B, int* T, int* S = nullptr,
+                  int* FS = nullptr);
 // Krylov launchers (cn_krylov.hip)
 constexpr int KT = 512;     // threads per workgroup of the streaming Krylov kernels
 constexpr int KGRID = 512;  // most workgroups of a streaming pass (= partial sums

@@ -436,12 +436,14 @@ hipError_t pc_inverse_f64(int, int, const Launch&, const Items&, int, void*, int
                           hipStream_t);
 hipError_t pc_inverse_f32(int, int, const Launch&, const Items&, int, void*, int, int,
                           hipStream_t);
-bool pc_candidate_f64(int log2n, int ci, int* B, int* T, int* S);
-bool pc_candidate_f32(int log2n, int ci, int* B, int* T, int* S);
-bool pc_candidate(int prec, int log2n, int ci, int* B, int* T, int* S) {
-  int s = 1;
-  const bool ok = prec ? pc_candidate_f32(log2n, ci, B, T, &s) : pc_candidate_f64(log2n, ci, B, T, &s);
+bool pc_candidate_f64(int log2n, int ci, int* B, int* T, int* S, int* FS);
+bool pc_candidate_f32(int log2n, int ci, int* B, int* T, int* S, int* FS);
+bool pc_candidate(int prec, int log2n, int ci, int* B, int* T, int* S, int* FS) {
+  int s = 1, f = 1;
+  const bool ok = prec ? pc_candidate_f32(log2n, ci, B, T, &s, &f)
+                       : pc_candidate_f64(log2n, ci, B, T, &s, &f);
   if (S != nullptr) *S = s;
+  if (FS != nullptr) *FS = f;
   return ok;
 }
 

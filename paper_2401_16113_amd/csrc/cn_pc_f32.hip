@@ -11,7 +11,7 @@ namespace cn {
     return inv_cand<float, L>(cand, Lc, it, j, z, zf, pitch, s);
 #define CN_INFO_CASE_f32(L) \
   case L:                  \
-    return cand_info<float, L>(ci, B, T, S);
+    return cand_info<float, L>(ci, B, T, S, FS);
 
 CN_DEFINE_PC_PRECISION(float, f32)
 

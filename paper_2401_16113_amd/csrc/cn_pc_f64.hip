@@ -11,7 +11,7 @@ namespace cn {
     return inv_cand<double, L>(cand, Lc, it, j, z, zf, pitch, s);
 #define CN_INFO_CASE_f64(L) \
   case L:                  \
-    return cand_info<double, L>(ci, B, T, S);
+    return cand_info<double, L>(ci, B, T, S, FS);
 
 CN_DEFINE_PC_PRECISION(double, f64)
 

@@ -229,13 +229,243 @@ __global__ __launch_bounds__(TT) void k_pc_forward(const InstDesc* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// K1 by frequency parity (float32, half the LDS)
+// ---------------------------------------------------------------------------
+// One radix-2 step of a decimation in frequency: with y the weighted tile
+// sequence, a_k = y_k + y_{k+N/2} and b_k = (y_k - y_{k+N/2}) w_N^k for
+// k < N/2, the even frequencies are Y_{2m} = DFT_{N/2}(a)_m and the odd ones
+// Y_{2m+1} = DFT_{N/2}(b)_m.  A conjugate pair (j, N - j) has one parity, so
+// the workgroup transforms a in LDS, solves the step-(b) systems of the even
+// frequencies and stores them while b waits in registers, then does the same
+// for b and the odd frequencies.  The tile is read once; LDS holds half of
+// it, so two workgroups (two tiles) share a CU and one's loads overlap the
+// other's transforms.  Sequence c of tile p keeps position j of the length-N
+// layout at (p NSEQ + c) N + (j mod 2) N/2 + floor(j/2) of the tile image;
+// the interface right-hand sides are written per frequency as in K1.
+template <typename R, int LOG2N, int BB, int TT>
+__device__ __forceinline__ void pc_forward_pair(
+    int p, const CN_G double* __restrict__ v, const CN_G double* scp, const CN_G int* stop,
+    const CN_G double* __restrict__ lo, const CN_G double* __restrict__ di,
+    const CN_G double* __restrict__ up, const CN_G double* __restrict__ wfw,
+    const CN_G Cx<R>* __restrict__ tw2, const CN_G Cx<double>* __restrict__ mu,
+    const CN_G Cx<double>* __restrict__ il2, CN_G Cx<R>* __restrict__ spec,
+    CN_G Cx<R>* __restrict__ iface, int nx, int vp, int P) {
+  using Cfg = PcCfg<R, LOG2N, BB, TT>;
+  using CfgH = PcCfg<R, LOG2N - 1, BB, TT>;
+  constexpr int N = Cfg::N, NH = N / 2, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
+  constexpr int TWN = Split2<N>::SIZE;
+  static_assert(T % B == 0 && NH % (T / B) == 0, "levels k and k + N/2 must share a thread");
+  // thread tid reads column b = tid mod B at levels k = tid/B + q T/B;
+  // level k + N/2 is q + LPH, so each thread pairs its own loads.  The tile
+  // is read in RND rounds of LPR pairs (2 LPR loads in flight).
+  constexpr int LPH = NH * B / T;
+  constexpr int RND = LPH >= 16 ? 2 : 1;
+  constexpr int LPR = LPH / RND;
+  __shared__ Cx<R> lds[CfgH::LDS_ELEMS];
+  __shared__ Cx<R> ltw[TWN];
+  __shared__ R co[3 * B];
+  const int tid = threadIdx.x;
+  const int i0 = p * B;
+  const int ncols = min(B, nx - i0);
+  R* ldsr = reinterpret_cast<R*>(lds);
+  R bv[LPH];  // this thread's entries of b (column tid mod B)
+  {
+    // weights as in K1: w_q = w_0 rho^q; level k + N/2 has w_q alpha^{1/2}
+    const int stopped = stop != nullptr ? *stop : 0;
+    const double sc = scp != nullptr ? *scp : 1.0;
+    const double w0 = wfw[tid / B];
+    const double rho = wfw[T / B];
+    const double ah = wfw[NH];
+    const BufRd vb(v + i0);
+    const int b = tid % B;
+    const unsigned vo = ((unsigned)(tid / B) * (unsigned)vp + (unsigned)min(b, ncols - 1)) * 8u;
+    const unsigned step = (unsigned)(T / B) * (unsigned)vp * 8u;
+    const unsigned hstep = (unsigned)NH * (unsigned)vp * 8u;
+    TwStage<R, TWN, T, (TWN + T - 1) / T> tws;
+    double w = w0 * sc;
+    const bool live = b < ncols;
+    const int slot = b & 1, sq = b >> 1;
+#pragma unroll
+    for (int r = 0; r < RND; ++r) {
+      double xl[LPR], xh[LPR];
+#pragma unroll
+      for (int q = 0; q < LPR; ++q) {
+        const unsigned o = (unsigned)(r * LPR + q) * step;
+        xl[q] = vb.f64(vo, o);
+        xh[q] = vb.f64(vo, o + hstep);
+      }
+      if (r == 0) {
+        tws.fetch(tw2);
+        double cov = 0.0;
+        if (tid < 3 * B) {
+          const int bb = min(tid / 3, ncols - 1), c = tid % 3;
+          cov = c == 0 ? lo[i0 + bb] : (c == 1 ? di[i0 + bb] : up[i0 + bb]);
+        }
+        // a stopped cycle's loads are simply dropped
+        if (stopped) return;
+        if (tid < 3 * B) co[tid] = tid / 3 < ncols ? (R)cov : R(0);
+      }
+#pragma unroll
+      for (int q = 0; q < LPR; ++q) {
+        const int k = tid / B + (r * LPR + q) * (T / B);
+        const double yl = xl[q] * w, yh = xh[q] * (w * ah);
+        ldsr[2 * lidx<NH>(sq, k) + slot] = live ? (R)(yl + yh) : R(0);
+        R bq = live ? (R)(yl - yh) : R(0);
+        // formed here: sunk to its use after the even half, it would keep
+        // the float64 inputs live instead (twice the registers, spilled)
+        asm volatile("" : "+v"(bq));
+        bv[r * LPR + q] = bq;
+        w *= rho;
+      }
+      // the next round's loads stay behind this one's use (hoisted, they
+      // would need twice the registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    tws.store(ltw);
+  }
+  __syncthreads();
+
+  constexpr int TASKS = N / 4;  // per parity
+  constexpr int NTK = (TASKS + T - 1) / T;
+  const bool has_sep = p < P - 1;
+  const int nb = has_sep ? B - 1 : ncols;
+  const R lsep = has_sep ? co[3 * (B - 1)] : R(0);
+  const R uprev = p > 0 ? (R)up[i0 - 1] : R(0);
+  CN_G Cx<R>* ifc = iface + (size_t)p * 2;
+#pragma unroll 1
+  for (int hf = 0; hf < 2; ++hf) {
+    const bool odd = hf != 0;
+    if (odd) {
+      // b replaces a in LDS (its w_N^k factor is applied by the first pass)
+#pragma unroll
+      for (int q = 0; q < LPH; ++q) {
+        const int t = phase_tid<T>();
+        const int k = t / B + q * (T / B);
+        ldsr[2 * lidx<NH>((t % B) >> 1, k) + (t & 1)] = bv[q];
+      }
+      __syncthreads();
+    }
+    fft_half<R, LOG2N, NSEQ, T, CfgH::MAXLOG>(lds, ltw, phase_tid<T>(), odd);
+    // Task t < N/4: even half, t = 0 the real modes 0 and N/2 (positions 0
+    // and N/4), else j = 2t at positions t and N/2 - t; odd half, j = 2t + 1
+    // at positions t and N/2 - 1 - t.
+    const int tid2 = phase_tid<T>();
+    Cx<double> tmd[NTK], tsd[NTK];
+#pragma unroll
+    for (int u = 0; u < NTK; ++u) {
+      const int t = tid2 + u * T;
+      const int tt = (TASKS % T == 0 || t < TASKS) ? t : 0;
+      const int j = 2 * tt + hf;
+      const Cx<double> ma = gld(mu + j), mb = gld(mu + NH);
+      const Cx<double> sa = gld(il2 + j), sb = gld(il2 + NH);
+      const bool real = !odd && t == 0;
+      tmd[u] = real ? Cx<double>{ma.x, mb.x} : ma;
+      tsd[u] = real ? Cx<double>{sa.x, sb.x} : sa;
+    }
+#pragma unroll
+    for (int u = 0; u < NTK; ++u) {
+      const int t = tid2 + u * T;
+      if (TASKS % T != 0 && t >= TASKS) break;
+      if (!odd && t == 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int j = h == 0 ? 0 : NH, pos = h == 0 ? 0 : NH / 2;
+          const R m = (R)(h == 0 ? tmd[u].x : tmd[u].y), s2 = (R)(h == 0 ? tsd[u].x : tsd[u].y);
+          R d[B];
+#pragma unroll
+          for (int c = 0; c < NSEQ; ++c) {
+            const Cx<R> z = lds[lidx<NH>(c, pos)];
+            d[2 * c] = z.x * s2;
+            d[2 * c + 1] = z.y * s2;
+          }
+          const R sepv = d[B - 1];
+          tile_solve<R, R, B>(d, m, co, nb);
+          R ylast = d[0];
+#pragma unroll
+          for (int bb = 1; bb < B; ++bb)
+            if (bb == nb - 1) ylast = d[bb];
+#pragma unroll
+          for (int c = 0; c < NSEQ; ++c) lds[lidx<NH>(c, pos)] = Cx<R>{d[2 * c], d[2 * c + 1]};
+          CN_G Cx<R>* f = ifc + (size_t)j * P * 2;
+          gst(f, Cx<R>{has_sep ? sepv + lsep * ylast : R(0), R(0)});
+          gst(f + 1, Cx<R>{uprev * d[0], R(0)});
+        }
+      } else {
+        const int j = 2 * t + hf;
+        const int pa = t, pb = NH - hf - t;
+        const Cx<R> m{(R)tmd[u].x, (R)tmd[u].y}, s2{(R)tsd[u].x, (R)tsd[u].y};
+        Cx<R> d[B];
+#pragma unroll
+        for (int c = 0; c < NSEQ; ++c) {
+          const Cx<R> z = lds[lidx<NH>(c, pa)];
+          const Cx<R> zc = conj(lds[lidx<NH>(c, pb)]);
+          const Cx<R> sum = z + zc, dif = z - zc;
+          d[2 * c] = (R(0.5) * sum) * s2;
+          d[2 * c + 1] = Cx<R>{R(0.5) * dif.y, R(-0.5) * dif.x} * s2;
+        }
+        const Cx<R> sepv = d[B - 1];
+        tile_solve<R, Cx<R>, B>(d, m, co, nb);
+        Cx<R> ylast = d[0];
+#pragma unroll
+        for (int bb = 1; bb < B; ++bb)
+          if (bb == nb - 1) ylast = d[bb];
+#pragma unroll
+        for (int c = 0; c < NSEQ; ++c) {
+          lds[lidx<NH>(c, pa)] = d[2 * c];
+          lds[lidx<NH>(c, pb)] = d[2 * c + 1];
+        }
+        CN_G Cx<R>* f = ifc + (size_t)j * P * 2;
+        gst(f, has_sep ? sepv + lsep * ylast : Cx<R>{R(0), R(0)});
+        gst(f + 1, uprev * d[0]);
+      }
+    }
+    __syncthreads();
+    {
+      const int tid3 = phase_tid<T>();
+      CN_G Cx<R>* img = spec + (size_t)p * NSEQ * N + (size_t)hf * NH;
+      constexpr int SPT = (NSEQ * NH + T - 1) / T;
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int e = tid3 + q * T;
+        if ((NSEQ * NH) % T == 0 || e < NSEQ * NH) {
+          const int c = e / NH, m = e % NH;
+          gst(img + (size_t)c * N + m, lds[lidx<NH>(c, m)]);
+        }
+      }
+    }
+    // the odd half overwrites the LDS the stores above read
+    __syncthreads();
+  }
+}
+
+// At most 128 registers, so that two workgroups fit a CU.
+template <typename R, int LOG2N, int BB, int TT>
+__global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_pc_forward_pair(const InstDesc* __restrict__ D, const int2* __restrict__ items, int nitems,
+                       int nitems_pad, int jv, const double* __restrict__ v_ovr, int pitch) {
+  const int itx = xcd_tile(blockIdx.x, nitems_pad);
+  if (itx >= nitems) return;
+  const int2 wi = work_item(items, itx);
+  const InstDesc& d = D[wi.x];
+  const PcPlan& pl = d.pl;
+  const bool in_solve = v_ovr == nullptr;
+  const double* v = in_solve ? d.V + (size_t)jv * d.vstride : v_ovr;
+  const Cx<R>* tw2 = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw2 : (const Cx<R>*)pl.tw2_f;
+  pc_forward_pair<R, LOG2N, BB, TT>(
+      wi.y, gp(v), in_solve ? gp(d.st->vscale + jv) : nullptr,
+      in_solve ? gp(&d.st->sum.done) : nullptr, gp(pl.lo), gp(pl.di), gp(pl.up), gp(pl.wfw),
+      gp(tw2), gp((const Cx<double>*)pl.mu), gp((const Cx<double>*)pl.il2),
+      gp((Cx<R>*)pl.spec), gp((Cx<R>*)pl.iface), pl.nx, pitch > 0 ? pitch : d.ldx, pl.P);
+}
+
+// ---------------------------------------------------------------------------
 // K3
 // ---------------------------------------------------------------------------
 // Workgroup hf of the SPL that serve tile p inverts the tile's sequences
 // [hf NSEQ/SPL, (hf+1) NSEQ/SPL) (columns [hf B/SPL, (hf+1) B/SPL)); each
 // forms the interface correction of the whole tile (it couples all B
 // columns) and applies it to its own sequences.
-template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL>
+template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL, bool PIMG>
 __device__ __forceinline__ void pc_inverse_tile(
     int p, int hf, const CN_G int* stop, const CN_G Cx<R>* __restrict__ spec,
     const CN_G Cx<R>* __restrict__ sep, const CN_G double* __restrict__ lo,
@@ -310,7 +540,13 @@ __device__ __forceinline__ void pc_inverse_tile(
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int e = tid + q * T;
-      if ((NSF * N) % T == 0 || e < NSF * N) lds[lidx<N>(e / N, e % N)] = iv[q];
+      if ((NSF * N) % T == 0 || e < NSF * N) {
+        // PIMG: the image holds each sequence's even positions, then its odd
+        // ones (written by the parity-split K1)
+        const int s = e % N;
+        const int j = !PIMG ? s : (s < N / 2 ? 2 * s : 2 * (s - N / 2) + 1);
+        lds[lidx<N>(e / N, j)] = iv[q];
+      }
     }
     if constexpr (CfgF::TWL) tws.store(ltw);
   }
@@ -408,7 +644,7 @@ __device__ __forceinline__ void pc_inverse_tile(
 // for the tile-blocked layout of Z.  SPL workgroups per tile item: nitems
 // counts tiles, the grid covers SPL nitems parts (the parts of one tile are
 // consecutive, so they share an XCD).
-template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL>
+template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL, bool PIMG>
 __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ D,
                                                    const int2* __restrict__ items, int nitems,
                                                    int nitems_pad, int jv, TZ* __restrict__ z_ovr,
@@ -424,7 +660,7 @@ __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ 
   const Cx<R>* tw = CfgF::TWMODE == 3
                         ? (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw2 : (const Cx<R>*)pl.tw2_f)
                         : (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f);
-  pc_inverse_tile<R, LOG2N, BB, TT, TZ, SPL>(wi.y, hf, z_ovr == nullptr ? gp(&d.st->sum.done) : nullptr,
+  pc_inverse_tile<R, LOG2N, BB, TT, TZ, SPL, PIMG>(wi.y, hf, z_ovr == nullptr ? gp(&d.st->sum.done) : nullptr,
                                         gp((const Cx<R>*)pl.spec), gp((const Cx<R>*)pl.sep),
                                         gp(pl.lo), gp(pl.di), gp(pl.up), gp(pl.winv), tw,
                                         gp((const Cx<double>*)pl.mu), gp(z), pl.nx,
@@ -445,9 +681,15 @@ static hipError_t launch_fwd_c(const Launch& Lc, const Items& it, int j, const d
     return hipErrorInvalidValue;
   } else {
     if (it.n <= 0) return hipSuccess;
-    const int nwg = pad8(it.n);
-    hipLaunchKernelGGL((k_pc_forward<R, L, C::B, C::T>), dim3(nwg), dim3(C::T), 0, s, Lc.D, it.it,
-                       it.n, nwg, j, v, pitch);
+    if constexpr (C::F == 2) {
+      const int nwg = pad8(it.n);
+      hipLaunchKernelGGL((k_pc_forward_pair<R, L, C::B, C::T>), dim3(nwg), dim3(C::T), 0, s, Lc.D,
+                         it.it, it.n, nwg, j, v, pitch);
+    } else {
+      const int nwg = pad8(it.n);
+      hipLaunchKernelGGL((k_pc_forward<R, L, C::B, C::T>), dim3(nwg), dim3(C::T), 0, s, Lc.D,
+                         it.it, it.n, nwg, j, v, pitch);
+    }
     return hipGetLastError();
   }
 }
@@ -462,10 +704,10 @@ static hipError_t launch_inv_c(const Launch& Lc, const Items& it, int j, void* z
     if (it.n <= 0) return hipSuccess;
     const int nwg = pad8(it.n * C::S);
     if (zf)
-      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, float, C::S>), dim3(nwg), dim3(C::T), 0,
+      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, float, C::S, C::F == 2>), dim3(nwg), dim3(C::T), 0,
                          s, Lc.D, it.it, it.n, nwg, j, (float*)z, pitch);
     else
-      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, double, C::S>), dim3(nwg), dim3(C::T), 0,
+      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, double, C::S, C::F == 2>), dim3(nwg), dim3(C::T), 0,
                          s, Lc.D, it.it, it.n, nwg, j, (double*)z, pitch);
     return hipGetLastError();
   }
@@ -494,7 +736,7 @@ static hipError_t inv_cand(int ci, const Launch& Lc, const Items& it, int j, voi
 }
 
 template <typename R, int L, int CI = 0>
-static bool cand_info(int ci, int* B, int* T, int* S) {
+static bool cand_info(int ci, int* B, int* T, int* S, int* FS) {
   if constexpr (CI >= kNumCand) {
     return false;
   } else {
@@ -502,9 +744,10 @@ static bool cand_info(int ci, int* B, int* T, int* S) {
       *B = PcCand<R, L, CI>::B;
       *T = PcCand<R, L, CI>::T;
       *S = PcCand<R, L, CI>::S;
+      *FS = PcCand<R, L, CI>::F;
       return PcCand<R, L, CI>::ok;
     }
-    return cand_info<R, L, CI + 1>(ci, B, T, S);
+    return cand_info<R, L, CI + 1>(ci, B, T, S, FS);
   }
 }
 
@@ -526,7 +769,7 @@ static bool cand_info(int ci, int* B, int* T, int* S) {
     }                                                                                         \
     return hipErrorInvalidValue;                                                              \
   }                                                                                           \
-  bool pc_candidate_##SUF(int log2n, int ci, int* B, int* T, int* S) {                        \
+  bool pc_candidate_##SUF(int log2n, int ci, int* B, int* T, int* S, int* FS) {               \
     switch (log2n) {                                                                          \
       CN_LOG2N_CASES(CN_INFO_CASE_##SUF)                                                      \
     }                                                                                         \

@@ -81,7 +81,7 @@ def test_null_arguments(lib):
     assert lib.cn_pc_apply(None, None, None) == B.CN_EINVAL
     assert lib.cn_rhs(None, None, None, None) == B.CN_EINVAL
     assert lib.cn_gmres_solve(None, None, None, None, None) == B.CN_EINVAL
-    assert lib.cn_aao_query(None, None, None, None, None) == B.CN_EINVAL
+    assert lib.cn_aao_query(None, None, None, None, None, None) == B.CN_EINVAL
 
 
 def test_mlp_create_rejects_bad_sizes(lib):

@@ -339,9 +339,11 @@ def test_aliasing_rejected():
 # every compiled (tile width, workgroup size) variant of the transform kernels
 # ---------------------------------------------------------------------------
 
-# (tile columns, threads, inverse-transform workgroups per tile)
-VARIANTS = [(16, 256, 1), (16, 512, 1), (16, 1024, 1), (8, 256, 1), (8, 512, 1), (8, 1024, 1),
-            (4, 256, 1), (4, 512, 1), (16, 256, 2), (16, 512, 2), (8, 256, 2), (8, 512, 2)]
+# (tile columns, threads, inverse-transform workgroups per tile,
+#  forward transform by frequency parity: 2)
+VARIANTS = [(16, 256, 1, 1), (16, 512, 1, 1), (16, 1024, 1, 1), (8, 256, 1, 1), (8, 512, 1, 1),
+            (8, 1024, 1, 1), (4, 256, 1, 1), (4, 512, 1, 1), (16, 256, 2, 1), (16, 512, 2, 1),
+            (8, 256, 2, 1), (8, 512, 2, 1), (8, 512, 1, 2), (8, 512, 2, 2)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -355,26 +357,27 @@ def test_pc_apply_every_variant(nx, nt, prec, monkeypatch):
     ref = O.pc_apply(*oracle_args(inst), inst.alpha, v)
     u = O.sequential_cn(*oracle_args(inst), inst.u0, inst.f)
     ran = 0
-    for bcols, thr, split in VARIANTS:
-        monkeypatch.setenv("CN_PC_TILE", f"{bcols},{thr},{split}")
+    for bcols, thr, split, fsplit in VARIANTS:
+        monkeypatch.setenv("CN_PC_TILE", f"{bcols},{thr},{split},{fsplit}")
         try:
             s = solver(inst, pc_prec=prec)
         except B.CnError as e:
             assert e.status == B.CN_EINVAL and "not a compiled variant" in str(e)
             continue
-        banner(f"pc_apply variant {prec} B={bcols} T={thr} S={split} nx={nx} nt={nt}")
+        banner(f"pc_apply variant {prec} B={bcols} T={thr} S={split} F={fsplit} nx={nx} nt={nt}")
         q = s.query()
-        assert (q["tile_cols"], q["threads"], q["inverse_split"]) == (bcols, thr, split)
+        assert (q["tile_cols"], q["threads"], q["inverse_split"], q["forward_split"]) == \
+            (bcols, thr, split, fsplit)
         z = torch.empty(inst.n, dtype=torch.float64, device="cuda")
         s.pc_apply(T(v), z)
         err = rel_inf(z.cpu().numpy(), ref)
-        assert err <= pc_tol(inst.alpha, prec, nt), (bcols, thr, split, err)
+        assert err <= pc_tol(inst.alpha, prec, nt), (bcols, thr, split, fsplit, err)
         b = torch.empty(inst.n, dtype=torch.float64, device="cuda")
         s.rhs(T(inst.u0), T(inst.f.reshape(-1)), b)
         x = torch.empty_like(b)
         r = s.solve(b, x, m=20, rtol=1e-10)
         assert r.status == B.CN_OK and r.relres_true <= 1e-10
-        assert rel_inf(x.cpu().numpy(), u) <= 1e-8, (bcols, thr, split)
+        assert rel_inf(x.cpu().numpy(), u) <= 1e-8, (bcols, thr, split, fsplit)
         s.close()
         ran += 1
     assert ran >= 1
