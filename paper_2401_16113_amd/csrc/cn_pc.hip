@@ -93,8 +93,8 @@ __device__ __forceinline__ void block_affine(Cx<double>& A, Cx<double>& Bv, Cx<d
 
 template <typename R, int W, int CH>
 __device__ __forceinline__ void reduced_line_strided(
-    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const RedFwd<R>* __restrict__ rf,
-    const Cx<R>* __restrict__ rb, Cx<double>* __restrict__ rtmp, int NS, int t,
+    const CN_G Cx<R>* __restrict__ f, CN_G Cx<R>* __restrict__ sep, const CN_G RedFwd<R>* __restrict__ rf,
+    const CN_G Cx<R>* __restrict__ rb, CN_G Cx<double>* __restrict__ rtmp, int NS, int t,
     Cx<double> (*sA)[2 * W + 1], Cx<double> (*sB)[2 * W + 1]) {
   // rr of up to four blocks stays in registers; beyond, it goes through
   // the (coalesced) scratch array
@@ -106,12 +106,12 @@ __device__ __forceinline__ void reduced_line_strided(
   // operands of block q + 1 are loaded while block q is scanned
   auto fwd_ops = [&](int q, RedFwd<R>& r, Cx<double>& rho) {
     const int s = q * L + t;
-    r = s < NS ? rf[s] : RedFwd<R>{onef, zerof};
+    r = s < NS ? gld(rf + s) : RedFwd<R>{onef, zerof};
     rho = s < NS ? line_rho(f, s) : zero;
   };
   auto bwd_ops = [&](int q, Cx<R>& ap) {
     const int s = q * L + t;
-    ap = s < NS ? rb[s] : onef;
+    ap = s < NS ? gld(rb + s) : onef;
   };
   Cx<double> rh[KEEP ? CH : 1];
   RedFwd<R> rn;
@@ -131,7 +131,7 @@ __device__ __forceinline__ void reduced_line_strided(
       rh[q] = r;
     } else {
       const int s = q * L + t;
-      if (s < NS) rtmp[s] = r;
+      if (s < NS) gst(rtmp + s, r);
     }
     carry = At * carry + Bt;
   }
@@ -145,7 +145,7 @@ __device__ __forceinline__ void reduced_line_strided(
       rq = rh[q];
     } else {
       const int s = q * L + t;
-      rq = s < NS ? rtmp[s] : zero;
+      rq = s < NS ? gld(rtmp + s) : zero;
     }
     Cx<double> A = wide(apn), Bv = rq, At, Bt;
     if (q > 0) bwd_ops(q - 1, apn);
@@ -154,7 +154,7 @@ __device__ __forceinline__ void reduced_line_strided(
     const Cx<double> S = A * carry + Bv;
     carry = At * carry + Bt;
     const int s = q * L + t;
-    if (s < NS) sep[s] = Cx<R>{(R)S.x, (R)S.y};
+    if (s < NS) gst(sep + s, Cx<R>{(R)S.x, (R)S.y});
   }
 }
 
@@ -188,8 +188,8 @@ __device__ __forceinline__ void block_affine_excl(Cx<double> A, Cx<double> Bv, C
 // map applied to the previous carry.  rr stays in registers.
 template <typename R, int RD>
 __device__ __forceinline__ void reduced_line_rounds(
-    const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep, const RedFwd<R>* __restrict__ rf,
-    const Cx<R>* __restrict__ rb, int NS, int t, Cx<double> (*sA)[17], Cx<double> (*sB)[17]) {
+    const CN_G Cx<R>* __restrict__ f, CN_G Cx<R>* __restrict__ sep, const CN_G RedFwd<R>* __restrict__ rf,
+    const CN_G Cx<R>* __restrict__ rb, int NS, int t, Cx<double> (*sA)[17], Cx<double> (*sB)[17]) {
   constexpr int W = 8, L = 64 * W, CH = 8;
   const int lane = t & 63, wave = t >> 6;
   const Cx<double> one{1.0, 0.0}, zero{0.0, 0.0};
@@ -205,10 +205,14 @@ __device__ __forceinline__ void reduced_line_rounds(
     Cx<R> p1[CH], p2[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int s = s0 + c;
-      q[c] = s < NS ? rf[s] : RedFwd<R>{onef, zerof};
-      p1[c] = s < NS ? f[(size_t)2 * s] : zerof;
-      p2[c] = s < NS ? f[(size_t)2 * s + 3] : zerof;
+      // loaded from a clamped index and selected (a load under the s < NS
+      // branch made the compiler wait there for every load in flight)
+      const int s = s0 + c, sc = min(s, NS - 1);
+      const RedFwd<R> qv = gld(rf + sc);
+      const Cx<R> v1 = gld(f + (size_t)2 * sc), v2 = gld(f + (size_t)2 * sc + 3);
+      q[c] = s < NS ? qv : RedFwd<R>{onef, zerof};
+      p1[c] = s < NS ? v1 : zerof;
+      p2[c] = s < NS ? v2 : zerof;
     }
     auto rho = [&](int c) {
       return Cx<double>{(double)p1[c].x + (double)p2[c].x, (double)p1[c].y + (double)p2[c].y};
@@ -237,7 +241,10 @@ __device__ __forceinline__ void reduced_line_rounds(
     const int s0 = r * L * CH + t * CH;
     Cx<R> ap[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) ap[c] = s0 + c < NS ? rb[s0 + c] : onef;
+    for (int c = 0; c < CH; ++c) {
+      const Cx<R> v = gld(rb + min(s0 + c, NS - 1));
+      ap[c] = s0 + c < NS ? v : onef;
+    }
     Cx<double> A = one, Bv = zero;
 #pragma unroll
     for (int c = CH - 1; c >= 0; --c) {
@@ -253,7 +260,7 @@ __device__ __forceinline__ void reduced_line_rounds(
     for (int c = CH - 1; c >= 0; --c) {
       S = wide(ap[c]) * S + rh[r][c];
       const int s = s0 + c;
-      if (s < NS) sep[s] = Cx<R>{(R)S.x, (R)S.y};
+      if (s < NS) gst(sep + s, Cx<R>{(R)S.x, (R)S.y});
     }
     carry = At * carry + Bt;
   }
@@ -272,9 +279,9 @@ __global__ __launch_bounds__(512) void k_pc_reduced_rounds(const InstDesc* __res
   if (!standalone && d.st->sum.done) return;
   const int j = wi.y;
   const size_t row = (size_t)j * pl.NS;
-  reduced_line_rounds<R, RD>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 2,
-                             (Cx<R>*)pl.sep + row, (const RedFwd<R>*)pl.recf + row,
-                             (const Cx<R>*)pl.recb + row, pl.NS, threadIdx.x, sA, sB);
+  reduced_line_rounds<R, RD>(gp((const Cx<R>*)pl.iface + (size_t)j * pl.P * 2),
+                             gp((Cx<R>*)pl.sep + row), gp((const RedFwd<R>*)pl.recf + row),
+                             gp((const Cx<R>*)pl.recb + row), pl.NS, threadIdx.x, sA, sB);
 }
 
 template <typename R, int W, int CH>
@@ -289,9 +296,9 @@ __global__ __launch_bounds__(64 * W) void k_pc_reduced_strided(
   if (!standalone && d.st->sum.done) return;
   const int j = wi.y;
   const size_t row = (size_t)j * pl.NS;
-  reduced_line_strided<R, W, CH>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 2,
-                                 (Cx<R>*)pl.sep + row, (const RedFwd<R>*)pl.recf + row,
-                                 (const Cx<R>*)pl.recb + row, pl.red_tmp + row, pl.NS,
+  reduced_line_strided<R, W, CH>(gp((const Cx<R>*)pl.iface + (size_t)j * pl.P * 2),
+                                 gp((Cx<R>*)pl.sep + row), gp((const RedFwd<R>*)pl.recf + row),
+                                 gp((const Cx<R>*)pl.recb + row), gp(pl.red_tmp + row), pl.NS,
                                  threadIdx.x, sA, sB);
 }
 
@@ -309,9 +316,10 @@ __global__ __launch_bounds__(W == 1 ? K2_THREADS : 64 * W) void k_pc_reduced(
   if (!standalone && d.st->sum.done) return;
   const int j = wi.y;
   const size_t row = (size_t)j * pl.NS;
-  reduced_line<R, W, CH>((const Cx<R>*)pl.iface + (size_t)j * pl.P * 2, (Cx<R>*)pl.sep + row,
-                         (const RedFwd<R>*)pl.recf + row, (const Cx<R>*)pl.recb + row,
-                         pl.red_tmp + row, pl.NS, t, sA, sB);
+  reduced_line<R, W, CH>(gp((const Cx<R>*)pl.iface + (size_t)j * pl.P * 2),
+                         gp((Cx<R>*)pl.sep + row), gp((const RedFwd<R>*)pl.recf + row),
+                         gp((const Cx<R>*)pl.recb + row), gp(pl.red_tmp + row), pl.NS, t, sA,
+                         sB);
 }
 
 // ---------------------------------------------------------------------------

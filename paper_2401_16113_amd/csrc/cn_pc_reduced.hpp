@@ -85,19 +85,24 @@ template <typename R>
 struct RedFwd {
   Cx<R> a, inv;
 };
+template <typename R>
+__device__ __forceinline__ RedFwd<R> gld(const CN_G RedFwd<R>* p) {
+  const CN_G Cx<R>* c = (const CN_G Cx<R>*)p;
+  return RedFwd<R>{gld(c), gld(c + 1)};
+}
 
 // rho_s of one line from the partial right-hand sides f[2p], f[2p+1] of the tiles
 template <typename R>
-__device__ __forceinline__ Cx<double> line_rho(const Cx<R>* __restrict__ f, int s) {
-  const Cx<R> p1 = f[(size_t)2 * s], p2 = f[(size_t)2 * s + 3];
+__device__ __forceinline__ Cx<double> line_rho(const CN_G Cx<R>* __restrict__ f, int s) {
+  const Cx<R> p1 = gld(f + (size_t)2 * s), p2 = gld(f + (size_t)2 * s + 3);
   return Cx<double>{(double)p1.x + (double)p2.x, (double)p1.y + (double)p2.y};
 }
 
 template <typename R, int W, int CH>
-__device__ __forceinline__ void reduced_line(const Cx<R>* __restrict__ f, Cx<R>* __restrict__ sep,
-                                             const RedFwd<R>* __restrict__ rf,
-                                             const Cx<R>* __restrict__ rb,
-                                             Cx<double>* __restrict__ rtmp, int NS, int t,
+__device__ __forceinline__ void reduced_line(const CN_G Cx<R>* __restrict__ f, CN_G Cx<R>* __restrict__ sep,
+                                             const CN_G RedFwd<R>* __restrict__ rf,
+                                             const CN_G Cx<R>* __restrict__ rb,
+                                             CN_G Cx<double>* __restrict__ rtmp, int NS, int t,
                                              Cx<double>* sA, Cx<double>* sB) {
   const int lane = t & 63, wave = t >> 6;
   const int chunk = (NS + 64 * W - 1) / (64 * W);
@@ -112,13 +117,13 @@ __device__ __forceinline__ void reduced_line(const Cx<R>* __restrict__ f, Cx<R>*
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int s = s0 + q;
-      const RedFwd<R> r = s < s1 ? rf[s] : RedFwd<R>{onef, zerof};
+      const RedFwd<R> r = s < s1 ? gld(rf + s) : RedFwd<R>{onef, zerof};
       a[q] = r.a;
       iv[q] = r.inv;
       rh[q] = s < s1 ? line_rho(f, s) : zero;
     }
 #pragma unroll
-    for (int q = 0; q < CH; ++q) ap[q] = s0 + q < s1 ? rb[s0 + q] : onef;
+    for (int q = 0; q < CH; ++q) ap[q] = s0 + q < s1 ? gld(rb + s0 + q) : onef;
     Cx<double> A = one, Bv = zero;
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
@@ -145,36 +150,36 @@ __device__ __forceinline__ void reduced_line(const Cx<R>* __restrict__ f, Cx<R>*
     for (int q = CH - 1; q >= 0; --q) {
       S = wide(ap[q]) * S + rh[q];
       const int s = s0 + q;
-      if (s < s1) sep[s] = Cx<R>{(R)S.x, (R)S.y};
+      if (s < s1) gst(sep + s, Cx<R>{(R)S.x, (R)S.y});
     }
   } else {
     Cx<double> A = one, Bv = zero;
 #pragma unroll 4
     for (int s = s0; s < s1; ++s) {
-      const Cx<double> a = wide(rf[s].a);
+      const Cx<double> a = wide(gld(rf + s).a);
       Bv = a * Bv + line_rho(f, s);
       A = a * A;
     }
     Cx<double> r = line_carry<true, W>(A, Bv, lane, wave, sA, sB);
 #pragma unroll 4
     for (int s = s0; s < s1; ++s) {
-      const RedFwd<R> q = rf[s];
+      const RedFwd<R> q = gld(rf + s);
       r = wide(q.a) * r + line_rho(f, s);
-      rtmp[s] = wide(q.inv) * r;
+      gst(rtmp + s, wide(q.inv) * r);
     }
     A = one;
     Bv = zero;
 #pragma unroll 4
     for (int s = s1 - 1; s >= s0; --s) {
-      const Cx<double> ap = wide(rb[s]);
-      Bv = ap * Bv + rtmp[s];
+      const Cx<double> ap = wide(gld(rb + s));
+      Bv = ap * Bv + gld(rtmp + s);
       A = ap * A;
     }
     Cx<double> S = line_carry<false, W>(A, Bv, lane, wave, sA, sB);
 #pragma unroll 4
     for (int s = s1 - 1; s >= s0; --s) {
-      S = wide(rb[s]) * S + rtmp[s];
-      sep[s] = Cx<R>{(R)S.x, (R)S.y};
+      S = wide(gld(rb + s)) * S + gld(rtmp + s);
+      gst(sep + s, Cx<R>{(R)S.x, (R)S.y});
     }
   }
 }
