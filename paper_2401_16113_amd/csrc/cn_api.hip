@@ -172,7 +172,7 @@ struct cn_aao {
   hipStream_t stream = nullptr;
   int device = 0;
   long long n = 0, npad = 0;
-  int ldx = 0;        // internal row pitch (N_x rounded up to 16)
+  int ldx = 0;        // internal row pitch (N_x rounded up to 16, padded, see create)
   long long pgrid = 0;  // partial sums per dot (largest grid of a reducing kernel)
   long long nin = 0;  // N_t ldx
   PcPlan pl;
@@ -389,7 +389,16 @@ static cn_status create_handle(const cn_problem* p, int force_cand, cn_aao** out
   h->prec = p->pc_prec == CN_PC_FP32 ? 1 : 0;
   h->stream = (hipStream_t)p->stream;
   h->n = n;
+  // Row pitch: N_x rounded up to 16.  A pitch that is a multiple of 8 KB puts
+  // the rows of a tile at one offset modulo a large power of two, and with
+  // vectors beyond the last-level cache the transforms' 64-byte row reads
+  // then crowd a few HBM channels: such a pitch is padded by 128 bytes
+  // (65535 x 4096: K1 1002 -> 824 us, the two Krylov passes about 2 % slower,
+  // a net 2-3 % per inner iteration; 2 KB and 8 KB pads gained less, 4 KB lost;
+  // cache-resident sizes are left alone).
   h->ldx = (p->nx + 15) / 16 * 16;
+  if (h->ldx % 1024 == 0 && (long long)p->nt * h->ldx * (long long)sizeof(double) > (256LL << 20))
+    h->ldx += 16;
   h->nin = (long long)p->nt * h->ldx;
   h->npad = (h->nin + 63) / 64 * 64;
   auto bail = [&](cn_status s) {
