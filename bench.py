@@ -61,7 +61,7 @@ KERNEL_SOURCES = ["paper_2401_16113_amd/csrc/cn_device.hpp",
 # production form's float32 apply (variant 8 x 512, two inverse workgroups)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_localvol_4095x1024_fp64pc.txt")
 TRAFFIC_FILE_PROD = os.path.join(ROOT, "profiles", "traffic_localvol_65535x4096_fp32pc.txt")
-TRAFFIC_PROD_VARIANT = {"tile_cols": 8, "threads": 512, "inverse_split": 2, "forward_split": 2}
+TRAFFIC_PROD_VARIANT = {"tile_cols": 8, "threads": 512, "inverse_split": 1, "forward_split": 2}
 
 
 def kernel_source_hash():

@@ -173,9 +173,10 @@ cn_status cn_gmres_solve(cn_aao *h, const double *b, double *x,
 /* Sizes chosen at creation (for tests and tooling): tile width of the
  * partitioned step-(b) solve, number of tiles, workgroup size of the
  * transform kernels, workgroups per tile of the inverse transform (1 or 2:
- * each inverts half of the tile's columns) and the forward transform's
- * split (1, or 2: it transforms and solves the even frequencies, then the
- * odd ones, in half the LDS).  Any pointer may be NULL. */
+ * each inverts half of the tile's columns) and the transforms' split (1, or
+ * 2: the forward and the inverse transform each handle the even
+ * frequencies, then the odd ones, in half the LDS).  Any pointer may be
+ * NULL. */
 cn_status cn_aao_query(const cn_aao *h, int32_t *tile_cols, int32_t *tiles,
                        int32_t *threads, int32_t *inverse_split,
                        int32_t *forward_split);

@@ -244,13 +244,14 @@ struct PcCfg {
 // parity at a time (two length-N_t/2 FFTs after one radix-2 decimation-in-
 // frequency step, the odd half held in registers meanwhile), in half the
 // LDS and at most 128 registers, so two workgroups share a CU and one's
-// loads overlap the other's transforms; the tile image is stored by parity
-// and K3 reads it so.
-constexpr int kNumCand = 15;
-constexpr int kCandB[kNumCand] = {0, 16, 16, 16, 8, 8, 8, 4, 4, 16, 16, 8, 8, 8, 8};
-constexpr int kCandT[kNumCand] = {0, 256, 512, 1024, 256, 512, 1024, 256, 512, 256, 512, 256, 512, 512, 512};
-constexpr int kCandS[kNumCand] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 1, 2};
-constexpr int kCandF[kNumCand] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2};
+// loads overlap the other's transforms.  The tile image is stored by parity
+// and K3 runs by parity as well (S = 1: one workgroup per tile, half the
+// LDS, each interface correction formed once).
+constexpr int kNumCand = 14;
+constexpr int kCandB[kNumCand] = {0, 16, 16, 16, 8, 8, 8, 4, 4, 16, 16, 8, 8, 8};
+constexpr int kCandT[kNumCand] = {0, 256, 512, 1024, 256, 512, 1024, 256, 512, 256, 512, 256, 512, 512};
+constexpr int kCandS[kNumCand] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 1};
+constexpr int kCandF[kNumCand] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2};
 
 template <typename R, int LOG2N, int CI>
 struct PcCand {
@@ -270,7 +271,7 @@ struct PcCand {
       CI == 0 || (!dup && LOG2N >= 6 && LOG2N <= 12 && Cfg::LDS_BYTES <= kLdsCap &&
                   Cfg::ELEMS >= T && (T < 1024 || B * (int)sizeof(R) <= 64) &&
                   (S == 1 || (B >= 8 && CfgF::ELEMS >= T)) &&
-                  (F == 1 || (sizeof(R) == 4 && T == 512 && LOG2N >= 7 && 2 * HALF_LDS <= kLdsCap &&
+                  (F == 1 || (sizeof(R) == 4 && S == 1 && T == 512 && LOG2N >= 7 && 2 * HALF_LDS <= kLdsCap &&
                               CfgH::ELEMS >= T && ((1 << LOG2N) / 2) % (T / B) == 0)));
 };
 

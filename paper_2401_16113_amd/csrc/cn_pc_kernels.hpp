@@ -465,7 +465,7 @@ void k_pc_forward_pair(const InstDesc* __restrict__ D, const int2* __restrict__ 
 // [hf NSEQ/SPL, (hf+1) NSEQ/SPL) (columns [hf B/SPL, (hf+1) B/SPL)); each
 // forms the interface correction of the whole tile (it couples all B
 // columns) and applies it to its own sequences.
-template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL, bool PIMG>
+template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL>
 __device__ __forceinline__ void pc_inverse_tile(
     int p, int hf, const CN_G int* stop, const CN_G Cx<R>* __restrict__ spec,
     const CN_G Cx<R>* __restrict__ sep, const CN_G double* __restrict__ lo,
@@ -540,13 +540,7 @@ __device__ __forceinline__ void pc_inverse_tile(
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int e = tid + q * T;
-      if ((NSF * N) % T == 0 || e < NSF * N) {
-        // PIMG: the image holds each sequence's even positions, then its odd
-        // ones (written by the parity-split K1)
-        const int s = e % N;
-        const int j = !PIMG ? s : (s < N / 2 ? 2 * s : 2 * (s - N / 2) + 1);
-        lds[lidx<N>(e / N, j)] = iv[q];
-      }
+      if ((NSF * N) % T == 0 || e < NSF * N) lds[lidx<N>(e / N, e % N)] = iv[q];
     }
     if constexpr (CfgF::TWL) tws.store(ltw);
   }
@@ -644,7 +638,7 @@ __device__ __forceinline__ void pc_inverse_tile(
 // for the tile-blocked layout of Z.  SPL workgroups per tile item: nitems
 // counts tiles, the grid covers SPL nitems parts (the parts of one tile are
 // consecutive, so they share an XCD).
-template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL, bool PIMG>
+template <typename R, int LOG2N, int BB, int TT, typename TZ, int SPL>
 __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ D,
                                                    const int2* __restrict__ items, int nitems,
                                                    int nitems_pad, int jv, TZ* __restrict__ z_ovr,
@@ -660,12 +654,230 @@ __global__ __launch_bounds__(TT) void k_pc_inverse(const InstDesc* __restrict__ 
   const Cx<R>* tw = CfgF::TWMODE == 3
                         ? (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw2 : (const Cx<R>*)pl.tw2_f)
                         : (std::is_same<R, double>::value ? (const Cx<R>*)pl.tw : (const Cx<R>*)pl.tw_f);
-  pc_inverse_tile<R, LOG2N, BB, TT, TZ, SPL, PIMG>(wi.y, hf, z_ovr == nullptr ? gp(&d.st->sum.done) : nullptr,
+  pc_inverse_tile<R, LOG2N, BB, TT, TZ, SPL>(wi.y, hf, z_ovr == nullptr ? gp(&d.st->sum.done) : nullptr,
                                         gp((const Cx<R>*)pl.spec), gp((const Cx<R>*)pl.sep),
                                         gp(pl.lo), gp(pl.di), gp(pl.up), gp(pl.winv), tw,
                                         gp((const Cx<double>*)pl.mu), gp(z), pl.nx,
                                         pitch > 0 ? pitch : (z_ovr == nullptr && d.zlog < 0 ? d.ldx : 0),
                                         pl.P, pl.NS);
+}
+
+// ---------------------------------------------------------------------------
+// K3 by frequency parity (float32, half the LDS; reads the image of the
+// parity K1)
+// ---------------------------------------------------------------------------
+// With a and b the length-N/2 inverse transforms of the corrected even and
+// odd frequencies, x_k = a_k + w_N^{-k} b_k and x_{k+N/2} = a_k - w_N^{-k} b_k.
+// The odd half of the image waits in registers while the even half is
+// corrected and transformed, then a waits in registers while the odd half
+// is; the interface correction of each frequency is formed once.
+template <typename R, int LOG2N, int BB, int TT, typename TZ>
+__device__ __forceinline__ void pc_inverse_pair(
+    int p, const CN_G int* stop, const CN_G Cx<R>* __restrict__ spec,
+    const CN_G Cx<R>* __restrict__ sep, const CN_G double* __restrict__ lo,
+    const CN_G double* __restrict__ di, const CN_G double* __restrict__ up,
+    const CN_G double* __restrict__ winv, const CN_G Cx<R>* __restrict__ tw2,
+    const CN_G Cx<double>* __restrict__ mu, CN_G TZ* __restrict__ z, int nx, int zp, int P,
+    int NS) {
+  using Cfg = PcCfg<R, LOG2N, BB, TT>;
+  using CfgH = PcCfg<R, LOG2N - 1, BB, TT>;
+  constexpr int N = Cfg::N, NH = N / 2, B = Cfg::B, NSEQ = Cfg::NSEQ, T = Cfg::T;
+  constexpr int TWN = Split2<N>::SIZE;
+  constexpr int EH = NSEQ * NH;  // complex entries of one half
+  constexpr int EPT = EH / T;
+  static_assert(EH % T == 0 && T % NSEQ == 0, "a half must spread evenly over the workgroup");
+  constexpr int TASKS = N / 4;  // per parity
+  constexpr int NTK = (TASKS + T - 1) / T;
+  __shared__ Cx<R> lds[CfgH::LDS_ELEMS];
+  __shared__ Cx<R> ltw[TWN];
+  __shared__ R co[3 * B];
+  const int tid = threadIdx.x;
+  const int i0 = p * B;
+  const int ncols = min(B, nx - i0);
+  const CN_G Cx<R>* img = spec + (size_t)p * NSEQ * N;
+  const int sli = max(p - 1, 0), sri = min(p, max(NS - 1, 0));
+  const bool has_sep = p < P - 1;
+  const bool has_left = p > 0;
+  const int nb = has_sep ? B - 1 : ncols;
+  const Cx<R> zero{R(0), R(0)};
+  Cx<R> hold[EPT];  // the odd half of the image, later a
+  {
+    // element e of a half: sequence e / NH, position e mod NH (coalesced)
+    const int stopped = stop != nullptr ? *stop : 0;
+    Cx<R> ev[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * T;
+      const CN_G Cx<R>* g = img + (size_t)(e / NH) * N + e % NH;
+      ev[q] = gld(g);
+      hold[q] = gld(g + NH);
+    }
+    TwStage<R, TWN, T, (TWN + T - 1) / T> tws;
+    tws.fetch(tw2);
+    double cov = 0.0;
+    if (tid < 3 * B) {
+      const int b = min(tid / 3, ncols - 1), c = tid % 3;
+      cov = c == 0 ? lo[i0 + b] : (c == 1 ? di[i0 + b] : up[i0 + b]);
+    }
+    if (stopped) return;  // a stopped cycle's loads are simply dropped
+    if (tid < 3 * B) co[tid] = tid / 3 < ncols ? (R)cov : R(0);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * T;
+      lds[lidx<NH>(e / NH, e % NH)] = ev[q];
+    }
+    tws.store(ltw);
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int hf = 0; hf < 2; ++hf) {
+    const bool odd = hf != 0;
+    const int tid2 = phase_tid<T>();
+    // separator values and shifts of this parity's frequencies (task t:
+    // j = 2t + hf; the even task 0 takes the real modes 0 and N/2, held as
+    // (.x, .y)); every thread loads and selects, as in K3
+    Cx<R> slv[NTK], srv[NTK];
+    Cx<double> tmd[NTK];
+    const size_t hr = (size_t)NH * NS;
+#pragma unroll
+    for (int u = 0; u < NTK; ++u) {
+      const int t = tid2 + u * T;
+      const int tt = (TASKS % T == 0 || t < TASKS) ? t : 0;
+      const size_t jr = (size_t)(2 * tt + hf) * NS;
+      const Cx<R> la = gld(sep + jr + sli), lb = gld(sep + hr + sli);
+      const Cx<R> ra = gld(sep + jr + sri), rb = gld(sep + hr + sri);
+      const Cx<double> ma = gld(mu + 2 * tt + hf), mb = gld(mu + NH);
+      const bool real = !odd && t == 0;
+      slv[u] = real ? Cx<R>{la.x, lb.x} : la;
+      srv[u] = real ? Cx<R>{ra.x, rb.x} : ra;
+      tmd[u] = real ? Cx<double>{ma.x, mb.x} : ma;
+    }
+#pragma unroll
+    for (int u = 0; u < NTK; ++u) {
+      const int t = tid2 + u * T;
+      if (TASKS % T != 0 && t >= TASKS) break;
+      if (!odd && t == 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int pos = h == 0 ? 0 : NH / 2;
+          const R m = (R)(h == 0 ? tmd[u].x : tmd[u].y);
+          const R sl = has_left ? (h == 0 ? slv[u].x : slv[u].y) : R(0);
+          const R sr = has_sep ? (h == 0 ? srv[u].x : srv[u].y) : R(0);
+          R d[B];
+#pragma unroll
+          for (int b = 0; b < B; ++b) d[b] = R(0);
+          d[0] = co[0] * sl;
+#pragma unroll
+          for (int b = 0; b < B; ++b)
+            if (b == nb - 1) d[b] = d[b] + co[3 * b + 2] * sr;
+          tile_solve<R, R, B>(d, m, co, nb);
+#pragma unroll
+          for (int c = 0; c < NSEQ; ++c) {
+            const Cx<R> yv = lds[lidx<NH>(c, pos)];
+            R xa = yv.x + d[2 * c], xb = yv.y + d[2 * c + 1];
+            if (2 * c >= nb) xa = (2 * c == B - 1 && has_sep) ? sr : R(0);
+            if (2 * c + 1 >= nb) xb = (2 * c + 1 == B - 1 && has_sep) ? sr : R(0);
+            lds[lidx<NH>(c, pos)] = Cx<R>{xa, xb};
+          }
+        }
+      } else {
+        const int pa = t, pb = NH - hf - t;
+        const Cx<R> m{(R)tmd[u].x, (R)tmd[u].y};
+        const Cx<R> sl = has_left ? slv[u] : zero, sr = has_sep ? srv[u] : zero;
+        Cx<R> d[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) d[b] = zero;
+        d[0] = co[0] * sl;
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+          if (b == nb - 1) d[b] = d[b] + co[3 * b + 2] * sr;
+        tile_solve<R, Cx<R>, B>(d, m, co, nb);
+#pragma unroll
+        for (int c = 0; c < NSEQ; ++c) {
+          Cx<R> xa = lds[lidx<NH>(c, pa)] + d[2 * c];
+          Cx<R> xb = lds[lidx<NH>(c, pb)] + d[2 * c + 1];
+          if (2 * c >= nb) xa = (2 * c == B - 1 && has_sep) ? sr : zero;
+          if (2 * c + 1 >= nb) xb = (2 * c + 1 == B - 1 && has_sep) ? sr : zero;
+          lds[lidx<NH>(c, pa)] = Cx<R>{xa.x - xb.y, xa.y + xb.x};
+          lds[lidx<NH>(c, pb)] = Cx<R>{xa.x + xb.y, xb.x - xa.y};
+        }
+      }
+    }
+    __syncthreads();
+    fft_run<R, LOG2N - 1, NSEQ, T, true, CfgH::MAXLOG, 0>(lds, TwTab2Half<R, N>{ltw},
+                                                         phase_tid<T>());
+    if (!odd) {
+      // a, in the store's order (sequence fastest), to registers; then the
+      // odd half of the image into LDS
+      const int tid3 = phase_tid<T>();
+      Cx<R> av[EPT];
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = tid3 + q * T;
+        av[q] = lds[lidx<NH>(e % NSEQ, e / NSEQ)];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = tid3 + q * T;
+        lds[lidx<NH>(e / NH, e % NH)] = hold[q];
+        hold[q] = av[q];
+      }
+      __syncthreads();
+    }
+  }
+  // x_k = a_k + w^{-k} b_k, x_{k+N/2} = a_k - w^{-k} b_k, times
+  // alpha^{-k/N_t}/N_t (by recurrence over the thread's levels k = tid/NSEQ +
+  // q T/NSEQ, as in K3); columns 2c, 2c+1 of rows k and k + N/2
+  {
+    const int tid4 = phase_tid<T>();
+    double w = winv[tid4 / NSEQ];
+    const double rho = winv[T / NSEQ] * (double)N;
+    const double wh = winv[NH] * (double)N;
+    const TwTab2<R, N> twf{ltw};
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid4 + q * T;
+      const int c = e % NSEQ, k = e / NSEQ;
+      const Cx<R> bq = lds[lidx<NH>(c, k)];
+      const Cx<R> wk = conj(twf(k));
+      const Cx<R> tq = wk * bq;
+      const Cx<R> xl = hold[q] + tq, xh = hold[q] - tq;
+      const double wl = w, whi = w * wh;
+      w *= rho;
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int col = 2 * c + s2;
+        if (col < ncols) {
+          const double vl = (double)(s2 == 0 ? xl.x : xl.y) * wl;
+          const double vh = (double)(s2 == 0 ? xh.x : xh.y) * whi;
+          const size_t zl = zp > 0 ? (size_t)k * zp + i0 + col : ((size_t)p * N + k) * B + col;
+          const size_t zh = zp > 0 ? (size_t)(k + NH) * zp + i0 + col
+                                   : ((size_t)p * N + k + NH) * B + col;
+          z[zl] = (TZ)vl;
+          z[zh] = (TZ)vh;
+        }
+      }
+    }
+  }
+}
+
+template <typename R, int LOG2N, int BB, int TT, typename TZ>
+__global__ __launch_bounds__(TT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_pc_inverse_pair(const InstDesc* __restrict__ D, const int2* __restrict__ items, int nitems,
+                       int nitems_pad, int jv, TZ* __restrict__ z_ovr, int pitch) {
+  const int itx = xcd_tile(blockIdx.x, nitems_pad);
+  if (itx >= nitems) return;
+  const int2 wi = work_item(items, itx);
+  const InstDesc& d = D[wi.x];
+  const PcPlan& pl = d.pl;
+  TZ* z = z_ovr != nullptr ? z_ovr : (TZ*)d.Z + (size_t)jv * d.vstride;
+  const Cx<R>* tw2 = std::is_same<R, double>::value ? (const Cx<R>*)pl.tw2 : (const Cx<R>*)pl.tw2_f;
+  pc_inverse_pair<R, LOG2N, BB, TT, TZ>(
+      wi.y, z_ovr == nullptr ? gp(&d.st->sum.done) : nullptr, gp((const Cx<R>*)pl.spec),
+      gp((const Cx<R>*)pl.sep), gp(pl.lo), gp(pl.di), gp(pl.up), gp(pl.winv), gp(tw2),
+      gp((const Cx<double>*)pl.mu), gp(z), pl.nx,
+      pitch > 0 ? pitch : (z_ovr == nullptr && d.zlog < 0 ? d.ldx : 0), pl.P, pl.NS);
 }
 
 // ---------------------------------------------------------------------------
@@ -702,12 +914,22 @@ static hipError_t launch_inv_c(const Launch& Lc, const Items& it, int j, void* z
     return hipErrorInvalidValue;
   } else {
     if (it.n <= 0) return hipSuccess;
+    if constexpr (C::F == 2) {
+      const int nwg = pad8(it.n);
+      if (zf)
+        hipLaunchKernelGGL((k_pc_inverse_pair<R, L, C::B, C::T, float>), dim3(nwg), dim3(C::T), 0,
+                           s, Lc.D, it.it, it.n, nwg, j, (float*)z, pitch);
+      else
+        hipLaunchKernelGGL((k_pc_inverse_pair<R, L, C::B, C::T, double>), dim3(nwg), dim3(C::T),
+                           0, s, Lc.D, it.it, it.n, nwg, j, (double*)z, pitch);
+      return hipGetLastError();
+    }
     const int nwg = pad8(it.n * C::S);
     if (zf)
-      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, float, C::S, C::F == 2>), dim3(nwg), dim3(C::T), 0,
+      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, float, C::S>), dim3(nwg), dim3(C::T), 0,
                          s, Lc.D, it.it, it.n, nwg, j, (float*)z, pitch);
     else
-      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, double, C::S, C::F == 2>), dim3(nwg), dim3(C::T), 0,
+      hipLaunchKernelGGL((k_pc_inverse<R, L, C::B, C::T, double, C::S>), dim3(nwg), dim3(C::T), 0,
                          s, Lc.D, it.it, it.n, nwg, j, (double*)z, pitch);
     return hipGetLastError();
   }
