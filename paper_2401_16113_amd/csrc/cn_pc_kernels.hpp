@@ -845,17 +845,30 @@ __device__ __forceinline__ void pc_inverse_pair(
       const Cx<R> xl = hold[q] + tq, xh = hold[q] - tq;
       const double wl = w, whi = w * wh;
       w *= rho;
+      if (zp == 0 && 2 * c + 1 < ncols) {
+        // tile-blocked: columns 2c, 2c+1 are adjacent (even offset), one
+        // vector store per row
+        typedef TZ tz2 __attribute__((ext_vector_type(2)));
+        tz2 vl, vh;
+        vl.x = (TZ)((double)xl.x * wl);
+        vl.y = (TZ)((double)xl.y * wl);
+        vh.x = (TZ)((double)xh.x * whi);
+        vh.y = (TZ)((double)xh.y * whi);
+        *(CN_G tz2*)(z + ((size_t)p * N + k) * B + 2 * c) = vl;
+        *(CN_G tz2*)(z + ((size_t)p * N + k + NH) * B + 2 * c) = vh;
+      } else {
 #pragma unroll
-      for (int s2 = 0; s2 < 2; ++s2) {
-        const int col = 2 * c + s2;
-        if (col < ncols) {
-          const double vl = (double)(s2 == 0 ? xl.x : xl.y) * wl;
-          const double vh = (double)(s2 == 0 ? xh.x : xh.y) * whi;
-          const size_t zl = zp > 0 ? (size_t)k * zp + i0 + col : ((size_t)p * N + k) * B + col;
-          const size_t zh = zp > 0 ? (size_t)(k + NH) * zp + i0 + col
-                                   : ((size_t)p * N + k + NH) * B + col;
-          z[zl] = (TZ)vl;
-          z[zh] = (TZ)vh;
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int col = 2 * c + s2;
+          if (col < ncols) {
+            const double vl = (double)(s2 == 0 ? xl.x : xl.y) * wl;
+            const double vh = (double)(s2 == 0 ? xh.x : xh.y) * whi;
+            const size_t zl = zp > 0 ? (size_t)k * zp + i0 + col : ((size_t)p * N + k) * B + col;
+            const size_t zh = zp > 0 ? (size_t)(k + NH) * zp + i0 + col
+                                     : ((size_t)p * N + k + NH) * B + col;
+            z[zl] = (TZ)vl;
+            z[zh] = (TZ)vh;
+          }
         }
       }
     }
